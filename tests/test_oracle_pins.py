@@ -1,0 +1,335 @@
+"""Pins of the FP64 oracle against facts it does not compute itself:
+textbook special cases, brute force, the paper's theorems and invariants.
+
+Every test here is CPU-only.  Node-level helpers in this file re-derive the
+problem from the per-node dynamics equation (Sec. II, eq. "2d_graph_dynamics")
+with explicit loops, so that a mistake in the oracle's stacking (a transposed
+coupling block, a wrong neighbour, a missing 1/2) shows up as a mismatch.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from lqgrid_synth import make_problem, config_problem
+from oracle import stack, kkt, riccati, splitting, slab, nbjm, pcg, residual
+
+
+# ---------------------------------------------------------------- helpers
+def simulate(p, u):
+    """x_{i,j,t+1} = A x + B u + E x_{i,j-1} + F x_{i,j+1} + G x_{i-1,j}
+    + H x_{i+1,j}, zero boundary states, x_{.,.,0} = gamma.
+    u: [T][N][K][m] -> x: [T+1][N][K][n]."""
+    K, N, T, n = p.K, p.N, p.T, p.n
+    x = np.zeros((T + 1, N, K, n))
+    x[0] = p.x0
+    for t in range(T):
+        for j in range(N):
+            for i in range(K):
+                acc = p.A[j, i] @ x[t, j, i] + p.B[j, i] @ u[t, j, i]
+                if j - 1 >= 0:
+                    acc += p.A_nbr[j, i, 0] @ x[t, j - 1, i]
+                if j + 1 < N:
+                    acc += p.A_nbr[j, i, 1] @ x[t, j + 1, i]
+                if i - 1 >= 0:
+                    acc += p.A_nbr[j, i, 2] @ x[t, j, i - 1]
+                if i + 1 < K:
+                    acc += p.A_nbr[j, i, 3] @ x[t, j, i + 1]
+                x[t + 1, j, i] = acc
+    return x
+
+
+def cost(p, x, u):
+    """1/2 sum_t sum_{i,j} (x'Qx + u'Ru), terminal 1/2 x_T' Q_T x_T."""
+    J = 0.0
+    for t in range(p.T + 1):
+        for j in range(p.N):
+            for i in range(p.K):
+                Qm = p.QT[j, i] if t == p.T else p.Q[j, i]
+                J += x[t, j, i] @ Qm @ x[t, j, i]
+                if t < p.T:
+                    J += u[t, j, i] @ p.R[j, i] @ u[t, j, i]
+    return 0.5 * J
+
+
+def shapes(p, sol):
+    x = sol["x"].reshape(p.T + 1, p.N, p.K, p.n)
+    u = sol["u"].reshape(p.T, p.N, p.K, p.m)
+    return x, u
+
+
+# ---------------------------------------------------------------- pins
+@pytest.mark.parametrize("seed,n,m,T,qt", [(0, 2, 1, 12, 1.0), (1, 3, 2, 25, 1.0),
+                                           (2, 4, 2, 40, 3.0), (3, 1, 1, 7, 0.5)])
+def test_riccati_special_case(seed, n, m, T, qt):
+    """K = N = 1 must equal the textbook Riccati LQR solution."""
+    p = make_problem(1, 1, T, n, m, rho=1.1, seed=seed, qt_scale=qt)
+    R = riccati.lqr_of_problem(p)
+    sol = kkt.solve_kkt(p)
+    x, u = shapes(p, sol)
+    assert np.abs(x[:, 0, 0] - R["x"]).max() <= 1e-12 * max(1, np.abs(R["x"]).max())
+    assert np.abs(u[:, 0, 0] - R["u"]).max() <= 1e-12 * max(1, np.abs(R["u"]).max())
+    dl = sol["delta"].reshape(T + 1, n)
+    assert np.abs(dl - R["delta"]).max() <= 1e-11 * max(1, np.abs(R["delta"]).max())
+    assert abs(cost(p, x, u) - R["cost"]) <= 1e-12 * R["cost"]
+    # and the matrix-free Schur path agrees with Riccati too
+    ops = slab.SlabOperators(p)
+    d = ops.phi_solve(ops.r_delta()) if T == 0 else None
+    xs, it, _ = pcg.cg(ops.delta, ops.r_delta(), tol=1e-13, max_iter=5000)
+    assert np.abs(xs - R["delta"]).max() <= 1e-9 * max(1, np.abs(R["delta"]).max())
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_kkt_solution_is_feasible_and_optimal(seed):
+    """Brute force on the tiny configuration: the LDL' KKT solution obeys the
+    node-level dynamics, and no random feasible perturbation lowers the cost."""
+    p, _ = config_problem("tiny", seed)
+    sol = kkt.solve_kkt(p)
+    x, u = shapes(p, sol)
+    xs = simulate(p, u)
+    assert np.abs(xs - x).max() <= 1e-11 * np.abs(x).max()
+    J = cost(p, x, u)
+    rng = np.random.default_rng(100 + seed)
+    for _ in range(4):
+        du = 1e-3 * rng.standard_normal(u.shape)
+        u2 = u + du
+        J2 = cost(p, simulate(p, u2), u2)
+        assert J2 > J
+    # first-order optimality: J(u + e du) - J(u) = O(e^2)
+    du = rng.standard_normal(u.shape)
+    e = 1e-4
+    d1 = cost(p, simulate(p, u + e * du), u + e * du) - J
+    assert abs(d1) < 1e-5 * abs(J) + 1e-12
+
+
+@pytest.mark.parametrize("K,N,T,n,m", [(4, 4, 20, 2, 1), (3, 5, 6, 3, 2),
+                                       (5, 2, 4, 4, 2), (1, 6, 5, 2, 1),
+                                       (6, 1, 5, 2, 1), (2, 3, 1, 2, 2)])
+def test_schur_solve_equals_kkt_ldl(K, N, T, n, m):
+    """Dense Cholesky of Delta == Bunch-Kaufman LDL' of the KKT system."""
+    p = make_problem(K, N, T, n, m, rho=0.95, seed=K * 7 + N)
+    a = kkt.solve_kkt(p)["delta"]
+    b = kkt.solve_schur_dense(p)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("K,N,T,n,m,qt", [(4, 4, 20, 2, 1, 1.0), (3, 5, 6, 3, 2, 2.0),
+                                          (5, 3, 3, 4, 2, 1.0), (2, 7, 4, 2, 1, 0.3),
+                                          (1, 1, 3, 2, 2, 1.0)])
+def test_slab_operators_match_full_matrices(K, N, T, n, m, qt):
+    p = make_problem(K, N, T, n, m, seed=11, qt_scale=qt)
+    ops = slab.SlabOperators(p)
+    spl = splitting.splittings(p)
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal((T + 1, K * N * n))
+    for name, f in [("Delta", ops.delta), ("Psi", ops.psi), ("Xi", ops.xi),
+                    ("Omega", ops.omega), ("Phi", ops.phi)]:
+        ref = spl[name] @ d.ravel()
+        got = f(d).ravel()
+        assert np.linalg.norm(got - ref) <= 1e-13 * max(1.0, np.linalg.norm(ref)), name
+    tau = ops.phi_solve(d)
+    assert np.linalg.norm(spl["Phi"] @ tau.ravel() - d.ravel()) <= 1e-12 * np.linalg.norm(d)
+
+
+def test_delta_from_node_level_definition():
+    """Delta d equals A~(Q~^-1 A~' d) + B~(R~^-1 B~' d) evaluated with
+    node-level loops (no stacked matrices)."""
+    p = make_problem(3, 4, 5, 2, 1, seed=4)
+    rng = np.random.default_rng(0)
+    d = rng.standard_normal((p.T + 1, p.N, p.K, p.n))
+    Qi = np.linalg.inv(p.Q)
+    QTi = np.linalg.inv(p.QT)
+    Ri = np.linalg.inv(p.R)
+
+    def nbrs(i, j):   # (coupling block of node (i,j), neighbour position)
+        out = [(p.A[j, i], (i, j))]
+        if j - 1 >= 0:
+            out.append((p.A_nbr[j, i, 0], (i, j - 1)))
+        if j + 1 < p.N:
+            out.append((p.A_nbr[j, i, 1], (i, j + 1)))
+        if i - 1 >= 0:
+            out.append((p.A_nbr[j, i, 2], (i - 1, j)))
+        if i + 1 < p.K:
+            out.append((p.A_nbr[j, i, 3], (i + 1, j)))
+        return out
+
+    T = p.T
+    # a = A~' d : a_t = -d_t + A_hat' d_{t+1}
+    a = -d.copy()
+    for t in range(T):
+        for j in range(p.N):
+            for i in range(p.K):
+                for M, (ii, jj) in nbrs(i, j):
+                    a[t, jj, ii] += M.T @ d[t + 1, j, i]
+    w = np.zeros_like(a)
+    for t in range(T + 1):
+        for j in range(p.N):
+            for i in range(p.K):
+                w[t, j, i] = (QTi if t == T else Qi)[j, i] @ a[t, j, i]
+    y = -w.copy()
+    for t in range(1, T + 1):
+        for j in range(p.N):
+            for i in range(p.K):
+                for M, (ii, jj) in nbrs(i, j):
+                    y[t, j, i] += M @ w[t - 1, jj, ii]
+                Bm = p.B[j, i]
+                y[t, j, i] += Bm @ Ri[j, i] @ Bm.T @ d[t, j, i]
+    ops = slab.SlabOperators(p)
+    got = ops.delta(d.reshape(T + 1, -1)).reshape(y.shape)
+    assert np.abs(got - y).max() <= 1e-13 * np.abs(y).max()
+
+
+def test_splitting_definiteness_and_convergence():
+    """Lemma 1 / Remark 1 / the convergence conditions of Sec. IV:
+    Delta, Psi~, Phi~, Phi~+Omega~, Psi~+Xi~ are positive definite and
+    rho(Phi~^-1 Omega~) < 1, rho(Psi~^-1 Xi~) < 1."""
+    for seed in range(3):
+        p, _ = config_problem("tiny", seed)
+        spl = splitting.splittings(p)
+        d = {k: v.toarray() for k, v in spl.items()}
+        for name, M in [("Delta", d["Delta"]), ("Psi", d["Psi"]), ("Phi", d["Phi"]),
+                        ("Phi+Omega", d["Phi"] + d["Omega"]),
+                        ("Psi+Xi", d["Psi"] + d["Xi"])]:
+            assert np.abs(M - M.T).max() <= 1e-12 * np.abs(M).max(), name
+            assert np.linalg.eigvalsh(M).min() > 0, name
+        r1 = np.abs(np.linalg.eigvals(np.linalg.solve(d["Phi"], d["Omega"]))).max()
+        r2 = np.abs(np.linalg.eigvals(np.linalg.solve(d["Psi"], d["Xi"]))).max()
+        assert r1 < 1 and r2 < 1
+
+
+def test_13_point_pattern_and_band():
+    """Psi_hat_t couples nodes at Manhattan distance <= 2 only; in the
+    interleaved order Phi_bar_{v,t} is banded with half-bandwidth 3*w*n-1."""
+    p = make_problem(6, 5, 3, 2, 1, seed=2)
+    ops = slab.SlabOperators(p)
+    C = ops.psi_hat(1).tocoo()
+    n, K = p.n, p.K
+    ni, nj = (C.row // n) % K, (C.row // n) // K
+    mi, mj = (C.col // n) % K, (C.col // n) // K
+    dist = np.abs(ni - mi) + np.abs(nj - mj)
+    assert dist.max() == 2
+    pairs = set(zip((ni - mi)[np.abs(C.data) > 0], (nj - mj)[np.abs(C.data) > 0]))
+    assert len(pairs) == 13
+    Phi = ops.phi_hat(1).tocsr()
+    for v in range(ops.V):
+        perm, w = ops._perm(v)
+        M = Phi[perm][:, perm].toarray()
+        r, c = np.nonzero(M)
+        assert np.abs(r - c).max() <= 3 * w * n - 1
+
+
+def test_theorem2_closed_form_and_spd():
+    """Theorem 2: S outer x L inner sweeps from zero apply P_S^-1 =
+    sum_s (Upsilon_L Xi)^s Upsilon_L, which is symmetric positive definite for
+    even L."""
+    for seed, (S, L) in [(0, (2, 2)), (1, (3, 2)), (2, (1, 4)), (3, (2, 6))]:
+        p, _ = config_problem("tiny", seed)
+        spl = splitting.splittings(p)
+        Pinv = splitting.preconditioner_inverse(spl, S, L)
+        apply = nbjm.sparse_preconditioner(spl, S, L)
+        rng = np.random.default_rng(seed)
+        for _ in range(3):
+            r = rng.standard_normal(Pinv.shape[0])
+            a, b = Pinv @ r, apply(r)
+            assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(a)
+        assert np.abs(Pinv - Pinv.T).max() <= 1e-13 * np.abs(Pinv).max()
+        assert np.linalg.eigvalsh(0.5 * (Pinv + Pinv.T)).min() > 0
+
+
+def test_preconditioner_special_cases():
+    # S = L = 1: block Jacobi with Phi~.
+    p = make_problem(3, 4, 5, 2, 1, seed=9)
+    spl = splitting.splittings(p)
+    Phi = spl["Phi"].toarray()
+    assert np.allclose(splitting.preconditioner_inverse(spl, 1, 1),
+                       np.linalg.inv(Phi), rtol=1e-12, atol=1e-14)
+    # S = 1: P^-1 = Upsilon_L.
+    assert np.allclose(splitting.preconditioner_inverse(spl, 1, 2),
+                       splitting.upsilon(spl["Phi"], spl["Omega"], 2),
+                       rtol=1e-12, atol=1e-14)
+    # One super-column (N <= 2): Omega~ = 0, Phi~ = Psi~, Upsilon_L = Psi~^-1.
+    p2 = make_problem(4, 2, 5, 2, 1, seed=3)
+    s2 = splitting.splittings(p2)
+    assert s2["Omega"].count_nonzero() == 0
+    U = splitting.upsilon(s2["Phi"], s2["Omega"], 4)
+    assert np.allclose(U, np.linalg.inv(s2["Psi"].toarray()), rtol=1e-12, atol=1e-14)
+    # Many sweeps: the nested iteration converges to Delta^-1 (the splittings
+    # are convergent), so P^-1 -> Delta^-1.  A sign error in Xi~ or Omega~
+    # converges elsewhere and fails here.
+    # (instance with rho(Psi~^-1 Xi~) ~ 0.92 so 600 sweeps reach ~1e-20)
+    p3 = make_problem(3, 4, 3, 2, 1, rho=0.5, seed=9)
+    s3 = splitting.splittings(p3)
+    Dinv = np.linalg.inv(s3["Delta"].toarray())
+    far = splitting.preconditioner_inverse(s3, 600, 30)
+    assert np.abs(far - Dinv).max() <= 1e-9 * np.abs(Dinv).max()
+
+
+def test_pcg_matches_dense_and_energy_norm_monotone():
+    """PCG converges to the dense solution; the Delta-norm of the error
+    decreases monotonically (the CG error bound of Sec. III); with P = Delta
+    (exact preconditioner) one step suffices; P = I is textbook CG."""
+    p, tol = config_problem("tiny", 0)
+    ops = slab.SlabOperators(p)
+    spl = splitting.splittings(p)
+    rd = ops.r_delta()
+    ds = kkt.solve_schur_dense(p).reshape(rd.shape)
+    pre = nbjm.slab_preconditioner(ops, 2, 2)
+    x, it, h = pcg.pcg(ops.delta, pre, rd, tol=tol, keep_iterates=True)
+    assert np.linalg.norm(x - ds) <= 1e-8 * np.linalg.norm(ds)
+    D = spl["Delta"]
+    en = [float(np.sqrt((xi - ds).ravel() @ (D @ (xi - ds).ravel())))
+          for xi in h["iterates"]]
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(en, en[1:]))
+    # CG error bound with kappa(Delta) (applied with P = I)
+    xc, itc, hc = pcg.cg(ops.delta, rd, tol=tol, keep_iterates=True)
+    ev = np.linalg.eigvalsh(D.toarray())
+    kap = ev[-1] / ev[0]
+    q = (np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)
+    enc = [float(np.sqrt((xi - ds).ravel() @ (D @ (xi - ds).ravel())))
+           for xi in hc["iterates"]]
+    for k, e in enumerate(enc):
+        assert e <= 2 * q ** k * enc[0] * (1 + 1e-9) + 1e-12
+    # exact preconditioner
+    Dd = D.toarray()
+    c = sla.cho_factor(Dd)
+    xe, ite, _ = pcg.pcg(ops.delta, lambda r: sla.cho_solve(c, r.ravel()).reshape(r.shape),
+                         rd, tol=1e-12)
+    assert ite == 1
+    # PCG beats CG in iterations with the NBJM preconditioner
+    assert it < itc
+
+
+def test_kkt_residual_gate():
+    p, tol = config_problem("tiny", 1)
+    ops = slab.SlabOperators(p)
+    ds = kkt.solve_schur_dense(p).reshape(p.T + 1, -1)
+    g = residual.kkt_residual(ops, ds)
+    assert g["rel2"] < 1e-13
+    bad = ds.copy()
+    bad[3, 5] += 1e-3
+    assert residual.kkt_residual(ops, bad)["rel2"] > 1e-6
+    # the primal pair recovered from delta equals the KKT LDL' primal pair
+    sol = kkt.solve_kkt(p)
+    x, u = residual.recover(ops, ds)
+    assert np.abs(x.ravel() - sol["x"]).max() <= 1e-11 * np.abs(sol["x"]).max()
+    assert np.abs(u.ravel() - sol["u"]).max() <= 1e-11 * np.abs(sol["u"]).max()
+
+
+def test_per_iteration_cost_is_linear():
+    """Table I: every operator in a PCG step has O(1) nonzeros per unknown, so
+    a step costs O(KNT).  Per row: Delta <= (13 + 5 + 5) n (13-point Psi_hat
+    plus two 5-point Xi_hat blocks), Xi~ <= 10 n, Phi~ and Omega~ <= 13 n;
+    interior rows reach these bounds, so the count saturates, not grows."""
+    n = 2
+    per = []
+    for K, N, T in [(3, 3, 4), (6, 6, 8), (10, 12, 16), (14, 14, 6)]:
+        p = make_problem(K, N, T, n, 1, seed=0)
+        spl = splitting.splittings(p)
+        rows = {k: np.diff(spl[k].tocsr().indptr) for k in spl}
+        nz = {k: np.array([np.count_nonzero(r) for r in
+                           np.split(spl[k].tocsr().data, spl[k].tocsr().indptr[1:-1])])
+              for k in ("Delta", "Xi", "Phi", "Omega")}
+        assert nz["Delta"].max() <= 23 * n
+        assert nz["Xi"].max() <= 10 * n
+        assert nz["Phi"].max() <= 13 * n and nz["Omega"].max() <= 13 * n
+        per.append(spl["Delta"].count_nonzero() / p.unknowns)
+    assert per[-1] <= 23 * n and per[-1] > 0.5 * 23 * n
