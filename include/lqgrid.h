@@ -1,0 +1,195 @@
+/*
+ * lqgrid -- MI355X (gfx950) solver for finite-horizon LQ optimal control over
+ * a K x N grid of coupled sub-systems, by the preconditioned conjugate
+ * gradient method of Zafar & Manchester, "Structured linear quadratic control
+ * computations over 2D grids" (arXiv 2304.04980).
+ *
+ * The library solves the Schur-complement system  Delta delta~ = r_delta
+ * (Sec. II-B, eq. "block_tridiagonal_system") with Algorithm 1 (PCGM,
+ * Sec. III), preconditioned by a fixed number of sweeps of Algorithm 2
+ * (nested block Jacobi, Sec. IV, Theorem 2), and recovers
+ * x~ = Q~^-1 A~' delta~, u~ = R~^-1 B~' delta~.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every pointer argument named as an array is DEVICE memory owned
+ *           by the caller.  The library never allocates device memory: all
+ *           scratch lives in the caller's workspace (size from
+ *           lqgrid_workspace_bytes).  It allocates only the small host-side
+ *           context, freed by lqgrid_destroy.
+ * Streams.  All device work is enqueued on the caller's HIP stream
+ *           (hipStream_t passed as void*; NULL = the null stream).
+ * Layout.   Row-major C arrays, node (i, j) with i = 0..K-1 the vertical and
+ *           j = 0..N-1 the horizontal grid index, column j outermost exactly as
+ *           in the paper's stacking x_hat_t = col_j col_i x_{i,j,t}
+ *           (Sec. II-A).  Vectors over the horizon are [T+1][N][K][n]
+ *           (t outermost), i.e. the order of delta~ = col(delta_hat_0, ...,
+ *           delta_hat_T).
+ * Sign.     delta~ follows the Schur-complement convention of Sec. II-B:
+ *           Q~ x~ = A~' delta~, R~ u~ = B~' delta~, Delta delta~ = r_delta.
+ * Data.     Time-invariant A, B, Q, R (the paper allows time variation; this
+ *           library does not yet).  Zero spatial boundary states.
+ * Errors.   Every call returns an lqgrid_status; none aborts.
+ * Threads.  A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef LQGRID_H
+#define LQGRID_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LQGRID_ABI_VERSION 1
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LQGRID_API __attribute__((visibility("default")))
+#else
+#define LQGRID_API
+#endif
+
+typedef struct lqgrid_ctx lqgrid_ctx; /* opaque, host side */
+
+typedef enum {
+  LQGRID_OK = 0,
+  LQGRID_EINVAL = 1,      /* bad dimension, option, or null required pointer */
+  LQGRID_ENOTSPD = 2,     /* a Phi_bar block Cholesky pivot was <= 0 or not finite */
+  LQGRID_EBREAKDOWN = 3,  /* PCG breakdown: d'Delta d <= 0, mu <= 0, or non-finite */
+  LQGRID_ENOCONV = 4,     /* max_iter reached; outputs and info are still written */
+  LQGRID_EWORKSPACE = 5,  /* workspace null, misaligned (256 B) or too small */
+  LQGRID_EHIP = 6,        /* a HIP runtime call failed */
+  LQGRID_EUNSUPPORTED = 7 /* a size outside the compiled range (n > 4, m > 8) */
+} lqgrid_status;
+
+typedef enum {
+  LQGRID_FP64 = 0,        /* every vector and sweep in FP64 */
+  LQGRID_FP32_REFINE = 1  /* FP32 operator/sweeps inside FP64 iterative refinement */
+} lqgrid_precision;
+
+/* One problem (Sec. II, eq. "2d_graph_dynamics" and the LQ problem):
+ *   x_{i,j,t+1} = A x_{i,j,t} + B u_{i,j,t} + E x_{i,j-1,t} + F x_{i,j+1,t}
+ *                 + G x_{i-1,j,t} + H x_{i+1,j,t}
+ * cost 1/2 sum (x'Qx + u'Ru) over t < T plus 1/2 x_T' QT x_T. */
+typedef struct {
+  int K, N, T, n, m;       /* grid rows, grid columns, horizon, state, input dims */
+  const double *A;         /* [N][K][n][n]    A_{i,j}                             */
+  const double *A_nbr;     /* [N][K][4][n][n] neighbour blocks of node (i,j):
+                              0: E (couples x_{i,j-1}), 1: F (x_{i,j+1}),
+                              2: G (x_{i-1,j}),         3: H (x_{i+1,j});
+                              slots that point outside the grid are ignored     */
+  const double *B;         /* [N][K][n][m]                                        */
+  const double *Q;         /* [N][K][n][n] SPD stage weight, t = 0..T-1          */
+  const double *R;         /* [N][K][m][m] SPD input weight                       */
+  const double *QT;        /* [N][K][n][n] SPD terminal weight; NULL means QT = Q */
+} lqgrid_problem_desc;
+
+typedef struct {
+  int outer_S;        /* S >= 1: outer block-Jacobi sweeps (Alg. 2); paper: 2   */
+  int inner_L;        /* L >= 2 and even (Theorem 2 needs even L); paper: 2     */
+  double tol;         /* stop when ||r||_2 <= tol * ||r_delta||_2, confirmed on
+                         the true FP64 residual r_delta - Delta delta~          */
+  int max_iter;       /* PCG iteration cap (<= 0: 10000)                         */
+  int precision;      /* lqgrid_precision                                        */
+  double inner_tol;   /* FP32_REFINE: relative tolerance of each inner solve
+                         (<= 0: 1e-5)                                            */
+  int check_every;    /* iterations between host convergence reads (<= 0: 8)    */
+} lqgrid_solve_opts;
+
+typedef struct {
+  int status;              /* lqgrid_status of the solve                        */
+  int iterations;          /* PCG iterations (all refinement passes summed)     */
+  int refinements;         /* outer FP64 refinement passes (FP32_REFINE)        */
+  int restarts;            /* restarts after a failed true-residual check       */
+  double rel_kkt_residual; /* ||r_delta - Delta delta~||_2 / ||r_delta||_2 (FP64) */
+  double rel_res_inf;      /* ||r_delta - Delta delta~||_inf / ||r_delta||_inf    */
+  double seconds;          /* device time of the solve (HIP events)             */
+} lqgrid_info;
+
+/* Fills opts with the paper's settings: S = L = 2, tol 1e-10, FP64. */
+LQGRID_API void lqgrid_default_opts(lqgrid_solve_opts *opts);
+
+/* Bytes of device workspace that lqgrid_setup needs for this problem and
+ * precision (0 if the description is invalid).  Workspace must be 256-byte
+ * aligned.  opts may be NULL (FP64). */
+LQGRID_API size_t lqgrid_workspace_bytes(const lqgrid_problem_desc *desc,
+                              const lqgrid_solve_opts *opts);
+
+/* Ingest and Schur-block assembly (Sec. II-B eq. "structure_of_Delta";
+ * Sec. II-B eq. "constructing_Phi_Omega_matrices").  Reads the problem
+ * arrays once (they may be freed after the call's work completes on the
+ * stream), writes the time-invariant operator blocks into the workspace and
+ * returns a context.  Enqueue only; no synchronisation.
+ * Errors: EINVAL (dims < 1, null A/A_nbr/B/Q/R), EUNSUPPORTED, EWORKSPACE. */
+LQGRID_API int lqgrid_setup(const lqgrid_problem_desc *desc, void *workspace,
+                 size_t workspace_bytes, void *hip_stream, lqgrid_ctx **out);
+
+/* Banded block Cholesky factorisation of every distinct Phi_bar_{v,t}
+ * (Sec. IV-B: factored once, before the PCG loop).  Synchronises
+ * the stream to read the pivot check.  Errors: ENOTSPD, EHIP. */
+LQGRID_API int lqgrid_factor(lqgrid_ctx *ctx);
+
+/* Algorithm 1 with the Algorithm 2 preconditioner (S outer x L inner sweeps).
+ *   x0         [N][K][n]       initial state gamma (DEVICE)
+ *   delta_init [T+1][N][K][n]  optional warm start (NULL: zero start); any
+ *                              value is allowed -- it only sets delta^(0)
+ *   delta      [T+1][N][K][n]  output multipliers delta~
+ *   x          [T+1][N][K][n]  optional primal state trajectory (NULL: skip)
+ *   u          [T][N][K][m]    optional inputs (NULL: skip)
+ *   info       host struct, always written when non-NULL
+ * Synchronises the stream before returning.  Errors: EINVAL (bad opts or
+ * factor not run), EBREAKDOWN, ENOCONV, EHIP. */
+LQGRID_API int lqgrid_pcg_solve(lqgrid_ctx *ctx, const double *x0,
+                     const lqgrid_solve_opts *opts, const double *delta_init,
+                     double *delta, double *x, double *u, lqgrid_info *info);
+
+/* Several independent problems solved together.  descs[p], x0s[p], deltas[p]
+ * describe problem p (device pointers, layouts as above); all share n, m and
+ * opts.  workspace sized by lqgrid_batch_workspace_bytes.  infos[p] receives
+ * problem p's result.  Synchronises the stream before returning.
+ * Returns LQGRID_OK only if every problem converged. */
+LQGRID_API size_t lqgrid_batch_workspace_bytes(int P, const lqgrid_problem_desc *descs,
+                                    const lqgrid_solve_opts *opts);
+LQGRID_API int lqgrid_batch_solve(int P, const lqgrid_problem_desc *descs,
+                       const double *const *x0s, const lqgrid_solve_opts *opts,
+                       double *const *deltas, void *workspace,
+                       size_t workspace_bytes, void *hip_stream,
+                       lqgrid_info *infos);
+
+/* Single operator applications on vectors in the [T+1][N][K][n] layout, for
+ * parity testing of each step of the path against a reference:
+ *   LQGRID_OP_DELTA     out = Delta in                       (Sec. II-B)
+ *   LQGRID_OP_XI        out = Xi~ in,  Xi~ = Psi~ - Delta    (eq. "splitting_Delta")
+ *   LQGRID_OP_OMEGA     out = Omega~ in, Omega~ = Phi~ - Psi~ (eq. "splitting_Psi")
+ *   LQGRID_OP_PHI_SOLVE out = Phi~^-1 in                     (eq. "decomposed_problem")
+ *   LQGRID_OP_PRECOND   out = P_S^-1 in  (Alg. 2, S x L sweeps; Theorem 2)
+ * Requires lqgrid_factor for PHI_SOLVE / PRECOND.  Enqueue only. */
+typedef enum {
+  LQGRID_OP_DELTA = 0,
+  LQGRID_OP_XI = 1,
+  LQGRID_OP_OMEGA = 2,
+  LQGRID_OP_PHI_SOLVE = 3,
+  LQGRID_OP_PRECOND = 4
+} lqgrid_op;
+LQGRID_API int lqgrid_apply_operator(lqgrid_ctx *ctx, int op, int outer_S, int inner_L,
+                          const double *in, double *out);
+
+/* Per-kernel device timing over the calls that follow (HIP events on the
+ * context's stream around every launch of the hot kernels).  enable = 0
+ * stops recording.  Used by the benchmark to time the dominant kernel. */
+LQGRID_API int lqgrid_profile_enable(lqgrid_ctx *ctx, int enable);
+/* kernel: 0 = Delta apply, 1 = Phi solve, 2 = Omega/Xi right-hand side,
+ * 3 = vector update.  Returns launches and summed milliseconds since enable. */
+LQGRID_API int lqgrid_profile_read(lqgrid_ctx *ctx, int kernel, long long *launches,
+                        double *total_ms);
+
+LQGRID_API void lqgrid_destroy(lqgrid_ctx *ctx);
+LQGRID_API const char *lqgrid_status_string(int status);
+LQGRID_API int lqgrid_abi_version(void);
+/* Text of the last HIP runtime failure seen by this thread (for EHIP). */
+LQGRID_API const char *lqgrid_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQGRID_H */

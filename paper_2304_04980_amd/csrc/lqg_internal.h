@@ -1,0 +1,132 @@
+// Internal definitions shared by the lqgrid HIP kernels and the host driver.
+//
+// Device layout (all FP64 unless noted):
+//   node id      p = j*K + i over an even number of columns Npad = 2V
+//                (V = ceil(N/2) super-columns of the paper, Sec. II-B); when N
+//                is odd the extra column j = N holds zero "dummy" nodes so that
+//                every super-column is a pair.
+//   vectors      v[((p*n + c)*ldt) + t]: time fastest, ldt = T+1 rounded up
+//                to 16 (128-byte rows).  A wavefront's 64 lanes cover 64
+//                consecutive t of one (node, component): every vector access
+//                is a contiguous 512-byte load/store.  Entries with t > T and
+//                dummy nodes are kept at zero.
+//   coefficients time invariant, per node, n x n row-major blocks:
+//     G13[p][k]  13-point blocks of G = A_hat Q^-1 A_hat' + B R^-1 B'
+//                (Psi_hat_t = Q_t^-1 + G for t >= 1, eq. "structure_of_Delta")
+//     Cdn[p][k]  A_hat[p,q] Q_q^-1  (q = p + off5[k]); Delta_{t,t-1} = -Cdn
+//     Cup[p][k]  Q_p^-1 A_hat[q,p]'; Delta_{t,t+1} = -Cup
+//     AT5[p][k]  A_hat[q,p]' (recovery x = Q^-1 A~' delta)
+//     Qi, QTi, QTd (= QT^-1 - Q^-1), Qm (= Q, the t = 0 block solve), RiBT
+//   factors      Lf[cls][v][i][3][(2n)^2]: banded block Cholesky of
+//                Phi_bar_{v,t} in (i, column-in-pair, component) order:
+//                slot 0 = inv(L_ii) (lower triangular), 1 = L_{i,i-1},
+//                2 = L_{i,i-2}.  cls 0: 1 <= t <= T-1 (and t = T when QT = Q),
+//                cls 1: t = T.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lqg {
+
+constexpr int kWave = 64;
+constexpr int kMaxN = 4;   // compiled state sizes: 1..kMaxN
+constexpr int kMaxM = 8;
+
+// (di, dj) offsets of the 13-point stencil (Manhattan distance <= 2).
+constexpr int kOff13[13][2] = {{0, 0},  {-1, 0}, {1, 0},  {0, -1}, {0, 1},
+                               {-2, 0}, {2, 0},  {0, -2}, {0, 2},  {-1, -1},
+                               {-1, 1}, {1, -1}, {1, 1}};
+// (di, dj) offsets of the 5-point stencil: self, north (i-1), south (i+1),
+// west (j-1), east (j+1).
+constexpr int kOff5[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+
+__host__ __device__ constexpr int off13_index(int di, int dj) {
+  for (int k = 0; k < 13; ++k)
+    if (kOff13[k][0] == di && kOff13[k][1] == dj) return k;
+  return -1;
+}
+
+struct Dims {
+  int K, N, T, n, m;
+  int Npad, V, Tt, ldt;
+  int nodes;       // Npad*K (including dummy column)
+  int real_nodes;  // N*K
+  long long vlen;  // nodes*n*ldt
+};
+
+struct Coef {
+  double *G13, *Cdn, *Cup, *AT5;
+  double *Qi, *QTi, *QTd, *Qm, *RiBT;
+  double *Lf;      // factors
+};
+
+// Device-resident PCG scalars.
+struct Scalars {
+  double rd2;      // ||r_delta||^2
+  double mu;       // q'r of the current direction
+  double yd;       // d' Delta d
+  double theta;    // step length
+  double beta;     // direction coefficient
+  double rr;       // ||r||^2 after the last update
+  double tol2;     // tol^2 * rd2
+  double rinf;     // ||r||_inf of the last true residual
+  double rdinf;    // ||r_delta||_inf
+  int done;        // 0 running, 1 converged (recurrence), 2 breakdown, 3 max_iter
+  int iter;
+  int max_iter;
+  int flag_notspd; // factor pivot failure
+  int qt_differs;  // QT != Q somewhere
+  int pad[3];
+};
+
+enum Done { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIter = 3 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over a block of BS threads (BS multiple of 64); result valid in thread 0.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[BS / kWave];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < BS / kWave; ++k) s += red[k];
+  }
+  __syncthreads();
+  return s;
+}
+template <int BS>
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double red[BS / kWave];
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < BS / kWave; ++k) s = fmax(s, red[k]);
+  }
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ int uniform(int x) {
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+}  // namespace lqg

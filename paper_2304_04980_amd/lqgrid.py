@@ -1,0 +1,284 @@
+"""Python binding of the lqgrid C ABI (include/lqgrid.h).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+liblqgrid.so.  PyTorch provides device memory (the problem arrays, outputs
+and the workspace are torch tensors on the GPU) and the current HIP stream.
+If the library is not built the binding raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblqgrid.so")
+
+OK, EINVAL, ENOTSPD, EBREAKDOWN, ENOCONV, EWORKSPACE, EHIP, EUNSUPPORTED = range(8)
+FP64, FP32_REFINE = 0, 1
+OP_DELTA, OP_XI, OP_OMEGA, OP_PHI_SOLVE, OP_PRECOND = range(5)
+PROF_DELTA, PROF_PHI_SOLVE, PROF_RHS, PROF_UPDATE = range(4)
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("K", c_int), ("N", c_int), ("T", c_int), ("n", c_int),
+                ("m", c_int), ("A", c_void_p), ("A_nbr", c_void_p),
+                ("B", c_void_p), ("Q", c_void_p), ("R", c_void_p),
+                ("QT", c_void_p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("outer_S", c_int), ("inner_L", c_int), ("tol", c_double),
+                ("max_iter", c_int), ("precision", c_int),
+                ("inner_tol", c_double), ("check_every", c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", c_int), ("iterations", c_int),
+                ("refinements", c_int), ("restarts", c_int),
+                ("rel_kkt_residual", c_double), ("rel_res_inf", c_double),
+                ("seconds", c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblqgrid.so (built by paper_2304_04980_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2304_04980_amd.build`"
+            " (the solver has no fallback path)")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7.
+    # Importing torch first makes the library's libamdhip64.so.7 dependency
+    # resolve (by SONAME) to the copy torch already mapped; loading ours first
+    # would map a second runtime that cannot open the device torch holds.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(path)
+    L.lqgrid_default_opts.argtypes = [POINTER(SolveOpts)]
+    L.lqgrid_default_opts.restype = None
+    L.lqgrid_workspace_bytes.argtypes = [POINTER(ProblemDesc), POINTER(SolveOpts)]
+    L.lqgrid_workspace_bytes.restype = c_size_t
+    L.lqgrid_setup.argtypes = [POINTER(ProblemDesc), c_void_p, c_size_t,
+                               c_void_p, POINTER(c_void_p)]
+    L.lqgrid_setup.restype = c_int
+    L.lqgrid_factor.argtypes = [c_void_p]
+    L.lqgrid_factor.restype = c_int
+    L.lqgrid_pcg_solve.argtypes = [c_void_p, c_void_p, POINTER(SolveOpts),
+                                   c_void_p, c_void_p, c_void_p, c_void_p,
+                                   POINTER(Info)]
+    L.lqgrid_pcg_solve.restype = c_int
+    L.lqgrid_batch_workspace_bytes.argtypes = [c_int, POINTER(ProblemDesc),
+                                               POINTER(SolveOpts)]
+    L.lqgrid_batch_workspace_bytes.restype = c_size_t
+    L.lqgrid_batch_solve.argtypes = [c_int, POINTER(ProblemDesc),
+                                     POINTER(c_void_p), POINTER(SolveOpts),
+                                     POINTER(c_void_p), c_void_p, c_size_t,
+                                     c_void_p, POINTER(Info)]
+    L.lqgrid_batch_solve.restype = c_int
+    L.lqgrid_apply_operator.argtypes = [c_void_p, c_int, c_int, c_int,
+                                        c_void_p, c_void_p]
+    L.lqgrid_apply_operator.restype = c_int
+    L.lqgrid_profile_enable.argtypes = [c_void_p, c_int]
+    L.lqgrid_profile_enable.restype = c_int
+    L.lqgrid_profile_read.argtypes = [c_void_p, c_int, POINTER(c_longlong),
+                                      POINTER(c_double)]
+    L.lqgrid_profile_read.restype = c_int
+    L.lqgrid_destroy.argtypes = [c_void_p]
+    L.lqgrid_destroy.restype = None
+    L.lqgrid_status_string.argtypes = [c_int]
+    L.lqgrid_status_string.restype = ctypes.c_char_p
+    L.lqgrid_abi_version.argtypes = []
+    L.lqgrid_abi_version.restype = c_int
+    L.lqgrid_last_error.argtypes = []
+    L.lqgrid_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+EXPORTED = ["lqgrid_default_opts", "lqgrid_workspace_bytes", "lqgrid_setup",
+            "lqgrid_factor", "lqgrid_pcg_solve", "lqgrid_batch_workspace_bytes",
+            "lqgrid_batch_solve", "lqgrid_apply_operator",
+            "lqgrid_profile_enable", "lqgrid_profile_read", "lqgrid_destroy",
+            "lqgrid_status_string", "lqgrid_abi_version", "lqgrid_last_error"]
+
+
+class LqgridError(RuntimeError):
+    def __init__(self, status, where):
+        L = load()
+        msg = L.lqgrid_status_string(status).decode()
+        if status == EHIP:
+            msg += " [" + L.lqgrid_last_error().decode() + "]"
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load().lqgrid_default_opts(byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def workspace_bytes(K, N, T, n, m) -> int:
+    d = ProblemDesc(K, N, T, n, m, None, None, None, None, None, None)
+    return load().lqgrid_workspace_bytes(byref(d), None)
+
+
+def problem_desc(K, N, T, n, m, A, A_nbr, B, Q, R, QT=None) -> ProblemDesc:
+    """Tensors must be contiguous float64 CUDA tensors in the header's
+    layouts; the caller keeps them alive while the setup work runs."""
+    return ProblemDesc(K, N, T, n, m, _ptr(A), _ptr(A_nbr), _ptr(B), _ptr(Q),
+                       _ptr(R), _ptr(QT))
+
+
+class Context:
+    """One problem: lqgrid_setup + lqgrid_factor, then any number of
+    lqgrid_pcg_solve calls (e.g. for different initial states)."""
+
+    def __init__(self, problem, device="cuda", factor=True, workspace=None,
+                 arrays=None):
+        """problem: an lqgrid_synth.Problem (numpy arrays, copied to the
+        device) or, with ``arrays``, just the dims of device-resident tensors.
+        workspace: optional preallocated uint8 CUDA tensor, reused as is."""
+        import torch
+        self.L = load()
+        p = problem
+        self.dims = (p.K, p.N, p.T, p.n, p.m)
+        f64 = dict(dtype=torch.float64, device=device)
+        if arrays is None:
+            arrays = {k: torch.as_tensor(getattr(p, k)).to(**f64).contiguous()
+                      for k in ("A", "A_nbr", "B", "Q", "R", "QT")}
+        self.arrays = arrays
+        a = self.arrays
+        self.desc = problem_desc(*self.dims, a["A"], a["A_nbr"], a["B"], a["Q"],
+                                 a["R"], a["QT"])
+        nbytes = self.L.lqgrid_workspace_bytes(byref(self.desc), None)
+        if nbytes == 0:
+            raise LqgridError(EINVAL, "lqgrid_workspace_bytes")
+        # 256-byte alignment: torch's caching allocator returns 512-byte
+        # aligned blocks for fresh allocations
+        if workspace is None or workspace.numel() < nbytes + 256:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self.workspace = workspace
+        base = self.workspace.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        ctx = c_void_p()
+        st = self.L.lqgrid_setup(byref(self.desc), c_void_p(self.ws_ptr),
+                                 self.ws_bytes, _stream(), byref(ctx))
+        if st != OK:
+            raise LqgridError(st, "lqgrid_setup")
+        self.ctx = ctx
+        if factor:
+            self.factor()
+
+    def factor(self):
+        st = self.L.lqgrid_factor(self.ctx)
+        if st != OK:
+            raise LqgridError(st, "lqgrid_factor")
+
+    def solve(self, x0, opts: SolveOpts | None = None, delta_init=None,
+              want_primal=False, out=None, raise_on_error=True):
+        """x0: [N][K][n] float64 CUDA tensor (or array).  Returns
+        (delta [T+1][N][K][n], x or None, u or None, info dict)."""
+        import torch
+        K, N, T, n, m = self.dims
+        dev = self.arrays["A"].device
+        x0 = torch.as_tensor(x0).to(dtype=torch.float64, device=dev).contiguous()
+        if opts is None:
+            opts = default_opts()
+        delta = out if out is not None else torch.empty((T + 1, N, K, n), dtype=torch.float64, device=dev)
+        x = u = None
+        if want_primal:
+            x = torch.empty((T + 1, N, K, n), dtype=torch.float64, device=dev)
+            u = torch.empty((T, N, K, m), dtype=torch.float64, device=dev)
+        di = None
+        if delta_init is not None:
+            di = torch.as_tensor(delta_init).to(dtype=torch.float64, device=dev).contiguous()
+        info = Info()
+        st = self.L.lqgrid_pcg_solve(self.ctx, _ptr(x0), byref(opts), _ptr(di),
+                                     _ptr(delta), _ptr(x), _ptr(u), byref(info))
+        if st != OK and raise_on_error:
+            raise LqgridError(st, "lqgrid_pcg_solve")
+        return delta, x, u, info.as_dict()
+
+    def apply(self, op, vec, S=2, L=2):
+        import torch
+        dev = self.arrays["A"].device
+        vin = torch.as_tensor(vec).to(dtype=torch.float64, device=dev).contiguous()
+        out = torch.empty_like(vin)
+        st = self.L.lqgrid_apply_operator(self.ctx, op, S, L, _ptr(vin), _ptr(out))
+        if st != OK:
+            raise LqgridError(st, "lqgrid_apply_operator")
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def profile_enable(self, on=True):
+        self.L.lqgrid_profile_enable(self.ctx, 1 if on else 0)
+
+    def profile_read(self, kernel):
+        n = c_longlong()
+        ms = c_double()
+        self.L.lqgrid_profile_read(self.ctx, kernel, byref(n), byref(ms))
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.lqgrid_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_solve(problems, x0s=None, opts: SolveOpts | None = None, device="cuda"):
+    """lqgrid_batch_solve over a list of problems sharing n and m."""
+    import torch
+    L = load()
+    f64 = dict(dtype=torch.float64, device=device)
+    keep = []
+    descs = (ProblemDesc * len(problems))()
+    x0p = (c_void_p * len(problems))()
+    outp = (c_void_p * len(problems))()
+    outs = []
+    for k, p in enumerate(problems):
+        a = {nm: torch.as_tensor(getattr(p, nm)).to(**f64).contiguous()
+             for nm in ("A", "A_nbr", "B", "Q", "R", "QT")}
+        keep.append(a)
+        descs[k] = problem_desc(p.K, p.N, p.T, p.n, p.m, a["A"], a["A_nbr"],
+                                a["B"], a["Q"], a["R"], a["QT"])
+        x0 = torch.as_tensor(p.x0 if x0s is None else x0s[k]).to(**f64).contiguous()
+        keep.append(x0)
+        x0p[k] = x0.data_ptr()
+        o = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
+        outs.append(o)
+        outp[k] = o.data_ptr()
+    if opts is None:
+        opts = default_opts()
+    nbytes = L.lqgrid_batch_workspace_bytes(len(problems), descs, byref(opts))
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    wp = (ws.data_ptr() + 255) // 256 * 256
+    infos = (Info * len(problems))()
+    st = L.lqgrid_batch_solve(len(problems), descs, x0p, byref(opts), outp,
+                              c_void_p(wp), nbytes, _stream(), infos)
+    return outs, [i.as_dict() for i in infos], st

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every symbol the header declares, and
+rejects invalid arguments before touching the GPU (CPU only: no kernel is
+launched by any call here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2304_04980_amd import lqgrid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lqgrid.h")
+
+
+def header_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"LQGRID_API\s+[\w\s\*]*?\b(lqgrid_\w+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    syms = header_symbols()
+    for name in ("lqgrid_setup", "lqgrid_factor", "lqgrid_pcg_solve",
+                 "lqgrid_batch_solve"):
+        assert name in syms
+    assert sorted(lqgrid.EXPORTED) == syms
+
+
+def test_library_exports_every_header_symbol():
+    L = lqgrid.load()
+    for name in header_symbols():
+        assert hasattr(L, name), name
+    assert L.lqgrid_abi_version() == 1
+
+
+def _desc(K=4, N=4, T=5, n=2, m=1, ptr=8):
+    p = ctypes.c_void_p(ptr)
+    return lqgrid.ProblemDesc(K, N, T, n, m, p, p, p, p, p, None)
+
+
+def test_workspace_bytes_and_invalid_dims():
+    L = lqgrid.load()
+    assert L.lqgrid_workspace_bytes(ctypes.byref(_desc()), None) > 0
+    for bad in [dict(K=0), dict(N=0), dict(T=0), dict(n=0), dict(m=0)]:
+        assert L.lqgrid_workspace_bytes(ctypes.byref(_desc(**bad)), None) == 0
+    # grows linearly in K*N*T (O(KNT) memory)
+    a = L.lqgrid_workspace_bytes(ctypes.byref(_desc(K=16, N=16, T=63)), None)
+    b = L.lqgrid_workspace_bytes(ctypes.byref(_desc(K=32, N=16, T=63)), None)
+    assert 1.8 < b / a < 2.2
+
+
+def test_setup_rejects_bad_arguments_without_gpu():
+    L = lqgrid.load()
+    ctx = ctypes.c_void_p()
+    # invalid dims
+    assert L.lqgrid_setup(ctypes.byref(_desc(K=0)), ctypes.c_void_p(256), 1 << 30,
+                          None, ctypes.byref(ctx)) == lqgrid.EINVAL
+    # null problem array
+    d = _desc()
+    d.A = None
+    assert L.lqgrid_setup(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None,
+                          ctypes.byref(ctx)) == lqgrid.EINVAL
+    # unsupported state size
+    assert L.lqgrid_setup(ctypes.byref(_desc(n=5)), ctypes.c_void_p(256), 1 << 30,
+                          None, ctypes.byref(ctx)) == lqgrid.EUNSUPPORTED
+    # workspace: null, misaligned, too small
+    need = L.lqgrid_workspace_bytes(ctypes.byref(_desc()), None)
+    assert L.lqgrid_setup(ctypes.byref(_desc()), None, need, None,
+                          ctypes.byref(ctx)) == lqgrid.EWORKSPACE
+    assert L.lqgrid_setup(ctypes.byref(_desc()), ctypes.c_void_p(256 + 8), need,
+                          None, ctypes.byref(ctx)) == lqgrid.EWORKSPACE
+    assert L.lqgrid_setup(ctypes.byref(_desc()), ctypes.c_void_p(256), need - 1,
+                          None, ctypes.byref(ctx)) == lqgrid.EWORKSPACE
+    assert L.lqgrid_setup(ctypes.byref(_desc()), ctypes.c_void_p(256), need,
+                          None, None) == lqgrid.EINVAL
+
+
+def test_null_context_and_status_strings():
+    L = lqgrid.load()
+    assert L.lqgrid_factor(None) == lqgrid.EINVAL
+    info = lqgrid.Info()
+    assert L.lqgrid_pcg_solve(None, None, None, None, None, None, None,
+                              ctypes.byref(info)) == lqgrid.EINVAL
+    assert L.lqgrid_apply_operator(None, 0, 2, 2, None, None) == lqgrid.EINVAL
+    for s in range(8):
+        assert len(L.lqgrid_status_string(s)) > 0
+    L.lqgrid_destroy(None)

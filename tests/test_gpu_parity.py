@@ -1,0 +1,206 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Operators: element-wise comparison on the same seeded inputs at sizes that
+span several 64-wide time tiles with a ragged tail, odd and even N (the odd
+case exercises the single-column last super-column), K = 1, N = 1, T = 1 and
+n = 1..4.
+
+Tolerances (FP64, derived from the arithmetic): each operator output is a sum
+of at most 23 n-by-n block products, evaluated in a different order than the
+oracle; the element-wise bound used is 1e-12 * max|ref|.  Phi~^-1 multiplies
+by the explicit inverse of each Cholesky diagonal block instead of a banded
+triangular solve: bound 1e-11 * max|ref| (kappa of the 2n x 2n blocks is
+O(10^2) on these inputs).  Whole solves: the relative residual must meet the
+requested tolerance, and the error to the exact solution obeys
+||e|| / ||delta*|| <= kappa(Delta) * relative residual.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from lqgrid_synth import make_problem, config_problem
+from oracle import kkt, slab, nbjm, pcg, residual
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_abi(p, v):
+    """(T+1, KNn) oracle array -> [T+1][N][K][n]."""
+    return v.reshape(p.T + 1, p.N, p.K, p.n)
+
+
+def rand_vec(p, seed):
+    return np.random.default_rng(seed).standard_normal((p.T + 1, p.N, p.K, p.n))
+
+
+CASES = [
+    # K, N, T, n, m, qt_scale
+    (4, 4, 20, 2, 1, 1.0),
+    (5, 7, 150, 3, 2, 1.0),     # odd N, three time tiles, ragged tail
+    (6, 6, 63, 4, 2, 2.5),      # T+1 = 64 exactly, distinct terminal weight
+    (3, 5, 64, 4, 2, 0.7),      # T+1 = 65: one-lane second tile, QT != Q
+    (1, 5, 9, 2, 1, 1.0),       # K = 1
+    (6, 1, 9, 2, 2, 1.0),       # N = 1 (single dummy-padded super-column)
+    (4, 3, 1, 1, 1, 1.0),       # T = 1, n = 1
+    (7, 8, 40, 4, 3, 1.0),
+]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.mark.parametrize("case", CASES, ids=[str(c) for c in CASES])
+def test_operators_match_oracle(lib, torch, case):
+    from paper_2304_04980_amd import lqgrid
+    K, N, T, n, m, qt = case
+    say("operators case", case)
+    p = make_problem(K, N, T, n, m, seed=K * 100 + N * 10 + T, qt_scale=qt)
+    ctx = lqgrid.Context(p)
+    ops = slab.SlabOperators(p)
+    v = rand_vec(p, 7)
+    vf = v.reshape(T + 1, -1)
+    checks = [
+        (lqgrid.OP_DELTA, ops.delta(vf), 1e-12),
+        (lqgrid.OP_XI, ops.xi(vf), 1e-12),
+        (lqgrid.OP_OMEGA, ops.omega(vf), 1e-12),
+        (lqgrid.OP_PHI_SOLVE, ops.phi_solve(vf), 1e-11),
+    ]
+    for op, ref, tol in checks:
+        got = ctx.apply(op, v).cpu().numpy().reshape(ref.shape)
+        err = np.abs(got - ref).max()
+        say(f"  op {op}: max err {err:.3e} (scale {np.abs(ref).max():.3e})")
+        assert err <= tol * np.abs(ref).max(), (op, err)
+    for S, L in [(2, 2), (1, 2), (3, 4)]:
+        ref = nbjm.slab_preconditioner(ops, S, L)(vf)
+        got = ctx.apply(lqgrid.OP_PRECOND, v, S=S, L=L).cpu().numpy().reshape(ref.shape)
+        err = np.abs(got - ref).max()
+        say(f"  precond S={S} L={L}: max err {err:.3e}")
+        assert err <= 1e-10 * np.abs(ref).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_tiny_solve_matches_dense_kkt(lib, torch, seed):
+    """Tiny configuration: GPU PCG vs brute-force dense KKT LDL'."""
+    from paper_2304_04980_amd import lqgrid
+    p, tol = config_problem("tiny", seed)
+    say("tiny solve seed", seed)
+    ctx = lqgrid.Context(p)
+    delta, x, u, info = ctx.solve(torch.as_tensor(p.x0), lqgrid.default_opts(tol=tol),
+                                  want_primal=True)
+    ref = kkt.solve_kkt(p)
+    d = delta.cpu().numpy().ravel()
+    err = np.linalg.norm(d - ref["delta"]) / np.linalg.norm(ref["delta"])
+    ops = slab.SlabOperators(p)
+    gate = residual.kkt_residual(ops, d.reshape(p.T + 1, -1))
+    from oracle import stack
+    D = stack.delta_matrix(p).toarray()
+    ev = np.linalg.eigvalsh(D)
+    kappa = ev[-1] / ev[0]
+    say(f"  iters {info['iterations']} gpu-res {info['rel_kkt_residual']:.2e} "
+        f"oracle-res {gate['rel2']:.2e} err {err:.2e} kappa {kappa:.1f}")
+    assert info["status"] == lqgrid.OK
+    assert gate["rel2"] <= tol * 1.01
+    assert abs(info["rel_kkt_residual"] - gate["schur_rel2"]) <= 1e-3 * tol + 1e-15
+    assert err <= kappa * gate["rel2"] * 1.01 + 1e-14
+    xr = ref["x"].reshape(p.T + 1, p.N, p.K, p.n)
+    ur = ref["u"].reshape(p.T, p.N, p.K, p.m)
+    assert np.abs(x.cpu().numpy() - xr).max() <= kappa * tol * 10 * np.abs(xr).max()
+    assert np.abs(u.cpu().numpy() - ur).max() <= kappa * tol * 10 * np.abs(ur).max()
+    # same iteration count as the oracle's Algorithm 1 (rounding may move the
+    # exit by an iteration)
+    pre = nbjm.slab_preconditioner(ops, 2, 2)
+    _, it, _ = pcg.pcg(ops.delta, pre, ops.r_delta(), tol=tol)
+    assert abs(info["iterations"] - it) <= 2
+    ctx.close()
+
+
+def test_riccati_single_node(lib, torch):
+    """K = N = 1: the GPU solution equals the textbook Riccati LQR."""
+    from paper_2304_04980_amd import lqgrid
+    from oracle import riccati
+    p = make_problem(1, 1, 60, 4, 2, rho=1.05, seed=3, qt_scale=2.0)
+    R = riccati.lqr_of_problem(p)
+    ctx = lqgrid.Context(p)
+    delta, x, u, info = ctx.solve(torch.as_tensor(p.x0),
+                                  lqgrid.default_opts(tol=1e-12), want_primal=True)
+    assert info["status"] == lqgrid.OK
+    assert np.abs(x.cpu().numpy()[:, 0, 0] - R["x"]).max() <= 1e-8 * np.abs(R["x"]).max()
+    assert np.abs(u.cpu().numpy()[:, 0, 0] - R["u"]).max() <= 1e-8 * np.abs(R["u"]).max()
+    assert np.abs(delta.cpu().numpy()[:, 0, 0] - R["delta"]).max() <= 1e-8 * np.abs(R["delta"]).max()
+
+
+def test_plain_config_solve(lib, torch):
+    """K = N = 32, T = 100, n = 4, m = 2 (the plain FP64 GPU configuration):
+    oracle-evaluated residual below tol, iteration count equal to the oracle's
+    Algorithm 1 within 2, and agreement with the oracle's PCG solution."""
+    from paper_2304_04980_amd import lqgrid
+    p, tol = config_problem("plain", 0)
+    say("plain config solve")
+    ctx = lqgrid.Context(p)
+    delta, _, _, info = ctx.solve(torch.as_tensor(p.x0), lqgrid.default_opts(tol=tol))
+    ops = slab.SlabOperators(p)
+    d = delta.cpu().numpy().reshape(p.T + 1, -1)
+    gate = residual.kkt_residual(ops, d)
+    pre = nbjm.slab_preconditioner(ops, 2, 2)
+    xo, it, _ = pcg.pcg(ops.delta, pre, ops.r_delta(), tol=tol)
+    rel = np.linalg.norm(d - xo) / np.linalg.norm(xo)
+    say(f"  gpu iters {info['iterations']} oracle iters {it} res {gate['rel2']:.2e} "
+        f"diff {rel:.2e} t {info['seconds']*1e3:.1f} ms")
+    assert info["status"] == lqgrid.OK
+    assert gate["rel2"] <= tol * 1.01
+    assert abs(info["iterations"] - it) <= 2
+    assert rel <= 1e-6
+
+
+def test_warm_start_and_exact_start(lib, torch):
+    """Any warm start reaches the same tolerance; starting at the solution
+    takes zero iterations."""
+    from paper_2304_04980_amd import lqgrid
+    p, tol = config_problem("tiny", 4)
+    ctx = lqgrid.Context(p)
+    x0 = torch.as_tensor(p.x0)
+    opts = lqgrid.default_opts(tol=tol)
+    d0, _, _, i0 = ctx.solve(x0, opts)
+    garbage = np.random.default_rng(1).standard_normal((p.T + 1, p.N, p.K, p.n)) * 10
+    d1, _, _, i1 = ctx.solve(x0, opts, delta_init=torch.as_tensor(garbage))
+    assert i1["status"] == lqgrid.OK and i1["rel_kkt_residual"] <= tol
+    ref = kkt.solve_kkt(p)["delta"].reshape(d0.shape)
+    d2, _, _, i2 = ctx.solve(x0, opts, delta_init=torch.as_tensor(ref))
+    assert i2["iterations"] == 0 and i2["rel_kkt_residual"] <= tol
+
+
+def test_error_paths(lib, torch):
+    from paper_2304_04980_amd import lqgrid
+    p, tol = config_problem("tiny", 0)
+    ctx = lqgrid.Context(p)
+    x0 = torch.as_tensor(p.x0)
+    # odd L is rejected (Theorem 2 needs even L)
+    with pytest.raises(lqgrid.LqgridError) as e:
+        ctx.solve(x0, lqgrid.default_opts(inner_L=3))
+    assert e.value.status == lqgrid.EINVAL
+    # iteration cap
+    _, _, _, info = ctx.solve(x0, lqgrid.default_opts(tol=1e-14, max_iter=3,
+                                                      check_every=1),
+                              raise_on_error=False)
+    assert info["status"] == lqgrid.ENOCONV and info["iterations"] == 3
+    # indefinite weight -> not SPD factor
+    q = make_problem(3, 3, 4, 2, 1, seed=0)
+    q.Q[1, 1] = -np.eye(2)
+    with pytest.raises(lqgrid.LqgridError) as e:
+        lqgrid.Context(q)
+    assert e.value.status == lqgrid.ENOTSPD
+    # non-finite initial state -> breakdown
+    bad = x0.clone()
+    bad[0, 0, 0] = float("nan")
+    _, _, _, info = ctx.solve(bad, lqgrid.default_opts(), raise_on_error=False)
+    assert info["status"] == lqgrid.EBREAKDOWN
