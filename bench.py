@@ -40,7 +40,7 @@ def kernel_bytes(p, precision_bytes=8):
                    per node 13 (G) + 5 (Cdn) + 5 (Cup) + 2 (Q^-1, Q_T^-1 - Q^-1)
                    n x n FP64 blocks.
       Phi solve:   read tau, write theta (2 U w) + the factors of the one
-                   interior class: V K blocks rows x 3 (2n)^2 FP64 + Q (t = 0).
+                   interior class: V K block rows x 6 (2n)^2 FP64 + Q (t = 0).
     """
     K, N, T, n = p.K, p.N, p.T, p.n
     U = K * N * n * (T + 1)
@@ -49,7 +49,7 @@ def kernel_bytes(p, precision_bytes=8):
     nodes = K * N
     return {
         "delta": 2 * U * w + nodes * 25 * n * n * 8,
-        "phi_solve": 2 * U * w + V * K * 3 * (2 * n) ** 2 * 8 + nodes * n * n * 8,
+        "phi_solve": 2 * U * w + V * K * 6 * (2 * n) ** 2 * 8 + nodes * n * n * 8,
     }
 
 

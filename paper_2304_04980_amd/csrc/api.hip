@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -26,7 +27,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 enum Vec { kRd, kDl, kR, kD, kY, kBufA, kBufB, kBufC, kBufD, kNumVec };
 
 struct Plan {
-  size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Lf;
+  size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Fw, Bw;
   size_t vec[kNumVec];
   size_t psum, pmax, scal;
   int npartial;
@@ -69,7 +70,8 @@ Plan make_plan(const Dims& D) {
   P.QTd = take(nodes * nn * 8);
   P.Qm = take(nodes * nn * 8);
   P.RiBT = take(nodes * (size_t)D.m * D.n * 8);
-  P.Lf = take((size_t)2 * D.V * D.K * 3 * NB * NB * 8);
+  P.Fw = take((size_t)2 * D.V * (D.K + 1) * NB * kFwRow * 8);
+  P.Bw = take((size_t)2 * D.V * D.K * NB * kBwRow * 8);
   const int apply_blocks = ((D.real_nodes + 3) / 4) * ((D.Tt + 63) / 64);
   P.npartial = std::max(apply_blocks, kFlatBlocks);
   P.psum = take((size_t)P.npartial * 8);
@@ -278,6 +280,8 @@ int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
   if (!desc->A || !desc->A_nbr || !desc->B || !desc->Q || !desc->R)
     return LQGRID_EINVAL;
   if (D.n > kMaxN || D.m > kMaxM) return LQGRID_EUNSUPPORTED;
+  // the block solves address each vector with 32-bit byte offsets
+  if (D.vlen * 8 >= (1LL << 31)) return LQGRID_EUNSUPPORTED;
   const Plan P = make_plan(D);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 ||
       workspace_bytes < P.total)
@@ -299,7 +303,8 @@ int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
   c->C.QTd = reinterpret_cast<double*>(w + P.QTd);
   c->C.Qm = reinterpret_cast<double*>(w + P.Qm);
   c->C.RiBT = reinterpret_cast<double*>(w + P.RiBT);
-  c->C.Lf = reinterpret_cast<double*>(w + P.Lf);
+  c->C.Fw = reinterpret_cast<double*>(w + P.Fw);
+  c->C.Bw = reinterpret_cast<double*>(w + P.Bw);
   for (int v = 0; v < kNumVec; ++v)
     c->vec[v] = reinterpret_cast<double*>(w + P.vec[v]);
   c->psum = reinterpret_cast<double*>(w + P.psum);
@@ -323,6 +328,10 @@ int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
 int lqgrid_factor(lqgrid_ctx* c) {
   if (!c) return LQGRID_EINVAL;
   clear_stale_error();
+  // entries never written by the factorisation (padding, N1/N2 of the last
+  // block rows) must read as zero
+  vec_zero(c->C.Fw, (long long)2 * c->D.V * (c->D.K + 1) * 2 * c->D.n * kFwRow, c->stream);
+  vec_zero(c->C.Bw, (long long)2 * c->D.V * c->D.K * 2 * c->D.n * kBwRow, c->stream);
   launch_factor(c->D, c->C, c->sc, c->stream);
   HIPCHECK(hipGetLastError());
   Scalars h;

@@ -17,11 +17,20 @@
 //     Cup[p][k]  Q_p^-1 A_hat[q,p]'; Delta_{t,t+1} = -Cup
 //     AT5[p][k]  A_hat[q,p]' (recovery x = Q^-1 A~' delta)
 //     Qi, QTi, QTd (= QT^-1 - Q^-1), Qm (= Q, the t = 0 block solve), RiBT
-//   factors      Lf[cls][v][i][3][(2n)^2]: banded block Cholesky of
-//                Phi_bar_{v,t} in (i, column-in-pair, component) order:
-//                slot 0 = inv(L_ii) (lower triangular), 1 = L_{i,i-1},
-//                2 = L_{i,i-2}.  cls 0: 1 <= t <= T-1 (and t = T when QT = Q),
-//                cls 1: t = T.
+//   factors      banded block Cholesky Phi_bar_{v,t} = L L' in (i,
+//                column-in-pair, component) order, stored as the products the
+//                substitutions use (Linv_i = L_ii^-1):
+//                  forward  z_i   = Linv_i tau_i - M1_i z_{i-1} - M2_i z_{i-2}
+//                           w_i   = Linv_i' z_i
+//                  backward theta_i = w_i - N1_i theta_{i+1} - N2_i theta_{i+2}
+//                with M1_i = Linv_i L_{i,i-1}, M2_i = Linv_i L_{i,i-2},
+//                N1_i = Linv_i' L_{i+1,i}', N2_i = Linv_i' L_{i+2,i}'.
+//                Fw[cls][v][i][r][32] (i = 0..K) = rows r of (M1_i, M2_i,
+//                Linv_i, Linv_{i-1}'), each padded to 8 doubles (block row K
+//                holds only Linv_{K-1}'); Bw[cls][v][i][r][16] = rows r of
+//                (N1_i, N2_i).  One row of a block row is 256 (128) contiguous
+//                bytes: one coalesced load per wavefront and block row.
+//                cls 0: 1 <= t <= T-1 (and t = T when QT = Q), cls 1: t = T.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
@@ -32,6 +41,8 @@ namespace lqg {
 constexpr int kWave = 64;
 constexpr int kMaxN = 4;   // compiled state sizes: 1..kMaxN
 constexpr int kMaxM = 8;
+constexpr int kFwRow = 32;  // doubles per row of a forward factor block row
+constexpr int kBwRow = 16;  // doubles per row of a backward factor block row
 
 // (di, dj) offsets of the 13-point stencil (Manhattan distance <= 2).
 constexpr int kOff13[13][2] = {{0, 0},  {-1, 0}, {1, 0},  {0, -1}, {0, 1},
@@ -58,7 +69,7 @@ struct Dims {
 struct Coef {
   double *G13, *Cdn, *Cup, *AT5;
   double *Qi, *QTi, *QTd, *Qm, *RiBT;
-  double *Lf;      // factors
+  double *Fw, *Bw;  // factors in the substitution layout
 };
 
 // Device-resident PCG scalars.
@@ -123,6 +134,15 @@ __device__ __forceinline__ double block_max(double v) {
   }
   __syncthreads();
   return s;
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store of the wavefront, which would drain
+// the register prefetch rings of the block-row sweeps at every block row.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 __device__ __forceinline__ int uniform(int x) {

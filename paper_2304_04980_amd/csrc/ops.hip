@@ -189,141 +189,232 @@ __global__ __launch_bounds__(256) void k_xi(Dims D, Coef C,
 }
 
 // Forward/backward substitution with the banded block Cholesky factor of
-// Phi_bar_{v,cls} for this lane's time step.  z (the forward result) is
-// parked in `out` and overwritten by theta in the backward sweep.
-template <int NS>
-__device__ __forceinline__ void sweep(const Dims& D, const Coef& C, int cls,
-                                      int v, int t, const double* __restrict__ tau,
-                                      double* __restrict__ out) {
-  constexpr int NB = 2 * NS, NB2 = NB * NB;
-  const int K = D.K, ldt = D.ldt;
-  const int p0 = (2 * v) * K, p1 = (2 * v + 1) * K;  // column starts
-  const double* F0 = C.Lf + (((size_t)cls * D.V + v) * K) * 3 * NB2;
-  double zm1[NB], zm2[NB];
+// Phi_bar_{v,cls} (eq. "decomposed_problem") for the 64 time steps of this
+// workgroup.  The 2n rows of each block row are split over 2n wavefronts,
+// one row per wavefront (R selects it at compile time), one time step per
+// lane.  Per block row the wavefronts exchange their row of z_i (theta_i)
+// through LDS with one barrier:
+//   z_i     = Linv_i tau_i - M1_i z_{i-1} - M2_i z_{i-2}
+//   w_i     = Linv_i' z_i                  (parked in `out`)
+//   theta_i = w_i - N1_i theta_{i+1} - N2_i theta_{i+2}
+// Latency hiding: a row's 32 (16) factor coefficients of a block row are one
+// 256-byte (128-byte) coalesced vector load, lane k holding dword k; they are
+// prefetched kPre block rows ahead in a register ring and moved to scalar
+// registers with v_readlane when used, so no scalar-memory wait is tied to
+// the LDS exchange.  tau and w are prefetched the same way.  All vector
+// accesses go through buffer resources: a lane outside this factor class
+// uses an out-of-range offset, whose loads return 0 and whose stores are
+// dropped, so the loop has no divergent branches.
+constexpr int kPre = 4;
+constexpr unsigned kOob = 0x80000000u;     // beyond every vector (< 2 GiB)
+constexpr int kRsrcWord3 = 0x00020000;     // raw buffer, 32-bit dwords
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p,
+                                                            long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                       double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+// Coefficient j (a double) of a row whose dwords are spread one per lane.
+__device__ __forceinline__ double coef(unsigned reg, int j) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j + 1);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int NS, int R>
+__device__ __forceinline__ void sweep_row(const Dims& D, const Coef& C, int cls,
+                                          int v, int lane, int t, bool act,
+                                          __amdgpu_buffer_rsrc_t rtau,
+                                          __amdgpu_buffer_rsrc_t rout,
+                                          double (*zb)[2 * NS][kWave]) {
+  constexpr int NB = 2 * NS;
+  constexpr int NT = R + 1;  // rows of tau that row R of z needs
+  const int K = D.K;
+  const unsigned istride = (unsigned)(NS * D.ldt * 8);  // bytes per block row
+  unsigned rb[NT];  // byte offset of row c of block row 0 (node (0, 2v + c/NS))
 #pragma unroll
-  for (int a = 0; a < NB; ++a) zm1[a] = zm2[a] = 0.0;
-  for (int i = 0; i < K; ++i) {
-    const double* F = F0 + (size_t)i * 3 * NB2;
-    double s[NB], h0[NS], h1[NS];
-    load_node<NS>(tau, p0 + i, t, ldt, h0);
-    load_node<NS>(tau, p1 + i, t, ldt, h1);
+  for (int c = 0; c < NT; ++c)
+    rb[c] = act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * 8)
+                : kOob;
+  const unsigned ro = act ? (unsigned)((((size_t)(2 * v + R / NS) * K * NS + (R % NS)) * D.ldt + t) * 8)
+                          : kOob;
+  // this row's factor coefficients: block row i at fw + i * fstep dwords
+  const size_t rows0 = ((size_t)cls * D.V + v) * K;
+  const size_t frows0 = ((size_t)cls * D.V + v) * (K + 1);
+  const unsigned* fw = reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow) + lane;
+  const unsigned* bw = reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow) + (lane & 31);
+  const size_t fstep = (size_t)NB * kFwRow * 2, bstep = (size_t)NB * kBwRow * 2;
+
+  // ---------------------------------------------------------- forward
+  // Block row i uses ring slot i % kPre; loads for row i + kPre (clamped to
+  // K-1) go into the slot just consumed.  The main loop covers whole chunks
+  // of kPre rows with straight-line code, so every wait on a prefetched slot
+  // is an exact in-order vmcnt count.
+  double z1[NB], z2[NB];
 #pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      s[a] = h0[a];
-      s[NS + a] = h1[a];
-    }
-    if (i >= 1) {
+  for (int b = 0; b < NB; ++b) z1[b] = z2[b] = 0.0;
+  unsigned cring[kPre];
+  double tring[kPre][NT];
 #pragma unroll
-      for (int a = 0; a < NB; ++a)
+  for (int u = 0; u < kPre; ++u) {
+    cring[u] = fw[(size_t)min(u, K) * fstep];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) s[a] = fma(-F[NB2 + a * NB + b], zm1[b], s[a]);
-    }
-    if (i >= 2) {
-#pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-          s[a] = fma(-F[2 * NB2 + a * NB + b], zm2[b], s[a]);
-    }
-    double z[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      double acc = 0.0;
-#pragma unroll
-      for (int b = 0; b <= a; ++b) acc = fma(F[a * NB + b], s[b], acc);
-      z[a] = acc;
-    }
-#pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      h0[a] = z[a];
-      h1[a] = z[NS + a];
-    }
-    store_node<NS>(out, p0 + i, t, ldt, h0);
-    store_node<NS>(out, p1 + i, t, ldt, h1);
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      zm2[a] = zm1[a];
-      zm1[a] = z[a];
-    }
+    for (int c = 0; c < NT; ++c)
+      tring[u][c] = buf_ld(rtau, rb[c] + (unsigned)min(u, K - 1) * istride);
   }
-  // backward: theta_i = Linv_i' (z_i - L_{i+1,i}' theta_{i+1} - L_{i+2,i}' theta_{i+2})
+  auto fstep_body = [&](int i, int s, bool has_prev) {
+    const unsigned cf = cring[s];
+    double ti[NT];
 #pragma unroll
-  for (int a = 0; a < NB; ++a) zm1[a] = zm2[a] = 0.0;
-  for (int i = K - 1; i >= 0; --i) {
-    const double* F = F0 + (size_t)i * 3 * NB2;
-    double s[NB], h0[NS], h1[NS];
-    load_node<NS>(out, p0 + i, t, ldt, h0);
-    load_node<NS>(out, p1 + i, t, ldt, h1);
+    for (int c = 0; c < NT; ++c) ti[c] = tring[s][c];
+    const int in = min(i + kPre, K);
+    cring[s] = fw[(size_t)in * fstep];
+    const int it = min(in, K - 1);
 #pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      s[a] = h0[a];
-      s[NS + a] = h1[a];
-    }
-    if (i + 1 < K) {
-      const double* F1 = F0 + (size_t)(i + 1) * 3 * NB2 + NB2;  // L_{i+1,i}
-#pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) s[a] = fma(-F1[b * NB + a], zm1[b], s[a]);
-    }
-    if (i + 2 < K) {
-      const double* F2 = F0 + (size_t)(i + 2) * 3 * NB2 + 2 * NB2;  // L_{i+2,i}
-#pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) s[a] = fma(-F2[b * NB + a], zm2[b], s[a]);
-    }
-    double th[NB];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
+    for (int c = 0; c < NT; ++c) tring[s][c] = buf_ld(rtau, rb[c] + (unsigned)it * istride);
+    if (has_prev) {  // w_{i-1} = row R of Linv_{i-1}' times z_{i-1}
       double acc = 0.0;
 #pragma unroll
-      for (int b = a; b < NB; ++b) acc = fma(F[b * NB + a], s[b], acc);
-      th[a] = acc;
+      for (int c = R; c < NB; ++c) acc = fma(coef(cf, 24 + c), z1[c], acc);
+      buf_st(rout, ro + (unsigned)(i - 1) * istride, acc);
     }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      h0[a] = th[a];
-      h1[a] = th[NS + a];
+    for (int c = 0; c < NB; ++c) {
+      if (c <= R) a0 = fma(coef(cf, 16 + c), ti[c], a0);
+      a1 = fma(coef(cf, c), z1[c], a1);
+      a2 = fma(coef(cf, 8 + c), z2[c], a2);
     }
-    store_node<NS>(out, p0 + i, t, ldt, h0);
-    store_node<NS>(out, p1 + i, t, ldt, h1);
+    zb[i & 1][R][lane] = a0 - a1 - a2;
+    lds_barrier();
 #pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      zm2[a] = zm1[a];
-      zm1[a] = th[a];
+    for (int b = 0; b < NB; ++b) {
+      z2[b] = z1[b];
+      z1[b] = zb[i & 1][b][lane];
     }
+  };
+  fstep_body(0, 0, false);
+  int i = 1;
+  for (; i + kPre <= K; i += kPre) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) fstep_body(i + u, (1 + u) % kPre, true);
+  }
+#pragma unroll
+  for (int u = 0; u < kPre - 1; ++u)
+    if (i + u < K) fstep_body(i + u, (1 + u) % kPre, true);
+  {  // w_{K-1}: block row K of Fw carries Linv_{K-1}'
+    const unsigned cf = fw[(size_t)K * fstep];
+    double acc = 0.0;
+#pragma unroll
+    for (int c = R; c < NB; ++c) acc = fma(coef(cf, 24 + c), z1[c], acc);
+    buf_st(rout, ro + (unsigned)(K - 1) * istride, acc);
+  }
+  lds_barrier();  // every wavefront is done reading zb before it is reused
+
+  // ---------------------------------------------------------- backward
+  double t1[NB], t2[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) t1[b] = t2[b] = 0.0;
+  unsigned bring[kPre];
+  double wring[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int iu = K - 1 - u >= 0 ? K - 1 - u : 0;
+    bring[u] = bw[(size_t)iu * bstep];
+    wring[u] = buf_ld(rout, ro + (unsigned)iu * istride);
+  }
+  auto bstep_body = [&](int i, int s) {
+    const unsigned cb = bring[s];
+    const double wi = wring[s];
+    const int in = max(i - kPre, 0);
+    bring[s] = bw[(size_t)in * bstep];
+    wring[s] = buf_ld(rout, ro + (unsigned)in * istride);
+    double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      a1 = fma(coef(cb, c), t1[c], a1);
+      a2 = fma(coef(cb, 8 + c), t2[c], a2);
+    }
+    const double th = wi - a1 - a2;
+    buf_st(rout, ro + (unsigned)i * istride, th);
+    zb[i & 1][R][lane] = th;
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      t2[b] = t1[b];
+      t1[b] = zb[i & 1][b][lane];
+    }
+  };
+  int j = K - 1;  // block row K-1-u uses slot u % kPre
+  for (; j - kPre + 1 >= 0; j -= kPre) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) bstep_body(j - u, u);
+  }
+#pragma unroll
+  for (int u = 0; u < kPre - 1; ++u)
+    if (j - u >= 0) bstep_body(j - u, u);
+  lds_barrier();
+}
+
+template <int NS, int R = 0>
+__device__ __forceinline__ void sweep_dispatch(int w, const Dims& D,
+                                               const Coef& C, int cls, int v,
+                                               int lane, int t, bool act,
+                                               __amdgpu_buffer_rsrc_t rtau,
+                                               __amdgpu_buffer_rsrc_t rout,
+                                               double (*zb)[2 * NS][kWave]) {
+  if constexpr (R < 2 * NS) {
+    if (w == R) sweep_row<NS, R>(D, C, cls, v, lane, t, act, rtau, rout, zb);
+    else sweep_dispatch<NS, R + 1>(w, D, C, cls, v, lane, t, act, rtau, rout, zb);
   }
 }
 
-// out = Phi~^-1 tau.  One wavefront per (super-column v, 64 time steps).
-// t = 0: Phi_bar_{v,0} = blkdiag(Q^-1), so theta = Q tau per node.
+// out = Phi~^-1 tau.  One workgroup of 2n wavefronts per (super-column v,
+// 64 time steps).  t = 0: Phi_bar_{v,0} = blkdiag(Q^-1), so theta = Q tau
+// per node.  t = T uses the second factor class when Q_T != Q.
 template <int NS>
-__global__ __launch_bounds__(64) void k_phi_solve(Dims D, Coef C,
-                                                  const double* __restrict__ tau,
-                                                  double* __restrict__ out,
-                                                  const Scalars* sc, int check,
-                                                  int qt_distinct) {
+__global__ __launch_bounds__(2 * NS * kWave) void k_phi_solve(
+    Dims D, Coef C, const double* __restrict__ tau, double* __restrict__ out,
+    const Scalars* sc, int check, int qt_distinct) {
   if (is_done(sc, check)) return;
+  __shared__ double zb[2][2 * NS][kWave];
   const int v = blockIdx.x;
-  const int t = blockIdx.y * kWave + (threadIdx.x & (kWave - 1));
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x >> 6);
+  const int t0 = blockIdx.y * kWave;
+  const int t = t0 + lane;
   const int T = D.T;
   const bool valid = t < D.Tt;
-  const bool cls0 = valid && t >= 1 && !(qt_distinct && t == T);
-  if (cls0) sweep<NS>(D, C, 0, v, t, tau, out);
-  if (qt_distinct && valid && t == T) sweep<NS>(D, C, 1, v, t, tau, out);
-  if (valid && t == 0) {
+  const long long bytes = D.vlen * 8;
+  const __amdgpu_buffer_rsrc_t rtau = make_rsrc(tau, bytes);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, bytes);
+  sweep_dispatch<NS>(w, D, C, 0, v, lane, t,
+                     valid && t >= 1 && !(qt_distinct && t == T), rtau, rout, zb);
+  if (qt_distinct && t0 <= T && T < t0 + kWave)
+    sweep_dispatch<NS>(w, D, C, 1, v, lane, t, valid && t == T, rtau, rout, zb);
+  if (blockIdx.y == 0) {
+    // t = 0 for every block row: independent n x n products, one block row
+    // per lane; wavefront w computes row w of the pair
     const size_t nn = (size_t)NS * NS;
-    for (int h = 0; h < 2; ++h)
-      for (int i = 0; i < D.K; ++i) {
-        const int p = (2 * v + h) * D.K + i;
-        double x[NS], acc[NS];
-        load_node<NS>(tau, p, 0, D.ldt, x);
+    const int h = w / NS, a = w % NS;
+    for (int i = lane; i < D.K; i += kWave) {
+      const int p = (2 * v + h) * D.K + i;
+      const double* Qp = C.Qm + p * nn + a * NS;
+      double acc = 0.0;
 #pragma unroll
-        for (int a = 0; a < NS; ++a) acc[a] = 0.0;
-        mv_add<NS>(C.Qm + p * nn, x, acc);
-        store_node<NS>(out, p, 0, D.ldt, acc);
-      }
+      for (int b = 0; b < NS; ++b)
+        acc = fma(Qp[b], tau[((size_t)p * NS + b) * D.ldt], acc);
+      out[((size_t)p * NS + a) * D.ldt] = acc;
+    }
   }
 }
 
@@ -606,9 +697,9 @@ void phi_solve(const Dims& D, const Coef& C, const double* tau, double* out,
                const Scalars* sc, int check_done, int qt_distinct,
                hipStream_t s) {
   const dim3 g(D.V, (D.Tt + kWave - 1) / kWave);
-#define CALL(NS)                                                            \
-  hipLaunchKernelGGL(k_phi_solve<NS>, g, dim3(64), 0, s, D, C, tau, out, sc, \
-                     check_done, qt_distinct)
+#define CALL(NS)                                                                \
+  hipLaunchKernelGGL((k_phi_solve<NS>), g, dim3(2 * NS * kWave), 0, s, D, C, tau, \
+                     out, sc, check_done, qt_distinct)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
 }

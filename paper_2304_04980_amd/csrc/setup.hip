@@ -314,10 +314,26 @@ __global__ __launch_bounds__(64) void k_factor(Dims D, Coef C, Scalars* sc) {
     }
     __syncthreads();
     if (act) {
-      double* out = C.Lf + ((((size_t)cls * D.V + v) * K + i) * 3) * NB2;
-      out[tid] = Li[tid];
-      out[NB2 + tid] = L1[tid];
-      out[2 * NB2 + tid] = L2[tid];
+      double m1 = 0.0, m2 = 0.0, n1 = 0.0, n2 = 0.0;
+      for (int k = 0; k < NB; ++k) {
+        m1 += Li[r * NB + k] * L1[k * NB + c];    // Linv_i L_{i,i-1}
+        m2 += Li[r * NB + k] * L2[k * NB + c];    // Linv_i L_{i,i-2}
+        n1 += Lp1[k * NB + r] * L1[c * NB + k];   // Linv_{i-1}' L_{i,i-1}'
+        n2 += Lp2[k * NB + r] * L2[c * NB + k];   // Linv_{i-2}' L_{i,i-2}'
+      }
+      const size_t rows = ((size_t)cls * D.V + v) * K;         // Bw rows of (cls, v)
+      const size_t frows = ((size_t)cls * D.V + v) * (K + 1);  // Fw rows of (cls, v)
+      double* fw = C.Fw + ((frows + i) * NB + r) * kFwRow;
+      fw[c] = m1;
+      fw[8 + c] = m2;
+      fw[16 + c] = Li[r * NB + c];
+      // Linv_i' is used one block row later (w_i needs all of z_i)
+      C.Fw[((frows + i + 1) * NB + r) * kFwRow + 24 + c] = Li[c * NB + r];
+      if (i >= 1) C.Bw[((rows + i - 1) * NB + r) * kBwRow + c] = n1;
+      if (i >= 2) C.Bw[((rows + i - 2) * NB + r) * kBwRow + 8 + c] = n2;
+    }
+    __syncthreads();
+    if (act) {
       Lp2[tid] = Lp1[tid];
       Lp1[tid] = Li[tid];
       L1p[tid] = L1[tid];
