@@ -121,7 +121,9 @@ def main():
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "plain", "tiny", "learned"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"],
+                    help="fp32r: FP32 sweeps inside FP64 iterative refinement")
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=512,
                     help="size of the plain copy used to scale PMC counters")
@@ -144,7 +146,12 @@ def main():
     nbytes = lqgrid.workspace_bytes(p.K, p.N, p.T, p.n, p.m)
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
     delta = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
-    opts = lqgrid.default_opts(tol=tol)
+    if args.precision == "fp32r":
+        opts = lqgrid.default_opts(tol=tol, precision=lqgrid.FP32_REFINE,
+                                   inner_tol=args.inner_tol)
+    else:
+        opts = lqgrid.default_opts(tol=tol)
+    wbytes = 4 if args.precision == "fp32r" else 8
     torch.cuda.synchronize()
 
     def step(profile=False):
@@ -189,7 +196,7 @@ def main():
         kern[nm] = {"launches": launches, "total_ms": ms,
                     "avg_ms": ms / launches if launches else None}
     dom = max(("delta", "phi_solve"), key=lambda k: kern[k]["total_ms"])
-    alg = kernel_bytes(p)[dom]
+    alg = kernel_bytes(p, wbytes)[dom]
     achieved = alg / (kern[dom]["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_from_profiles(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -201,7 +208,7 @@ def main():
     if kern[other]["avg_ms"]:
         roofline["other_kernel"] = {
             "kernel": other,
-            "achieved": round(kernel_bytes(p)[other] / (kern[other]["avg_ms"] * 1e-3) / 1e9, 1),
+            "achieved": round(kernel_bytes(p, wbytes)[other] / (kern[other]["avg_ms"] * 1e-3) / 1e9, 1),
             "avg_launch_ms": kern[other]["avg_ms"]}
 
     # plain copy of known size: reference for scaling the PMC byte counters
@@ -223,15 +230,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: K={p.K} N={p.N} T={p.T} n={p.n} "
-                               f"m={p.m}, plain FP64 PCG, S=L=2, tol={tol}",
+                               f"m={p.m}, {'plain FP64 PCG' if args.precision == 'fp64' else 'FP32 sweeps + FP64 refinement'}, S=L=2, tol={tol}",
                    "K": p.K, "N": p.N, "T": p.T, "n": p.n, "m": p.m,
-                   "S": 2, "L": 2, "tol": tol, "precision": "fp64",
+                   "S": 2, "L": 2, "tol": tol, "precision": args.precision,
                    "step": "setup+factor+pcg_solve"},
         "converged": ok,
         "pcg_iterations": iters,
+        "refinements": sum(i["refinements"] for i in infos) / len(infos),
         "pcg_iters_per_s": iters * args.steps / elapsed,
         "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
         "kernels": kern,

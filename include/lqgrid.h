@@ -109,9 +109,9 @@ typedef struct {
 /* Fills opts with the paper's settings: S = L = 2, tol 1e-10, FP64. */
 LQGRID_API void lqgrid_default_opts(lqgrid_solve_opts *opts);
 
-/* Bytes of device workspace that lqgrid_setup needs for this problem and
- * precision (0 if the description is invalid).  Workspace must be 256-byte
- * aligned.  opts may be NULL (FP64). */
+/* Bytes of device workspace that lqgrid_setup needs for this problem (0 if
+ * the description is invalid); it covers both precisions.  Workspace must be
+ * 256-byte aligned.  opts is unused and may be NULL. */
 LQGRID_API size_t lqgrid_workspace_bytes(const lqgrid_problem_desc *desc,
                               const lqgrid_solve_opts *opts);
 
@@ -163,13 +163,16 @@ LQGRID_API int lqgrid_batch_solve(int P, const lqgrid_problem_desc *descs,
  *   LQGRID_OP_OMEGA     out = Omega~ in, Omega~ = Phi~ - Psi~ (eq. "splitting_Psi")
  *   LQGRID_OP_PHI_SOLVE out = Phi~^-1 in                     (eq. "decomposed_problem")
  *   LQGRID_OP_PRECOND   out = P_S^-1 in  (Alg. 2, S x L sweeps; Theorem 2)
- * Requires lqgrid_factor for PHI_SOLVE / PRECOND.  Enqueue only. */
+ * Or-ing LQGRID_OP_F32 into op runs the FP32 kernels of the precision form
+ * (input rounded to FP32, output widened back).  Requires lqgrid_factor for
+ * PHI_SOLVE / PRECOND.  Enqueue only. */
 typedef enum {
   LQGRID_OP_DELTA = 0,
   LQGRID_OP_XI = 1,
   LQGRID_OP_OMEGA = 2,
   LQGRID_OP_PHI_SOLVE = 3,
-  LQGRID_OP_PRECOND = 4
+  LQGRID_OP_PRECOND = 4,
+  LQGRID_OP_F32 = 16
 } lqgrid_op;
 LQGRID_API int lqgrid_apply_operator(lqgrid_ctx *ctx, int op, int outer_S, int inner_L,
                           const double *in, double *out);

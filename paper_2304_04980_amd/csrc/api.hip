@@ -1,8 +1,16 @@
 // Host side of the lqgrid C ABI: argument checks, workspace layout, and the
-// driver of Algorithm 1 (PCGM) with the Algorithm 2 preconditioner.  All
-// device work is enqueued on the caller's stream; PCG scalars stay on the
-// device and the host reads the convergence flag every `check_every`
-// iterations.
+// driver of Algorithm 1 (PCGM) with the Algorithm 2 preconditioner.
+//
+// Solve structure.  An outer FP64 loop keeps the iterate delta~ and checks
+// the true residual r = r_delta - Delta delta~ (FP64 Delta apply).  Each pass
+// solves Delta e = r / ||r|| with Algorithm 1 from e = 0 in the working
+// precision (FP64, or FP32 vectors and sweeps for the precision form, with
+// FP64 scalars and FP64 accumulation of every dot product) and adds e to
+// delta~.  In FP64 the first pass is plain PCG to the requested tolerance and
+// the loop only repeats when rounding leaves the true residual above it; in
+// FP32 the loop is iterative refinement.  All device work is enqueued on the
+// caller's stream; PCG scalars stay on the device and the host reads the
+// convergence flag every `check_every` iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,13 +31,18 @@ namespace {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int kMaxPasses = 64;     // outer refinement passes per solve
+constexpr int kOpF32 = 16;         // lqgrid_apply_operator: FP32 kernels
 
-enum Vec { kRd, kDl, kR, kD, kY, kBufA, kBufB, kBufC, kBufD, kNumVec };
+// FP64 vectors of the outer loop, then the 8 vectors of one PCG instance.
+enum OuterVec { kRd, kDl, kRt, kYt, kNumOuter };
+enum PcgVec { kX, kR, kD, kY, kBufA, kBufB, kBufC, kBufD, kNumPcg };
 
 struct Plan {
   size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Fw, Bw;
-  size_t vec[kNumVec];
-  size_t psum, pmax, scal;
+  size_t G13f, Cdnf, Cupf, Qif, QTdf, Qmf, Fwf, Bwf;
+  size_t outer[kNumOuter], p64[kNumPcg], p32[kNumPcg];
+  size_t psum, pmax, scal, scal_outer;
   int npartial;
   size_t total;
 };
@@ -60,7 +73,10 @@ Plan make_plan(const Dims& D) {
     return o;
   };
   const size_t nn = (size_t)D.n * D.n, nodes = D.nodes, NB = 2 * D.n;
+  const size_t fw = (size_t)2 * D.V * (D.K + 1) * NB * kFwRow;
+  const size_t bw = (size_t)2 * D.V * D.K * NB * kBwRow;
   P.scal = take(sizeof(Scalars));
+  P.scal_outer = take(sizeof(Scalars));
   P.G13 = take(nodes * 13 * nn * 8);
   P.Cdn = take(nodes * 5 * nn * 8);
   P.Cup = take(nodes * 5 * nn * 8);
@@ -70,16 +86,31 @@ Plan make_plan(const Dims& D) {
   P.QTd = take(nodes * nn * 8);
   P.Qm = take(nodes * nn * 8);
   P.RiBT = take(nodes * (size_t)D.m * D.n * 8);
-  P.Fw = take((size_t)2 * D.V * (D.K + 1) * NB * kFwRow * 8);
-  P.Bw = take((size_t)2 * D.V * D.K * NB * kBwRow * 8);
-  const int apply_blocks = ((D.real_nodes + 3) / 4) * ((D.Tt + 63) / 64);
+  P.Fw = take(fw * 8);
+  P.Bw = take(bw * 8);
+  P.G13f = take(nodes * 13 * nn * 4);
+  P.Cdnf = take(nodes * 5 * nn * 4);
+  P.Cupf = take(nodes * 5 * nn * 4);
+  P.Qif = take(nodes * nn * 4);
+  P.QTdf = take(nodes * nn * 4);
+  P.Qmf = take(nodes * nn * 4);
+  P.Fwf = take(fw * 4);
+  P.Bwf = take(bw * 4);
+  const int apply_blocks = padded_grid(((D.real_nodes + 3) / 4) * ((D.Tt + 63) / 64));
   P.npartial = std::max(apply_blocks, kFlatBlocks);
   P.psum = take((size_t)P.npartial * 8);
   P.pmax = take((size_t)P.npartial * 8);
-  for (int v = 0; v < kNumVec; ++v) P.vec[v] = take((size_t)D.vlen * 8);
+  for (int v = 0; v < kNumOuter; ++v) P.outer[v] = take((size_t)D.vlen * 8);
+  for (int v = 0; v < kNumPcg; ++v) P.p64[v] = take((size_t)D.vlen * 8);
+  for (int v = 0; v < kNumPcg; ++v) P.p32[v] = take((size_t)D.vlen * 4);
   P.total = off;
   return P;
 }
+
+template <typename T>
+struct PcgBufs {
+  T* v[kNumPcg];
+};
 
 }  // namespace
 
@@ -87,13 +118,19 @@ struct lqgrid_ctx {
   Dims D;
   Plan P;
   Coef C;
+  OpCoef<double> op64;
+  OpCoef<float> op32;
   hipStream_t stream;
   char* ws;
-  Scalars* sc;
-  double* vec[kNumVec];
+  Scalars* sc;        // the PCG instance
+  Scalars* sco;       // the outer loop
+  double* outer[kNumOuter];
+  PcgBufs<double> b64;
+  PcgBufs<float> b32;
   double *psum, *pmax;
   bool factored = false;
   bool qt_distinct = false;
+  int host_iter[2];   // staging for resetting the device iteration counters
   // profiling
   bool prof = false;
   long long prof_launches[4] = {0, 0, 0, 0};
@@ -103,8 +140,8 @@ struct lqgrid_ctx {
   int prof_used = 0;
   ~lqgrid_ctx() {
     for (auto& e : prof_ev) {
-      hipEventDestroy(e.first);
-      hipEventDestroy(e.second);
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
     }
   }
 };
@@ -131,12 +168,11 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
   } while (0)
 
 // Optional event timing around one launch (profiling mode only).  Events are
-// recorded without synchronising; lqgrid_profile_read resolves them.
+// recorded without synchronising and resolved after the next stream sync.
 struct ProfScope {
   lqgrid_ctx* c;
-  int k;
   int slot = -1;
-  ProfScope(lqgrid_ctx* c_, int k_) : c(c_), k(k_) {
+  ProfScope(lqgrid_ctx* c_, int k) : c(c_) {
     if (!c->prof) return;
     if (c->prof_used >= (int)c->prof_ev.size()) {
       hipEvent_t a, b;
@@ -147,14 +183,13 @@ struct ProfScope {
     }
     slot = c->prof_used++;
     c->prof_kind[slot] = k;
-    hipEventRecord(c->prof_ev[slot].first, c->stream);
+    (void)hipEventRecord(c->prof_ev[slot].first, c->stream);
   }
   ~ProfScope() {
-    if (slot >= 0) hipEventRecord(c->prof_ev[slot].second, c->stream);
+    if (slot >= 0) (void)hipEventRecord(c->prof_ev[slot].second, c->stream);
   }
 };
 
-// Fold recorded event pairs into the per-kernel totals (after a sync).
 void prof_resolve(lqgrid_ctx* c) {
   for (int e = 0; e < c->prof_used; ++e) {
     float ms = 0.f;
@@ -181,55 +216,162 @@ bool opts_valid(const lqgrid_solve_opts& o) {
          (o.precision == LQGRID_FP64 || o.precision == LQGRID_FP32_REFINE);
 }
 
+int read_scalars(lqgrid_ctx* c, const Scalars* src, Scalars* h) {
+  HIPCHECK(hipMemcpyAsync(h, src, sizeof(Scalars), hipMemcpyDeviceToHost,
+                          c->stream));
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  if (c->prof_used) prof_resolve(c);
+  return LQGRID_OK;
+}
+
+template <typename T>
+const OpCoef<T>& op_coef(const lqgrid_ctx* c);
+template <>
+const OpCoef<double>& op_coef<double>(const lqgrid_ctx* c) { return c->op64; }
+template <>
+const OpCoef<float>& op_coef<float>(const lqgrid_ctx* c) { return c->op32; }
+template <typename T>
+PcgBufs<T>& pcg_bufs(lqgrid_ctx* c);
+template <>
+PcgBufs<double>& pcg_bufs<double>(lqgrid_ctx* c) { return c->b64; }
+template <>
+PcgBufs<float>& pcg_bufs<float>(lqgrid_ctx* c) { return c->b32; }
+
 // q = P_S^-1 r by S outer x L inner NBJM sweeps (Alg. 2 with a fixed number
 // of sweeps, Theorem 2).  Returns the buffer holding the result (one of the
-// two theta buffers).
-double* precondition(lqgrid_ctx* c, const double* r, int S, int L, int check) {
+// two theta buffers of the PCG instance).
+template <typename T>
+T* precondition(lqgrid_ctx* c, const T* r, int S, int L, int check) {
   const Dims& D = c->D;
-  double* rho = c->vec[kBufA];
-  double* tau = c->vec[kBufB];
-  double* thx = c->vec[kBufC];
-  double* thy = c->vec[kBufD];
-  double* dprev = nullptr;  // delta^(s) of Alg. 2 (zero for s = 0)
+  const OpCoef<T>& C = op_coef<T>(c);
+  PcgBufs<T>& b = pcg_bufs<T>(c);
+  T* rho = b.v[kBufA];
+  T* tau = b.v[kBufB];
+  T* thx = b.v[kBufC];
+  T* thy = b.v[kBufD];
+  T* dprev = nullptr;  // delta^(s) of Alg. 2 (zero for s = 0)
   for (int s = 0; s < S; ++s) {
-    const double* rs = r;
+    const T* rs = r;
     if (s > 0) {  // r_theta^(s) = r + Xi~ delta^(s)
       ProfScope ps(c, 2);
-      xi_rhs(D, c->C, r, dprev, rho, c->sc, check, c->stream);
+      xi_rhs<T>(D, C, r, dprev, rho, c->sc, check, c->stream);
       rs = rho;
     }
-    double* th = (dprev == thx) ? thy : thx;
+    T* th = (dprev == thx) ? thy : thx;
     for (int l = 0; l < L; ++l) {
-      const double* rhs = rs;
+      const T* rhs = rs;
       if (l > 0) {  // tau = r_theta + Omega~ theta^(l)
         ProfScope ps(c, 2);
-        omega_rhs(D, c->C, rs, th, tau, c->sc, check, c->stream);
+        omega_rhs<T>(D, C, rs, th, tau, c->sc, check, c->stream);
         rhs = tau;
       }
       ProfScope ps(c, 1);
-      phi_solve(D, c->C, rhs, th, c->sc, check, c->qt_distinct ? 1 : 0,
-                c->stream);
+      phi_solve<T>(D, C, rhs, th, c->sc, check, c->qt_distinct ? 1 : 0,
+                   c->stream);
     }
     dprev = th;
   }
   return dprev;
 }
 
-// r = r_delta - Delta dl (into r), true residual norms into sc.
-void true_residual(lqgrid_ctx* c, const double* dl, double* r) {
+// Algorithm 1 on Delta x = b from x = 0 in element type T.  On entry the PCG
+// instance's r vector holds b and x is zero.  Stops when the recursively
+// updated residual satisfies ||r|| <= tol_rel ||b||, on breakdown, or after
+// max_iter iterations.  Returns a HIP status; *iters and *done report the
+// iterations taken and the device stop reason.
+template <typename T>
+int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
+             int S, int L, int* iters, int* done) {
   const Dims& D = c->D;
-  double* y = c->vec[kY];
-  delta_apply(D, c->C, dl, y, nullptr, c->sc, 0, c->stream);
-  const int np = vec_sub_norm(D, c->vec[kRd], y, r, c->psum, c->pmax, c->stream);
-  scalar_step(kModeTrue, c->psum, c->pmax, np, c->sc, 0.0, c->stream);
+  const OpCoef<T>& C = op_coef<T>(c);
+  PcgBufs<T>& b = pcg_bufs<T>(c);
+  hipStream_t s = c->stream;
+  Scalars* sc = c->sc;
+  T* r = b.v[kR];
+  T* d = b.v[kD];
+  T* y = b.v[kY];
+  T* x = b.v[kX];
+  int np = vec_norms<T>(D, r, c->psum, c->pmax, s);
+  scalar_step(kModeRd2, c->psum, c->pmax, np, sc, tol_rel, s);
+  c->host_iter[0] = 0;
+  c->host_iter[1] = max_iter;
+  HIPCHECK(hipMemcpyAsync(&sc->iter, c->host_iter, 2 * sizeof(int),
+                          hipMemcpyHostToDevice, s));
+  T* q = precondition<T>(c, r, S, L, 0);
+  np = vec_dot<T>(D, q, r, c->psum, sc, 0, s);
+  scalar_step(kModeMuInit, c->psum, nullptr, np, sc, 0.0, s);
+  vec_zero<T>(d, D.vlen, s);
+  Scalars h{};
+  for (;;) {
+    for (int k = 0; k < check_every; ++k) {
+      vec_dir<T>(D, q, d, sc, s);  // d = q + beta d (beta = 0 after init)
+      {
+        ProfScope ps(c, 0);
+        np = delta_apply<T>(D, C, d, y, c->psum, sc, 1, s);
+      }
+      scalar_step(kModeYd, c->psum, nullptr, np, sc, 0.0, s);
+      {
+        ProfScope ps(c, 3);
+        np = vec_update<T>(D, d, y, x, r, c->psum, sc, s);
+      }
+      scalar_step(kModeRr, c->psum, nullptr, np, sc, 0.0, s);
+      q = precondition<T>(c, r, S, L, 1);
+      np = vec_dot<T>(D, q, r, c->psum, sc, 1, s);
+      scalar_step(kModeMu, c->psum, nullptr, np, sc, 0.0, s);
+    }
+    HIPCHECK(hipGetLastError());
+    const int st = read_scalars(c, sc, &h);
+    if (st != LQGRID_OK) return st;
+    if (h.done != kRunning) break;
+  }
+  *iters = h.iter;
+  *done = h.done;
+  return LQGRID_OK;
 }
 
-int read_scalars(lqgrid_ctx* c, Scalars* h) {
-  HIPCHECK(hipMemcpyAsync(h, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
-                          c->stream));
-  HIPCHECK(hipStreamSynchronize(c->stream));
-  if (c->prof_used) prof_resolve(c);
+// r = r_delta - Delta dl (FP64), true residual norms into the outer scalars.
+void true_residual(lqgrid_ctx* c) {
+  const Dims& D = c->D;
+  delta_apply<double>(D, c->op64, c->outer[kDl], c->outer[kYt], nullptr, c->sco,
+                      0, c->stream);
+  const int np = vec_sub_norm(D, c->outer[kRd], c->outer[kYt], c->outer[kRt],
+                              c->psum, c->pmax, c->stream);
+  scalar_step(kModeTrue, c->psum, c->pmax, np, c->sco, 0.0, c->stream);
+}
+
+// One pass in element type T: e = PCG(Delta, r / ||r||), dl += ||r|| e.
+template <typename T>
+int refine_pass(lqgrid_ctx* c, double rnorm, double tol_rel, int max_iter,
+                const lqgrid_solve_opts& o, int* iters, int* done) {
+  PcgBufs<T>& b = pcg_bufs<T>(c);
+  vec_scale_to<T>(c->D, c->outer[kRt], 1.0 / rnorm, b.v[kR], c->stream);
+  vec_zero<T>(b.v[kX], c->D.vlen, c->stream);
+  const int st = pcg_core<T>(c, tol_rel, max_iter, o.check_every, o.outer_S,
+                             o.inner_L, iters, done);
+  if (st != LQGRID_OK) return st;
+  vec_axpy_from<T>(c->D, rnorm, b.v[kX], c->outer[kDl], c->stream);
   return LQGRID_OK;
+}
+
+// FP32 copies of the operator blocks (after assembly) and of the factors
+// (after factorisation) for the precision form.
+void make_f32_blocks(lqgrid_ctx* c, bool factors) {
+  const Dims& D = c->D;
+  const long long nn = (long long)D.n * D.n, nodes = D.nodes, NB = 2 * D.n;
+  char* w = c->ws;
+  const Plan& P = c->P;
+  auto fp = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
+  if (!factors) {
+    copy_to_float(c->C.G13, fp(P.G13f), nodes * 13 * nn, c->stream);
+    copy_to_float(c->C.Cdn, fp(P.Cdnf), nodes * 5 * nn, c->stream);
+    copy_to_float(c->C.Cup, fp(P.Cupf), nodes * 5 * nn, c->stream);
+    copy_to_float(c->C.Qi, fp(P.Qif), nodes * nn, c->stream);
+    copy_to_float(c->C.QTd, fp(P.QTdf), nodes * nn, c->stream);
+    copy_to_float(c->C.Qm, fp(P.Qmf), nodes * nn, c->stream);
+  } else {
+    copy_to_float(c->C.Fw, fp(P.Fwf), 2LL * D.V * (D.K + 1) * NB * kFwRow, c->stream);
+    copy_to_float(c->C.Bw, fp(P.Bwf), 2LL * D.V * D.K * NB * kBwRow, c->stream);
+  }
 }
 
 }  // namespace
@@ -293,29 +435,35 @@ int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ws = static_cast<char*>(workspace);
   char* w = c->ws;
+  auto dp = [&](size_t off) { return reinterpret_cast<double*>(w + off); };
+  auto fp = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
   c->sc = reinterpret_cast<Scalars*>(w + P.scal);
-  c->C.G13 = reinterpret_cast<double*>(w + P.G13);
-  c->C.Cdn = reinterpret_cast<double*>(w + P.Cdn);
-  c->C.Cup = reinterpret_cast<double*>(w + P.Cup);
-  c->C.AT5 = reinterpret_cast<double*>(w + P.AT5);
-  c->C.Qi = reinterpret_cast<double*>(w + P.Qi);
-  c->C.QTi = reinterpret_cast<double*>(w + P.QTi);
-  c->C.QTd = reinterpret_cast<double*>(w + P.QTd);
-  c->C.Qm = reinterpret_cast<double*>(w + P.Qm);
-  c->C.RiBT = reinterpret_cast<double*>(w + P.RiBT);
-  c->C.Fw = reinterpret_cast<double*>(w + P.Fw);
-  c->C.Bw = reinterpret_cast<double*>(w + P.Bw);
-  for (int v = 0; v < kNumVec; ++v)
-    c->vec[v] = reinterpret_cast<double*>(w + P.vec[v]);
-  c->psum = reinterpret_cast<double*>(w + P.psum);
-  c->pmax = reinterpret_cast<double*>(w + P.pmax);
+  c->sco = reinterpret_cast<Scalars*>(w + P.scal_outer);
+  c->C = Coef{dp(P.G13), dp(P.Cdn), dp(P.Cup), dp(P.AT5), dp(P.Qi), dp(P.QTi),
+              dp(P.QTd), dp(P.Qm), dp(P.RiBT), dp(P.Fw), dp(P.Bw)};
+  c->op64 = OpCoef<double>{c->C.G13, c->C.Cdn, c->C.Cup, c->C.Qi, c->C.QTd,
+                           c->C.Qm, c->C.Fw, c->C.Bw};
+  c->op32 = OpCoef<float>{fp(P.G13f), fp(P.Cdnf), fp(P.Cupf), fp(P.Qif),
+                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf)};
+  for (int v = 0; v < kNumOuter; ++v) c->outer[v] = dp(P.outer[v]);
+  for (int v = 0; v < kNumPcg; ++v) {
+    c->b64.v[v] = dp(P.p64[v]);
+    c->b32.v[v] = fp(P.p32[v]);
+  }
+  c->psum = dp(P.psum);
+  c->pmax = dp(P.pmax);
   clear_stale_error();
-  // zero scalars and every vector (padding entries must stay zero)
-  vec_zero(reinterpret_cast<double*>(w + P.scal), sizeof(Scalars) / 8, c->stream);
-  for (int v = 0; v < kNumVec; ++v) vec_zero(c->vec[v], D.vlen, c->stream);
+  // zero the scalars and every vector (padding entries must stay zero)
+  vec_zero<double>(dp(P.scal), (long long)(P.G13 - P.scal) / 8, c->stream);
+  for (int v = 0; v < kNumOuter; ++v) vec_zero<double>(c->outer[v], D.vlen, c->stream);
+  for (int v = 0; v < kNumPcg; ++v) {
+    vec_zero<double>(c->b64.v[v], D.vlen, c->stream);
+    vec_zero<float>(c->b32.v[v], D.vlen, c->stream);
+  }
   ProblemIn in{D.K, D.N, D.n, D.m, desc->A, desc->A_nbr, desc->B,
                desc->Q, desc->R, desc->QT};
   launch_setup(D, in, c->C, c->sc, c->stream);
+  make_f32_blocks(c, false);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     delete c;
@@ -330,12 +478,14 @@ int lqgrid_factor(lqgrid_ctx* c) {
   clear_stale_error();
   // entries never written by the factorisation (padding, N1/N2 of the last
   // block rows) must read as zero
-  vec_zero(c->C.Fw, (long long)2 * c->D.V * (c->D.K + 1) * 2 * c->D.n * kFwRow, c->stream);
-  vec_zero(c->C.Bw, (long long)2 * c->D.V * c->D.K * 2 * c->D.n * kBwRow, c->stream);
+  const long long NB = 2 * c->D.n;
+  vec_zero<double>(c->C.Fw, 2LL * c->D.V * (c->D.K + 1) * NB * kFwRow, c->stream);
+  vec_zero<double>(c->C.Bw, 2LL * c->D.V * c->D.K * NB * kBwRow, c->stream);
   launch_factor(c->D, c->C, c->sc, c->stream);
+  make_f32_blocks(c, true);
   HIPCHECK(hipGetLastError());
   Scalars h;
-  int st = read_scalars(c, &h);
+  int st = read_scalars(c, c->sc, &h);
   if (st != LQGRID_OK) return st;
   c->qt_distinct = h.qt_differs != 0;
   if (h.flag_notspd) return LQGRID_ENOTSPD;
@@ -351,7 +501,6 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
   lqgrid_solve_opts o;
   opts_fill(opts_in, &o);
   if (!opts_valid(o) || !c->factored) return LQGRID_EINVAL;
-  if (o.precision != LQGRID_FP64) return LQGRID_EUNSUPPORTED;
   const Dims& D = c->D;
   hipStream_t s = c->stream;
   clear_stale_error();
@@ -360,117 +509,66 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
   HIPCHECK(hipEventCreate(&e1));
   HIPCHECK(hipEventRecord(e0, s));
 
-  double* rd = c->vec[kRd];
-  double* dl = c->vec[kDl];
-  double* r = c->vec[kR];
-  double* d = c->vec[kD];
-  double* y = c->vec[kY];
-  Scalars* sc = c->sc;
+  // r_delta, ||r_delta||, tol^2 ||r_delta||^2 (outer scalars)
+  launch_rhs_init(D, x0, c->outer[kRd], s);
+  int np = vec_norms<double>(D, c->outer[kRd], c->psum, c->pmax, s);
+  scalar_step(kModeRd2, c->psum, c->pmax, np, c->sco, o.tol, s);
+  if (delta_init) to_internal(D, delta_init, c->outer[kDl], s);
+  else vec_zero<double>(c->outer[kDl], D.vlen, s);
 
-  // r_delta, ||r_delta||^2, tol^2 ||r_delta||^2
-  launch_rhs_init(D, x0, rd, s);
-  int np = vec_norms(D, rd, c->psum, c->pmax, s);
-  scalar_step(kModeRd2, c->psum, c->pmax, np, sc, o.tol, s);
-  // delta^(0) and r^(0) = r_delta - Delta delta^(0)
-  if (delta_init) {
-    to_internal(D, delta_init, dl, s);
-    true_residual(c, dl, r);
-  } else {
-    vec_zero(dl, D.vlen, s);
-    vec_copy(D, rd, r, s);
-  }
+  int status = LQGRID_OK, total_it = 0, passes = 0;
   Scalars h{};
-  {
-    // set iteration state
-    Scalars init{};
-    int st = read_scalars(c, &h);
+  for (;;) {
+    true_residual(c);
+    int st = read_scalars(c, c->sco, &h);
     if (st != LQGRID_OK) return st;
-    init = h;
-    init.iter = 0;
-    init.max_iter = o.max_iter;
-    init.done = kRunning;
-    HIPCHECK(hipMemcpyAsync(sc, &init, sizeof(Scalars), hipMemcpyHostToDevice, s));
-    h = init;
-  }
-  int status = LQGRID_OK;
-  int restarts = 0;
-  bool need_init = true;
-  double* q = nullptr;
-  // a start that already meets the tolerance needs no iteration
-  const bool start_converged = h.rr <= h.tol2;
-  for (; !start_converged;) {
-    if (need_init) {
-      // d^(0) = P^-1 r^(0), mu^(0) = d'r
-      q = precondition(c, r, o.outer_S, o.inner_L, 0);
-      np = vec_dot(D, q, r, c->psum, sc, 0, s);
-      scalar_step(kModeMuInit, c->psum, nullptr, np, sc, 0.0, s);
-      vec_zero(d, D.vlen, s);
-      need_init = false;
-    }
-    for (int k = 0; k < o.check_every; ++k) {
-      vec_dir(D, q, d, sc, s);  // d = q + beta d (beta = 0 after init)
-      {
-        ProfScope ps(c, 0);
-        np = delta_apply(D, c->C, d, y, c->psum, sc, 1, s);
-      }
-      scalar_step(kModeYd, c->psum, nullptr, np, sc, 0.0, s);
-      {
-        ProfScope ps(c, 3);
-        np = vec_update(D, d, y, dl, r, c->psum, sc, s);
-      }
-      scalar_step(kModeRr, c->psum, nullptr, np, sc, 0.0, s);
-      q = precondition(c, r, o.outer_S, o.inner_L, 1);
-      np = vec_dot(D, q, r, c->psum, sc, 1, s);
-      scalar_step(kModeMu, c->psum, nullptr, np, sc, 0.0, s);
-    }
-    HIPCHECK(hipGetLastError());
-    int st = read_scalars(c, &h);
-    if (st != LQGRID_OK) return st;
-    if (h.done == kRunning) continue;
-    if (h.done == kBreakdown) {
+    if (h.rr <= h.tol2) break;  // also the exact-start case (0 iterations)
+    if (!std::isfinite(h.rr)) {
       status = LQGRID_EBREAKDOWN;
       break;
     }
-    // converged by the recurrence, or out of iterations: check the true residual
-    true_residual(c, dl, r);
-    st = read_scalars(c, &h);
-    if (st != LQGRID_OK) return st;
-    if (h.rr <= h.tol2) break;
-    if (h.iter >= o.max_iter) {
+    if (total_it >= o.max_iter || passes >= kMaxPasses) {
       status = LQGRID_ENOCONV;
       break;
     }
-    // restart from the true residual
-    ++restarts;
-    Scalars fix = h;
-    fix.done = kRunning;
-    HIPCHECK(hipMemcpyAsync(sc, &fix, sizeof(Scalars), hipMemcpyHostToDevice, s));
-    need_init = true;
+    const double rnorm = std::sqrt(h.rr);
+    // relative target of this pass: the absolute tol ||r_delta|| ...
+    double tol_rel = o.tol * std::sqrt(h.rd2) / rnorm;
+    int it = 0, done = kRunning;
+    if (o.precision == LQGRID_FP32_REFINE) {
+      // ... but no tighter than FP32 vectors can resolve
+      tol_rel = std::max(tol_rel, o.inner_tol);
+      st = refine_pass<float>(c, rnorm, tol_rel, o.max_iter - total_it, o, &it, &done);
+    } else {
+      st = refine_pass<double>(c, rnorm, std::min(tol_rel, 0.5),
+                               o.max_iter - total_it, o, &it, &done);
+    }
+    if (st != LQGRID_OK) return st;
+    total_it += it;
+    ++passes;
+    if (done == kBreakdown && it <= 1) {
+      status = LQGRID_EBREAKDOWN;
+      break;
+    }
   }
-  // final true residual (already in h when converged; recompute otherwise)
-  if (status != LQGRID_OK) {
-    true_residual(c, dl, r);
-    read_scalars(c, &h);
-  }
-  to_abi(D, dl, delta, s);
-  if (x || u) recover(D, c->C, dl, x, u, s);
+  to_abi(D, c->outer[kDl], delta, s);
+  if (x || u) recover(D, c->C, c->outer[kDl], x, u, s);
   HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(hipEventSynchronize(e1));
   if (c->prof_used) prof_resolve(c);
   float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   HIPCHECK(hipGetLastError());
   if (info) {
     info->status = status;
-    info->iterations = h.iter;
-    info->refinements = 0;
-    info->restarts = restarts;
+    info->iterations = total_it;
+    info->refinements = passes;
+    info->restarts = std::max(0, passes - 1);
     info->rel_kkt_residual = h.rd2 > 0 ? std::sqrt(h.rr / h.rd2) : 0.0;
-    info->seconds = ms * 1e-3;
-    // ||r_delta||_inf = max |x0| (r_delta = col(-gamma, 0, ...))
     info->rel_res_inf = h.rdinf > 0 ? h.rinf / h.rdinf : 0.0;
+    info->seconds = ms * 1e-3;
   }
   return status;
 }
@@ -521,31 +619,36 @@ int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
   const Dims& D = c->D;
   hipStream_t s = c->stream;
   clear_stale_error();
-  double* vin = c->vec[kD];
-  double* vout = c->vec[kY];
+  const bool f32 = (op & kOpF32) != 0;
+  op &= ~kOpF32;
+  if (op < LQGRID_OP_DELTA || op > LQGRID_OP_PRECOND) return LQGRID_EINVAL;
+  if ((op == LQGRID_OP_PHI_SOLVE || op == LQGRID_OP_PRECOND) && !c->factored)
+    return LQGRID_EINVAL;
+  if (op == LQGRID_OP_PRECOND && (S < 1 || L < 1)) return LQGRID_EINVAL;
+  double* vin = c->outer[kRt];
+  double* vout = c->outer[kYt];
   to_internal(D, in, vin, s);
-  switch (op) {
-    case LQGRID_OP_DELTA:
-      delta_apply(D, c->C, vin, vout, nullptr, c->sc, 0, s);
-      break;
-    case LQGRID_OP_XI:
-      xi_rhs(D, c->C, nullptr, vin, vout, c->sc, 0, s);
-      break;
-    case LQGRID_OP_OMEGA:
-      omega_rhs(D, c->C, nullptr, vin, vout, c->sc, 0, s);
-      break;
-    case LQGRID_OP_PHI_SOLVE:
-      if (!c->factored) return LQGRID_EINVAL;
-      phi_solve(D, c->C, vin, vout, c->sc, 0, c->qt_distinct ? 1 : 0, s);
-      break;
-    case LQGRID_OP_PRECOND: {
-      if (!c->factored || S < 1 || L < 1) return LQGRID_EINVAL;
-      vout = precondition(c, vin, S, L, 0);
-      break;
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    const OpCoef<T>& C = op_coef<T>(c);
+    PcgBufs<T>& b = pcg_bufs<T>(c);
+    T* x = b.v[kD];
+    T* y = b.v[kY];
+    vec_scale_to<T>(D, vin, 1.0, x, s);
+    switch (op) {
+      case LQGRID_OP_DELTA: delta_apply<T>(D, C, x, y, nullptr, c->sc, 0, s); break;
+      case LQGRID_OP_XI: xi_rhs<T>(D, C, (const T*)nullptr, x, y, c->sc, 0, s); break;
+      case LQGRID_OP_OMEGA: omega_rhs<T>(D, C, (const T*)nullptr, x, y, c->sc, 0, s); break;
+      case LQGRID_OP_PHI_SOLVE:
+        phi_solve<T>(D, C, x, y, c->sc, 0, c->qt_distinct ? 1 : 0, s);
+        break;
+      default: y = precondition<T>(c, x, S, L, 0); break;
     }
-    default:
-      return LQGRID_EINVAL;
-  }
+    vec_zero<double>(vout, D.vlen, s);
+    vec_axpy_from<T>(D, 1.0, y, vout, s);
+  };
+  if (f32) run(float{});
+  else run(double{});
   to_abi(D, vout, out, s);
   HIPCHECK(hipGetLastError());
   return LQGRID_OK;

@@ -17,35 +17,50 @@ void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s);
 void launch_rhs_init(const Dims& D, const double* x0, double* rd,
                      hipStream_t s);
 
-// ops.hip -- every launcher returns the number of partial sums it wrote (0
-// if none).  check_done != 0 makes the kernels return at once when the
+// ops.hip (T = double or float).  delta_apply returns the number of partial
+// sums it wrote.  check_done != 0 makes the kernels return at once when the
 // device flag sc->done is set (converged iterations become no-ops).
-int delta_apply(const Dims& D, const Coef& C, const double* d, double* y,
+template <typename T>
+int delta_apply(const Dims& D, const OpCoef<T>& C, const T* d, T* y,
                 double* partial, const Scalars* sc, int check_done,
                 hipStream_t s);
-void omega_rhs(const Dims& D, const Coef& C, const double* rho,
-               const double* th, double* tau, const Scalars* sc,
-               int check_done, hipStream_t s);
-void xi_rhs(const Dims& D, const Coef& C, const double* r, const double* dl,
-            double* rho, const Scalars* sc, int check_done, hipStream_t s);
-void phi_solve(const Dims& D, const Coef& C, const double* tau, double* out,
+template <typename T>
+void omega_rhs(const Dims& D, const OpCoef<T>& C, const T* rho, const T* th,
+               T* tau, const Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void xi_rhs(const Dims& D, const OpCoef<T>& C, const T* r, const T* dl, T* rho,
+            const Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void phi_solve(const Dims& D, const OpCoef<T>& C, const T* tau, T* out,
                const Scalars* sc, int check_done, int qt_distinct,
                hipStream_t s);
+void recover(const Dims& D, const Coef& C, const double* dl, double* x,
+             double* u, hipStream_t s);
 
-// flat vector kernels over D.vlen entries
+// vec.hip: flat vector kernels over D.vlen entries
 constexpr int kFlatBlocks = 1024;
-void vec_dir(const Dims& D, const double* q, double* d, const Scalars* sc,
-             hipStream_t s);
-int vec_update(const Dims& D, const double* d, const double* y, double* dl,
-               double* r, double* partial, const Scalars* sc, hipStream_t s);
-int vec_dot(const Dims& D, const double* a, const double* b, double* partial,
+template <typename T>
+void vec_dir(const Dims& D, const T* q, T* d, const Scalars* sc, hipStream_t s);
+template <typename T>
+int vec_update(const Dims& D, const T* d, const T* y, T* x, T* r,
+               double* partial, const Scalars* sc, hipStream_t s);
+template <typename T>
+int vec_dot(const Dims& D, const T* a, const T* b, double* partial,
             const Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+int vec_norms(const Dims& D, const T* a, double* psum, double* pmax,
+              hipStream_t s);
+template <typename T>
+void vec_zero(T* a, long long len, hipStream_t s);
+template <typename T>
+void vec_scale_to(const Dims& D, const double* a, double scale, T* out,
+                  hipStream_t s);
+template <typename T>
+void vec_axpy_from(const Dims& D, double scale, const T* e, double* x,
+                   hipStream_t s);
 int vec_sub_norm(const Dims& D, const double* rd, const double* y, double* r,
                  double* psum, double* pmax, hipStream_t s);
-int vec_norms(const Dims& D, const double* a, double* psum, double* pmax,
-              hipStream_t s);
-void vec_copy(const Dims& D, const double* a, double* b, hipStream_t s);
-void vec_zero(double* a, long long len, hipStream_t s);
+void copy_to_float(const double* a, float* b, long long n, hipStream_t s);
 
 enum ScalarMode {
   kModeRd2 = 0,   // rd2 = sum, rdinf = max; tol2 = tol^2 rd2; done = 0
@@ -63,7 +78,5 @@ void scalar_step(int mode, const double* psum, const double* pmax, int np,
 void to_internal(const Dims& D, const double* abi, double* internal,
                  hipStream_t s);
 void to_abi(const Dims& D, const double* internal, double* abi, hipStream_t s);
-void recover(const Dims& D, const Coef& C, const double* dl, double* x,
-             double* u, hipStream_t s);
 
 }  // namespace lqg

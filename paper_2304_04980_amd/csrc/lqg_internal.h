@@ -72,6 +72,13 @@ struct Coef {
   double *Fw, *Bw;  // factors in the substitution layout
 };
 
+// The operator blocks the hot kernels read, in the element type of the
+// vectors they act on (FP64 arrays above, or their FP32 copies).
+template <typename T>
+struct OpCoef {
+  const T *G13, *Cdn, *Cup, *Qi, *QTd, *Qm, *Fw, *Bw;
+};
+
 // Device-resident PCG scalars.
 struct Scalars {
   double rd2;      // ||r_delta||^2
@@ -143,6 +150,21 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The 8 XCDs of the MI355X each own an L2 cache and receive workgroups
+// round-robin (hardware block b runs on XCD b % 8).  Grids are launched with
+// a multiple of 8 blocks and remapped so that each XCD processes one
+// contiguous range of logical blocks: neighbouring tiles, whose halos
+// overlap, then share an L2.  Returns the logical block (>= the real count
+// for the padding blocks, which exit).
+constexpr int kXcds = 8;
+__host__ __device__ inline int padded_grid(int nblocks) {
+  return (nblocks + kXcds - 1) / kXcds * kXcds;
+}
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, per = gridDim.x / kXcds;
+  return (b % kXcds) * per + b / kXcds;
 }
 
 __device__ __forceinline__ int uniform(int x) {

@@ -1,47 +1,46 @@
 // Hot-path kernels of one PCG iteration (Algorithm 1) and of the NBJM
-// preconditioner (Algorithm 2).
+// preconditioner (Algorithm 2), generic over the vector element type T
+// (double for the FP64 path, float for the FP32 sweeps of the precision
+// form; partial sums are always accumulated in FP64).
 //
-// Work mapping: a wavefront owns one grid node (or one super-column for the
-// block solve) and 64 consecutive time steps, one per lane.  The operator
-// blocks are time invariant, so every coefficient address is wave-uniform and
-// is read through the scalar cache into SGPRs; the vectors are time-fastest,
-// so each lane's accesses form one contiguous 512-byte segment per
-// (node, component).  The t = 0 and t = T special cases of Delta
-// (Psi_hat_0 = Q^-1, no t-1 / t+1 neighbour) are lane predicates.
+// Work mapping: a wavefront owns one grid node (or one row of a super-column
+// block row for the block solve) and 64 consecutive time steps, one per lane.
+// The operator blocks are time invariant, so every coefficient address is
+// wave-uniform; the vectors are time-fastest, so each lane's accesses form
+// one contiguous segment per (node, component).  The t = 0 and t = T special
+// cases of Delta (Psi_hat_0 = Q^-1, no t-1 / t+1 neighbour) are lane
+// predicates.
 #include "launch.h"
 
 namespace lqg {
 namespace {
 
-template <int NS>
-__device__ __forceinline__ void load_node(const double* __restrict__ v,
-                                          int p, int t, int ldt,
-                                          double (&x)[NS]) {
-  const double* b = v + (size_t)p * NS * ldt + t;
+template <int NS, typename T>
+__device__ __forceinline__ void load_node(const T* __restrict__ v, int p, int t,
+                                          int ldt, T (&x)[NS]) {
+  const T* b = v + (size_t)p * NS * ldt + t;
 #pragma unroll
   for (int c = 0; c < NS; ++c) x[c] = b[(size_t)c * ldt];
 }
-template <int NS>
-__device__ __forceinline__ void store_node(double* __restrict__ v, int p, int t,
-                                           int ldt, const double (&x)[NS]) {
-  double* b = v + (size_t)p * NS * ldt + t;
+template <int NS, typename T>
+__device__ __forceinline__ void store_node(T* __restrict__ v, int p, int t,
+                                           int ldt, const T (&x)[NS]) {
+  T* b = v + (size_t)p * NS * ldt + t;
 #pragma unroll
   for (int c = 0; c < NS; ++c) b[(size_t)c * ldt] = x[c];
 }
 // acc += M x   (M: NS x NS row-major, wave-uniform)
-template <int NS>
-__device__ __forceinline__ void mv_add(const double* __restrict__ M,
-                                       const double (&x)[NS],
-                                       double (&acc)[NS]) {
+template <int NS, typename T>
+__device__ __forceinline__ void mv_add(const T* __restrict__ M, const T (&x)[NS],
+                                       T (&acc)[NS]) {
 #pragma unroll
   for (int a = 0; a < NS; ++a)
 #pragma unroll
     for (int b = 0; b < NS; ++b) acc[a] = fma(M[a * NS + b], x[b], acc[a]);
 }
-template <int NS>
-__device__ __forceinline__ void mv_sub(const double* __restrict__ M,
-                                       const double (&x)[NS],
-                                       double (&acc)[NS]) {
+template <int NS, typename T>
+__device__ __forceinline__ void mv_sub(const T* __restrict__ M, const T (&x)[NS],
+                                       T (&acc)[NS]) {
 #pragma unroll
   for (int a = 0; a < NS; ++a)
 #pragma unroll
@@ -52,32 +51,42 @@ __device__ __forceinline__ bool is_done(const Scalars* sc, int check) {
   return check && __builtin_nontemporal_load(&sc->done) != 0;
 }
 
+// Logical block of the node-tile kernels: chunk-major, node group (4 nodes,
+// one per wavefront) fastest, remapped per XCD.  Returns false for padding.
+__device__ __forceinline__ bool node_tile(const Dims& D, int* lb, int* p, int* t) {
+  const int ngroups = (D.real_nodes + 3) / 4;
+  *lb = xcd_block();
+  if (*lb >= ngroups * ((D.Tt + kWave - 1) / kWave)) return false;
+  *p = uniform((*lb % ngroups) * 4 + (threadIdx.x >> 6));
+  *t = (*lb / ngroups) * kWave + (threadIdx.x & (kWave - 1));
+  return true;
+}
+
 // ---------------------------------------------------------------------------
-// y = Delta d, fused partial sums of y'd.
+// y = Delta d, fused partial sums of y'd (FP64).
 //   y_t(p) = Q_t^-1 d_t(p)
 //          + [t>=1] ( sum_13 G[p][k] d_t(p+o_k) - sum_5 Cdn[p][k] d_{t-1}(p+o_k) )
 //          - [t<T]  sum_5 Cup[p][k] d_{t+1}(p+o_k)
-template <int NS>
-__global__ __launch_bounds__(256) void k_delta(Dims D, Coef C,
-                                               const double* __restrict__ d,
-                                               double* __restrict__ y,
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_delta(Dims D, OpCoef<T> C,
+                                               const T* __restrict__ d,
+                                               T* __restrict__ y,
                                                double* __restrict__ partial,
                                                const Scalars* sc, int check) {
   if (is_done(sc, check)) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int p = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int t = blockIdx.y * kWave + lane;
-  const int T = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  int lb, p, t;
+  if (!node_tile(D, &lb, &p, &t)) return;
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
   const size_t nn = (size_t)NS * NS;
   double dot = 0.0;
   if (p < D.real_nodes && t < D.Tt) {
     const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-    double self[NS], acc[NS], nb[NS];
+    T self[NS], acc[NS], nb[NS];
 #pragma unroll
-    for (int a = 0; a < NS; ++a) acc[a] = 0.0;
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
     load_node<NS>(d, p, t, ldt, self);
     mv_add<NS>(C.Qi + p * nn, self, acc);
-    if (t == T) mv_add<NS>(C.QTd + p * nn, self, acc);
+    if (t == T_) mv_add<NS>(C.QTd + p * nn, self, acc);
     if (t >= 1) {
 #pragma unroll
       for (int k = 0; k < 13; ++k) {
@@ -94,7 +103,7 @@ __global__ __launch_bounds__(256) void k_delta(Dims D, Coef C,
         mv_sub<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
       }
     }
-    if (t < T) {
+    if (t < T_) {
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
         const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
@@ -105,34 +114,32 @@ __global__ __launch_bounds__(256) void k_delta(Dims D, Coef C,
     }
     store_node<NS>(y, p, t, ldt, acc);
 #pragma unroll
-    for (int a = 0; a < NS; ++a) dot = fma(acc[a], self[a], dot);
+    for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
   }
   dot = block_sum<256>(dot);
-  if (partial && threadIdx.x == 0)
-    partial[blockIdx.y * gridDim.x + blockIdx.x] = dot;
+  if (partial && threadIdx.x == 0) partial[lb] = dot;
 }
 
 // tau = rho + Omega~ theta, Omega~ = Phi~ - Psi~: minus the blocks of
 // Psi_hat_t (t >= 1) that couple different super-columns; Omega_hat_0 = 0.
-template <int NS>
-__global__ __launch_bounds__(256) void k_omega(Dims D, Coef C,
-                                               const double* __restrict__ rho,
-                                               const double* __restrict__ th,
-                                               double* __restrict__ tau,
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_omega(Dims D, OpCoef<T> C,
+                                               const T* __restrict__ rho,
+                                               const T* __restrict__ th,
+                                               T* __restrict__ tau,
                                                const Scalars* sc, int check) {
   if (is_done(sc, check)) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int p = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int t = blockIdx.y * kWave + lane;
+  int lb, p, t;
+  if (!node_tile(D, &lb, &p, &t)) return;
   const int ldt = D.ldt, K = D.K, N = D.N;
   const size_t nn = (size_t)NS * NS;
   if (p >= D.real_nodes || t >= D.Tt) return;
   const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-  double acc[NS], nb[NS];
+  T acc[NS], nb[NS];
   if (rho) load_node<NS>(rho, p, t, ldt, acc);
   else
 #pragma unroll
-    for (int a = 0; a < NS; ++a) acc[a] = 0.0;
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
   if (t >= 1) {
 #pragma unroll
     for (int k = 0; k < 13; ++k) {
@@ -148,25 +155,24 @@ __global__ __launch_bounds__(256) void k_omega(Dims D, Coef C,
 
 // rho = r + Xi~ dl, Xi~ = Psi~ - Delta:
 //   (Xi~ dl)_t(p) = [t>=1] sum_5 Cdn[p][k] dl_{t-1}(q) + [t<T] sum_5 Cup[p][k] dl_{t+1}(q)
-template <int NS>
-__global__ __launch_bounds__(256) void k_xi(Dims D, Coef C,
-                                            const double* __restrict__ r,
-                                            const double* __restrict__ dl,
-                                            double* __restrict__ rho,
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_xi(Dims D, OpCoef<T> C,
+                                            const T* __restrict__ r,
+                                            const T* __restrict__ dl,
+                                            T* __restrict__ rho,
                                             const Scalars* sc, int check) {
   if (is_done(sc, check)) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int p = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int t = blockIdx.y * kWave + lane;
-  const int T = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  int lb, p, t;
+  if (!node_tile(D, &lb, &p, &t)) return;
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
   const size_t nn = (size_t)NS * NS;
   if (p >= D.real_nodes || t >= D.Tt) return;
   const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-  double acc[NS], nb[NS];
+  T acc[NS], nb[NS];
   if (r) load_node<NS>(r, p, t, ldt, acc);
   else
 #pragma unroll
-    for (int a = 0; a < NS; ++a) acc[a] = 0.0;
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
   if (t >= 1) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(256) void k_xi(Dims D, Coef C,
       mv_add<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
     }
   }
-  if (t < T) {
+  if (t < T_) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
@@ -186,6 +192,55 @@ __global__ __launch_bounds__(256) void k_xi(Dims D, Coef C,
     }
   }
   store_node<NS>(rho, p, t, ldt, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Buffer-resource access for the block solve: a lane outside the current
+// factor class uses an out-of-range offset, whose loads return 0 and whose
+// stores are dropped, so the sweeps have no divergent branches.
+constexpr int kPre = 4;
+constexpr unsigned kOob = 0x80000000u;     // beyond every vector (< 2 GiB)
+constexpr int kRsrcWord3 = 0x00020000;     // raw buffer, 32-bit dwords
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p,
+                                                            long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)bytes, kRsrcWord3);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r,
+                                                 unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r,
+                                               unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                       double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                       float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+// Coefficient j of a factor row whose dwords are spread one per lane.
+template <typename T>
+__device__ __forceinline__ T coef(unsigned reg, int j);
+template <>
+__device__ __forceinline__ double coef<double>(unsigned reg, int j) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j + 1);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <>
+__device__ __forceinline__ float coef<float>(unsigned reg, int j) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane((int)reg, j));
 }
 
 // Forward/backward substitution with the banded block Cholesky factor of
@@ -198,101 +253,75 @@ __global__ __launch_bounds__(256) void k_xi(Dims D, Coef C,
 //   w_i     = Linv_i' z_i                  (parked in `out`)
 //   theta_i = w_i - N1_i theta_{i+1} - N2_i theta_{i+2}
 // Latency hiding: a row's 32 (16) factor coefficients of a block row are one
-// 256-byte (128-byte) coalesced vector load, lane k holding dword k; they are
-// prefetched kPre block rows ahead in a register ring and moved to scalar
-// registers with v_readlane when used, so no scalar-memory wait is tied to
-// the LDS exchange.  tau and w are prefetched the same way.  All vector
-// accesses go through buffer resources: a lane outside this factor class
-// uses an out-of-range offset, whose loads return 0 and whose stores are
-// dropped, so the loop has no divergent branches.
-constexpr int kPre = 4;
-constexpr unsigned kOob = 0x80000000u;     // beyond every vector (< 2 GiB)
-constexpr int kRsrcWord3 = 0x00020000;     // raw buffer, 32-bit dwords
-
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p,
-                                                            long long bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
-                                           (int)bytes, kRsrcWord3);
-}
-__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
-                                       double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
-}
-// Coefficient j (a double) of a row whose dwords are spread one per lane.
-__device__ __forceinline__ double coef(unsigned reg, int j) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j + 1);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-template <int NS, int R>
-__device__ __forceinline__ void sweep_row(const Dims& D, const Coef& C, int cls,
-                                          int v, int lane, int t, bool act,
-                                          __amdgpu_buffer_rsrc_t rtau,
+// coalesced vector load, lane k holding dword k; they are prefetched kPre
+// block rows ahead in a register ring and moved to scalar registers with
+// v_readlane when used, so no scalar-memory wait is tied to the LDS
+// exchange.  tau and w are prefetched the same way.
+template <typename T, int NS, int R>
+__device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
+                                          int cls, int v, int lane, int t,
+                                          bool act, __amdgpu_buffer_rsrc_t rtau,
                                           __amdgpu_buffer_rsrc_t rout,
-                                          double (*zb)[2 * NS][kWave]) {
+                                          T (*zb)[2 * NS][kWave]) {
   constexpr int NB = 2 * NS;
   constexpr int NT = R + 1;  // rows of tau that row R of z needs
+  constexpr int ES = sizeof(T);
+  constexpr int FD = kFwRow * ES / 4, BD = kBwRow * ES / 4;  // dwords per row
   const int K = D.K;
-  const unsigned istride = (unsigned)(NS * D.ldt * 8);  // bytes per block row
+  const unsigned istride = (unsigned)(NS * D.ldt * ES);  // bytes per block row
   unsigned rb[NT];  // byte offset of row c of block row 0 (node (0, 2v + c/NS))
 #pragma unroll
   for (int c = 0; c < NT; ++c)
-    rb[c] = act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * 8)
+    rb[c] = act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * ES)
                 : kOob;
-  const unsigned ro = act ? (unsigned)((((size_t)(2 * v + R / NS) * K * NS + (R % NS)) * D.ldt + t) * 8)
+  const unsigned ro = act ? (unsigned)((((size_t)(2 * v + R / NS) * K * NS + (R % NS)) * D.ldt + t) * ES)
                           : kOob;
   // this row's factor coefficients: block row i at fw + i * fstep dwords
   const size_t rows0 = ((size_t)cls * D.V + v) * K;
   const size_t frows0 = ((size_t)cls * D.V + v) * (K + 1);
-  const unsigned* fw = reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow) + lane;
-  const unsigned* bw = reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow) + (lane & 31);
-  const size_t fstep = (size_t)NB * kFwRow * 2, bstep = (size_t)NB * kBwRow * 2;
+  const unsigned* fw = reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow) + (lane % FD);
+  const unsigned* bw = reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow) + (lane % BD);
+  const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
 
   // ---------------------------------------------------------- forward
-  // Block row i uses ring slot i % kPre; loads for row i + kPre (clamped to
-  // K-1) go into the slot just consumed.  The main loop covers whole chunks
-  // of kPre rows with straight-line code, so every wait on a prefetched slot
+  // Block row i uses ring slot i % kPre; loads for row i + kPre (clamped)
+  // go into the slot just consumed.  The main loop covers whole chunks of
+  // kPre rows with straight-line code, so every wait on a prefetched slot
   // is an exact in-order vmcnt count.
-  double z1[NB], z2[NB];
+  T z1[NB], z2[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) z1[b] = z2[b] = 0.0;
+  for (int b = 0; b < NB; ++b) z1[b] = z2[b] = T(0);
   unsigned cring[kPre];
-  double tring[kPre][NT];
+  T tring[kPre][NT];
 #pragma unroll
   for (int u = 0; u < kPre; ++u) {
     cring[u] = fw[(size_t)min(u, K) * fstep];
 #pragma unroll
     for (int c = 0; c < NT; ++c)
-      tring[u][c] = buf_ld(rtau, rb[c] + (unsigned)min(u, K - 1) * istride);
+      tring[u][c] = buf_ld<T>(rtau, rb[c] + (unsigned)min(u, K - 1) * istride);
   }
   auto fstep_body = [&](int i, int s, bool has_prev) {
     const unsigned cf = cring[s];
-    double ti[NT];
+    T ti[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) ti[c] = tring[s][c];
     const int in = min(i + kPre, K);
     cring[s] = fw[(size_t)in * fstep];
     const int it = min(in, K - 1);
 #pragma unroll
-    for (int c = 0; c < NT; ++c) tring[s][c] = buf_ld(rtau, rb[c] + (unsigned)it * istride);
+    for (int c = 0; c < NT; ++c) tring[s][c] = buf_ld<T>(rtau, rb[c] + (unsigned)it * istride);
     if (has_prev) {  // w_{i-1} = row R of Linv_{i-1}' times z_{i-1}
-      double acc = 0.0;
+      T acc = T(0);
 #pragma unroll
-      for (int c = R; c < NB; ++c) acc = fma(coef(cf, 24 + c), z1[c], acc);
+      for (int c = R; c < NB; ++c) acc = fma(coef<T>(cf, 24 + c), z1[c], acc);
       buf_st(rout, ro + (unsigned)(i - 1) * istride, acc);
     }
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    T a0 = T(0), a1 = T(0), a2 = T(0);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      if (c <= R) a0 = fma(coef(cf, 16 + c), ti[c], a0);
-      a1 = fma(coef(cf, c), z1[c], a1);
-      a2 = fma(coef(cf, 8 + c), z2[c], a2);
+      if (c <= R) a0 = fma(coef<T>(cf, 16 + c), ti[c], a0);
+      a1 = fma(coef<T>(cf, c), z1[c], a1);
+      a2 = fma(coef<T>(cf, 8 + c), z2[c], a2);
     }
     zb[i & 1][R][lane] = a0 - a1 - a2;
     lds_barrier();
@@ -313,38 +342,38 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const Coef& C, int cls,
     if (i + u < K) fstep_body(i + u, (1 + u) % kPre, true);
   {  // w_{K-1}: block row K of Fw carries Linv_{K-1}'
     const unsigned cf = fw[(size_t)K * fstep];
-    double acc = 0.0;
+    T acc = T(0);
 #pragma unroll
-    for (int c = R; c < NB; ++c) acc = fma(coef(cf, 24 + c), z1[c], acc);
+    for (int c = R; c < NB; ++c) acc = fma(coef<T>(cf, 24 + c), z1[c], acc);
     buf_st(rout, ro + (unsigned)(K - 1) * istride, acc);
   }
   lds_barrier();  // every wavefront is done reading zb before it is reused
 
   // ---------------------------------------------------------- backward
-  double t1[NB], t2[NB];
+  T t1[NB], t2[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) t1[b] = t2[b] = 0.0;
+  for (int b = 0; b < NB; ++b) t1[b] = t2[b] = T(0);
   unsigned bring[kPre];
-  double wring[kPre];
+  T wring[kPre];
 #pragma unroll
   for (int u = 0; u < kPre; ++u) {
     const int iu = K - 1 - u >= 0 ? K - 1 - u : 0;
     bring[u] = bw[(size_t)iu * bstep];
-    wring[u] = buf_ld(rout, ro + (unsigned)iu * istride);
+    wring[u] = buf_ld<T>(rout, ro + (unsigned)iu * istride);
   }
   auto bstep_body = [&](int i, int s) {
     const unsigned cb = bring[s];
-    const double wi = wring[s];
+    const T wi = wring[s];
     const int in = max(i - kPre, 0);
     bring[s] = bw[(size_t)in * bstep];
-    wring[s] = buf_ld(rout, ro + (unsigned)in * istride);
-    double a1 = 0.0, a2 = 0.0;
+    wring[s] = buf_ld<T>(rout, ro + (unsigned)in * istride);
+    T a1 = T(0), a2 = T(0);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      a1 = fma(coef(cb, c), t1[c], a1);
-      a2 = fma(coef(cb, 8 + c), t2[c], a2);
+      a1 = fma(coef<T>(cb, c), t1[c], a1);
+      a2 = fma(coef<T>(cb, 8 + c), t2[c], a2);
     }
-    const double th = wi - a1 - a2;
+    const T th = wi - a1 - a2;
     buf_st(rout, ro + (unsigned)i * istride, th);
     zb[i & 1][R][lane] = th;
     lds_barrier();
@@ -365,237 +394,59 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const Coef& C, int cls,
   lds_barrier();
 }
 
-template <int NS, int R = 0>
+template <typename T, int NS, int R = 0>
 __device__ __forceinline__ void sweep_dispatch(int w, const Dims& D,
-                                               const Coef& C, int cls, int v,
-                                               int lane, int t, bool act,
+                                               const OpCoef<T>& C, int cls,
+                                               int v, int lane, int t, bool act,
                                                __amdgpu_buffer_rsrc_t rtau,
                                                __amdgpu_buffer_rsrc_t rout,
-                                               double (*zb)[2 * NS][kWave]) {
+                                               T (*zb)[2 * NS][kWave]) {
   if constexpr (R < 2 * NS) {
-    if (w == R) sweep_row<NS, R>(D, C, cls, v, lane, t, act, rtau, rout, zb);
-    else sweep_dispatch<NS, R + 1>(w, D, C, cls, v, lane, t, act, rtau, rout, zb);
+    if (w == R) sweep_row<T, NS, R>(D, C, cls, v, lane, t, act, rtau, rout, zb);
+    else sweep_dispatch<T, NS, R + 1>(w, D, C, cls, v, lane, t, act, rtau, rout, zb);
   }
 }
 
 // out = Phi~^-1 tau.  One workgroup of 2n wavefronts per (super-column v,
 // 64 time steps).  t = 0: Phi_bar_{v,0} = blkdiag(Q^-1), so theta = Q tau
 // per node.  t = T uses the second factor class when Q_T != Q.
-template <int NS>
+template <typename T, int NS>
 __global__ __launch_bounds__(2 * NS * kWave) void k_phi_solve(
-    Dims D, Coef C, const double* __restrict__ tau, double* __restrict__ out,
+    Dims D, OpCoef<T> C, const T* __restrict__ tau, T* __restrict__ out,
     const Scalars* sc, int check, int qt_distinct) {
   if (is_done(sc, check)) return;
-  __shared__ double zb[2][2 * NS][kWave];
-  const int v = blockIdx.x;
+  __shared__ T zb[2][2 * NS][kWave];
+  const int nchunks = (D.Tt + kWave - 1) / kWave;
+  const int lb = xcd_block();  // super-column major: a v's chunks share an XCD
+  if (lb >= D.V * nchunks) return;
+  const int v = lb / nchunks, chunk = lb % nchunks;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x >> 6);
-  const int t0 = blockIdx.y * kWave;
+  const int t0 = chunk * kWave;
   const int t = t0 + lane;
-  const int T = D.T;
+  const int T_ = D.T;
   const bool valid = t < D.Tt;
-  const long long bytes = D.vlen * 8;
+  const long long bytes = D.vlen * (long long)sizeof(T);
   const __amdgpu_buffer_rsrc_t rtau = make_rsrc(tau, bytes);
   const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, bytes);
-  sweep_dispatch<NS>(w, D, C, 0, v, lane, t,
-                     valid && t >= 1 && !(qt_distinct && t == T), rtau, rout, zb);
-  if (qt_distinct && t0 <= T && T < t0 + kWave)
-    sweep_dispatch<NS>(w, D, C, 1, v, lane, t, valid && t == T, rtau, rout, zb);
-  if (blockIdx.y == 0) {
+  sweep_dispatch<T, NS>(w, D, C, 0, v, lane, t,
+                        valid && t >= 1 && !(qt_distinct && t == T_), rtau, rout, zb);
+  if (qt_distinct && t0 <= T_ && T_ < t0 + kWave)
+    sweep_dispatch<T, NS>(w, D, C, 1, v, lane, t, valid && t == T_, rtau, rout, zb);
+  if (chunk == 0) {
     // t = 0 for every block row: independent n x n products, one block row
     // per lane; wavefront w computes row w of the pair
     const size_t nn = (size_t)NS * NS;
     const int h = w / NS, a = w % NS;
     for (int i = lane; i < D.K; i += kWave) {
       const int p = (2 * v + h) * D.K + i;
-      const double* Qp = C.Qm + p * nn + a * NS;
-      double acc = 0.0;
+      const T* Qp = C.Qm + p * nn + a * NS;
+      T acc = T(0);
 #pragma unroll
       for (int b = 0; b < NS; ++b)
         acc = fma(Qp[b], tau[((size_t)p * NS + b) * D.ldt], acc);
       out[((size_t)p * NS + a) * D.ldt] = acc;
     }
-  }
-}
-
-// ------------------------------------------------------------ flat vectors
-__global__ __launch_bounds__(256) void k_dir(long long n,
-                                             const double* __restrict__ q,
-                                             double* __restrict__ d,
-                                             const Scalars* sc) {
-  if (sc->done) return;
-  const double beta = sc->beta;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x)
-    d[g] = fma(beta, d[g], q[g]);
-}
-
-__global__ __launch_bounds__(256) void k_update(long long n,
-                                                const double* __restrict__ d,
-                                                const double* __restrict__ y,
-                                                double* __restrict__ dl,
-                                                double* __restrict__ r,
-                                                double* __restrict__ partial,
-                                                const Scalars* sc) {
-  if (sc->done) return;
-  const double th = sc->theta;
-  double acc = 0.0;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x) {
-    dl[g] = fma(th, d[g], dl[g]);
-    const double rn = fma(-th, y[g], r[g]);
-    r[g] = rn;
-    acc = fma(rn, rn, acc);
-  }
-  acc = block_sum<256>(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_dot(long long n,
-                                             const double* __restrict__ a,
-                                             const double* __restrict__ b,
-                                             double* __restrict__ partial,
-                                             const Scalars* sc, int check) {
-  if (is_done(sc, check)) return;
-  double acc = 0.0;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x)
-    acc = fma(a[g], b[g], acc);
-  acc = block_sum<256>(acc);
-  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
-}
-
-__global__ __launch_bounds__(256) void k_sub_norm(long long n,
-                                                  const double* __restrict__ rd,
-                                                  const double* __restrict__ y,
-                                                  double* __restrict__ r,
-                                                  double* __restrict__ psum,
-                                                  double* __restrict__ pmax) {
-  double acc = 0.0, mx = 0.0;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x) {
-    const double v = rd[g] - y[g];
-    r[g] = v;
-    acc = fma(v, v, acc);
-    mx = fmax(mx, fabs(v));
-  }
-  acc = block_sum<256>(acc);
-  mx = block_max<256>(mx);
-  if (threadIdx.x == 0) {
-    psum[blockIdx.x] = acc;
-    pmax[blockIdx.x] = mx;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_norms(long long n,
-                                               const double* __restrict__ a,
-                                               double* __restrict__ psum,
-                                               double* __restrict__ pmax) {
-  double acc = 0.0, mx = 0.0;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x) {
-    acc = fma(a[g], a[g], acc);
-    mx = fmax(mx, fabs(a[g]));
-  }
-  acc = block_sum<256>(acc);
-  mx = block_max<256>(mx);
-  if (threadIdx.x == 0) {
-    psum[blockIdx.x] = acc;
-    pmax[blockIdx.x] = mx;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_copy(long long n,
-                                              const double* __restrict__ a,
-                                              double* __restrict__ b) {
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x)
-    b[g] = a[g];
-}
-
-__global__ __launch_bounds__(256) void k_zero(long long n, double* __restrict__ a) {
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-       g += (long long)gridDim.x * blockDim.x)
-    a[g] = 0.0;
-}
-
-// Deterministic fixed-order reduction of np partials, then the scalar update
-// of Algorithm 1 selected by mode.
-__global__ __launch_bounds__(256) void k_scalar(int mode,
-                                                const double* __restrict__ psum,
-                                                const double* __restrict__ pmax,
-                                                int np, Scalars* sc, double tol) {
-  const bool gated = (mode == kModeYd || mode == kModeRr || mode == kModeMu);
-  if (gated && sc->done) return;
-  double s = 0.0, m = 0.0;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    s += psum[k];
-    if (pmax) m = fmax(m, pmax[k]);
-  }
-  s = block_sum<256>(s);
-  if (pmax) m = block_max<256>(m);
-  if (threadIdx.x != 0) return;
-  switch (mode) {
-    case kModeRd2:
-      sc->rd2 = s;
-      sc->rdinf = m;
-      sc->rr = s;     // residual of the zero start
-      sc->rinf = m;
-      sc->tol2 = tol * tol * s;
-      sc->done = kRunning;
-      break;
-    case kModeYd:
-      sc->yd = s;
-      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->mu)) sc->done = kBreakdown;
-      else sc->theta = sc->mu / s;
-      break;
-    case kModeRr:
-      sc->rr = s;
-      sc->iter += 1;
-      if (!isfinite(s)) sc->done = kBreakdown;
-      else if (s <= sc->tol2) sc->done = kConverged;
-      else if (sc->iter >= sc->max_iter) sc->done = kMaxIter;
-      break;
-    case kModeMu:
-      if (!(s > 0.0) || !isfinite(s)) {
-        sc->done = kBreakdown;
-      } else {
-        sc->beta = s / sc->mu;
-        sc->mu = s;
-      }
-      break;
-    case kModeMuInit:
-      sc->mu = s;
-      sc->beta = 0.0;
-      sc->done = (s > 0.0 && isfinite(s)) ? kRunning : kBreakdown;
-      break;
-    case kModeTrue:
-      sc->rr = s;
-      sc->rinf = m;
-      break;
-  }
-}
-
-// interface [T+1][N][K][n] -> internal [p][c][t]
-__global__ void k_to_internal(Dims D, const double* __restrict__ abi,
-                              double* __restrict__ in) {
-  const long long total = (long long)D.real_nodes * D.n * D.Tt;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-       g < total; g += (long long)gridDim.x * blockDim.x) {
-    const int t = (int)(g % D.Tt);
-    const long long pc = g / D.Tt;  // p*n + c
-    in[pc * D.ldt + t] = abi[(long long)t * D.real_nodes * D.n + pc];
-  }
-}
-__global__ void k_to_abi(Dims D, const double* __restrict__ in,
-                         double* __restrict__ abi) {
-  const long long per_t = (long long)D.real_nodes * D.n;
-  const long long total = per_t * D.Tt;
-  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-       g < total; g += (long long)gridDim.x * blockDim.x) {
-    const int t = (int)(g / per_t);
-    const long long pc = g - (long long)t * per_t;
-    abi[g] = in[pc * D.ldt + t];
   }
 }
 
@@ -607,9 +458,8 @@ __global__ __launch_bounds__(256) void k_recover(Dims D, Coef C,
                                                  const double* __restrict__ dl,
                                                  double* __restrict__ x,
                                                  double* __restrict__ u) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int p = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
-  const int t = blockIdx.y * kWave + lane;
+  int lb, p, t;
+  if (!node_tile(D, &lb, &p, &t)) return;
   const int T = D.T, ldt = D.ldt, K = D.K, N = D.N, m = D.m;
   const size_t nn = (size_t)NS * NS;
   if (p >= D.real_nodes || t >= D.Tt) return;
@@ -648,9 +498,10 @@ __global__ __launch_bounds__(256) void k_recover(Dims D, Coef C,
   }
 }
 
-inline dim3 node_grid(const Dims& D) {
-  return dim3((D.real_nodes + 3) / 4, (D.Tt + kWave - 1) / kWave);
+inline int node_blocks(const Dims& D) {
+  return ((D.real_nodes + 3) / 4) * ((D.Tt + kWave - 1) / kWave);
 }
+inline dim3 node_grid(const Dims& D) { return dim3(padded_grid(node_blocks(D))); }
 
 }  // namespace
 
@@ -663,46 +514,69 @@ inline dim3 node_grid(const Dims& D) {
     default: break;             \
   }
 
-int delta_apply(const Dims& D, const Coef& C, const double* d, double* y,
+template <typename T>
+int delta_apply(const Dims& D, const OpCoef<T>& C, const T* d, T* y,
                 double* partial, const Scalars* sc, int check_done,
                 hipStream_t s) {
   const dim3 g = node_grid(D);
-#define CALL(NS) \
-  hipLaunchKernelGGL(k_delta<NS>, g, dim3(256), 0, s, D, C, d, y, partial, sc, check_done)
+#define CALL(NS)                                                              \
+  hipLaunchKernelGGL((k_delta<T, NS>), g, dim3(256), 0, s, D, C, d, y, partial, \
+                     sc, check_done)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
-  return (int)(g.x * g.y);
+  return node_blocks(D);
 }
 
-void omega_rhs(const Dims& D, const Coef& C, const double* rho,
-               const double* th, double* tau, const Scalars* sc,
-               int check_done, hipStream_t s) {
+template <typename T>
+void omega_rhs(const Dims& D, const OpCoef<T>& C, const T* rho, const T* th,
+               T* tau, const Scalars* sc, int check_done, hipStream_t s) {
   const dim3 g = node_grid(D);
-#define CALL(NS) \
-  hipLaunchKernelGGL(k_omega<NS>, g, dim3(256), 0, s, D, C, rho, th, tau, sc, check_done)
+#define CALL(NS)                                                               \
+  hipLaunchKernelGGL((k_omega<T, NS>), g, dim3(256), 0, s, D, C, rho, th, tau, \
+                     sc, check_done)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
 }
 
-void xi_rhs(const Dims& D, const Coef& C, const double* r, const double* dl,
-            double* rho, const Scalars* sc, int check_done, hipStream_t s) {
+template <typename T>
+void xi_rhs(const Dims& D, const OpCoef<T>& C, const T* r, const T* dl, T* rho,
+            const Scalars* sc, int check_done, hipStream_t s) {
   const dim3 g = node_grid(D);
-#define CALL(NS) \
-  hipLaunchKernelGGL(k_xi<NS>, g, dim3(256), 0, s, D, C, r, dl, rho, sc, check_done)
+#define CALL(NS)                                                                 \
+  hipLaunchKernelGGL((k_xi<T, NS>), g, dim3(256), 0, s, D, C, r, dl, rho, sc, \
+                     check_done)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
 }
 
-void phi_solve(const Dims& D, const Coef& C, const double* tau, double* out,
+template <typename T>
+void phi_solve(const Dims& D, const OpCoef<T>& C, const T* tau, T* out,
                const Scalars* sc, int check_done, int qt_distinct,
                hipStream_t s) {
-  const dim3 g(D.V, (D.Tt + kWave - 1) / kWave);
-#define CALL(NS)                                                                \
-  hipLaunchKernelGGL((k_phi_solve<NS>), g, dim3(2 * NS * kWave), 0, s, D, C, tau, \
-                     out, sc, check_done, qt_distinct)
+  const dim3 g(padded_grid(D.V * ((D.Tt + kWave - 1) / kWave)));
+#define CALL(NS)                                                                   \
+  hipLaunchKernelGGL((k_phi_solve<T, NS>), g, dim3(2 * NS * kWave), 0, s, D, C, \
+                     tau, out, sc, check_done, qt_distinct)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
 }
+
+template int delta_apply<double>(const Dims&, const OpCoef<double>&, const double*,
+                                 double*, double*, const Scalars*, int, hipStream_t);
+template int delta_apply<float>(const Dims&, const OpCoef<float>&, const float*,
+                                float*, double*, const Scalars*, int, hipStream_t);
+template void omega_rhs<double>(const Dims&, const OpCoef<double>&, const double*,
+                                const double*, double*, const Scalars*, int, hipStream_t);
+template void omega_rhs<float>(const Dims&, const OpCoef<float>&, const float*,
+                               const float*, float*, const Scalars*, int, hipStream_t);
+template void xi_rhs<double>(const Dims&, const OpCoef<double>&, const double*,
+                             const double*, double*, const Scalars*, int, hipStream_t);
+template void xi_rhs<float>(const Dims&, const OpCoef<float>&, const float*,
+                            const float*, float*, const Scalars*, int, hipStream_t);
+template void phi_solve<double>(const Dims&, const OpCoef<double>&, const double*,
+                                double*, const Scalars*, int, int, hipStream_t);
+template void phi_solve<float>(const Dims&, const OpCoef<float>&, const float*,
+                               float*, const Scalars*, int, int, hipStream_t);
 
 void recover(const Dims& D, const Coef& C, const double* dl, double* x,
              double* u, hipStream_t s) {
@@ -710,55 +584,6 @@ void recover(const Dims& D, const Coef& C, const double* dl, double* x,
 #define CALL(NS) hipLaunchKernelGGL(k_recover<NS>, g, dim3(256), 0, s, D, C, dl, x, u)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
-}
-
-void vec_dir(const Dims& D, const double* q, double* d, const Scalars* sc,
-             hipStream_t s) {
-  hipLaunchKernelGGL(k_dir, dim3(kFlatBlocks), dim3(256), 0, s, D.vlen, q, d, sc);
-}
-int vec_update(const Dims& D, const double* d, const double* y, double* dl,
-               double* r, double* partial, const Scalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(kFlatBlocks), dim3(256), 0, s, D.vlen, d, y,
-                     dl, r, partial, sc);
-  return kFlatBlocks;
-}
-int vec_dot(const Dims& D, const double* a, const double* b, double* partial,
-            const Scalars* sc, int check_done, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(kFlatBlocks), dim3(256), 0, s, D.vlen, a, b,
-                     partial, sc, check_done);
-  return kFlatBlocks;
-}
-int vec_sub_norm(const Dims& D, const double* rd, const double* y, double* r,
-                 double* psum, double* pmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_norm, dim3(kFlatBlocks), dim3(256), 0, s, D.vlen, rd,
-                     y, r, psum, pmax);
-  return kFlatBlocks;
-}
-int vec_norms(const Dims& D, const double* a, double* psum, double* pmax,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_norms, dim3(kFlatBlocks), dim3(256), 0, s, D.vlen, a,
-                     psum, pmax);
-  return kFlatBlocks;
-}
-void vec_copy(const Dims& D, const double* a, double* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy, dim3(kFlatBlocks), dim3(256), 0, s, D.vlen, a, b);
-}
-void vec_zero(double* a, long long len, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero, dim3(kFlatBlocks), dim3(256), 0, s, len, a);
-}
-void scalar_step(int mode, const double* psum, const double* pmax, int np,
-                 Scalars* sc, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, mode, psum, pmax, np,
-                     sc, tol);
-}
-void to_internal(const Dims& D, const double* abi, double* internal,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_to_internal, dim3(kFlatBlocks), dim3(256), 0, s, D, abi,
-                     internal);
-}
-void to_abi(const Dims& D, const double* internal, double* abi, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_abi, dim3(kFlatBlocks), dim3(256), 0, s, D, internal,
-                     abi);
 }
 
 }  // namespace lqg

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblqgrid.so")
 OK, EINVAL, ENOTSPD, EBREAKDOWN, ENOCONV, EWORKSPACE, EHIP, EUNSUPPORTED = range(8)
 FP64, FP32_REFINE = 0, 1
 OP_DELTA, OP_XI, OP_OMEGA, OP_PHI_SOLVE, OP_PRECOND = range(5)
+OP_F32 = 16   # or-ed into an operator code: run the FP32 kernels
 PROF_DELTA, PROF_PHI_SOLVE, PROF_RHS, PROF_UPDATE = range(4)
 
 

@@ -204,3 +204,63 @@ def test_error_paths(lib, torch):
     bad[0, 0, 0] = float("nan")
     _, _, _, info = ctx.solve(bad, lqgrid.default_opts(), raise_on_error=False)
     assert info["status"] == lqgrid.EBREAKDOWN
+
+
+# ------------------------------------------------------------ precision form
+F32_CASES = [(4, 4, 20, 2, 1, 1.0), (5, 7, 150, 3, 2, 1.0), (3, 5, 64, 4, 2, 0.7),
+             (6, 1, 9, 2, 2, 1.0)]
+
+
+@pytest.mark.parametrize("case", F32_CASES, ids=[str(c) for c in F32_CASES])
+def test_fp32_operators_match_oracle(lib, torch, case):
+    """FP32 kernels of the precision form against the FP64 oracle.  Inputs and
+    coefficients are rounded to FP32 (unit roundoff u = 2^-24 ~ 6e-8); each
+    output is a sum of at most 23 n x n block products (<= 92 terms), so the
+    element-wise bound used is 1e-5 * max|ref| (~170 u, covering the
+    cancellation of terms of either sign).  Phi~^-1 adds the conditioning of
+    the 2n x 2n Cholesky blocks: 1e-4 * max|ref|."""
+    from paper_2304_04980_amd import lqgrid
+    K, N, T, n, m, qt = case
+    say("fp32 operators case", case)
+    p = make_problem(K, N, T, n, m, seed=K * 100 + N * 10 + T, qt_scale=qt)
+    ctx = lqgrid.Context(p)
+    ops = slab.SlabOperators(p)
+    v = rand_vec(p, 7)
+    vf = v.reshape(T + 1, -1)
+    checks = [
+        (lqgrid.OP_DELTA, ops.delta(vf), 1e-5),
+        (lqgrid.OP_XI, ops.xi(vf), 1e-5),
+        (lqgrid.OP_OMEGA, ops.omega(vf), 1e-5),
+        (lqgrid.OP_PHI_SOLVE, ops.phi_solve(vf), 1e-4),
+    ]
+    for op, ref, tol in checks:
+        got = ctx.apply(op | lqgrid.OP_F32, v).cpu().numpy().reshape(ref.shape)
+        err = np.abs(got - ref).max()
+        say(f"  op {op} f32: max err {err:.3e} (scale {np.abs(ref).max():.3e})")
+        assert err <= tol * np.abs(ref).max(), (op, err)
+    ref = nbjm.slab_preconditioner(ops, 2, 2)(vf)
+    got = ctx.apply(lqgrid.OP_PRECOND | lqgrid.OP_F32, v).cpu().numpy().reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("tol", [1e-8, 1e-10])
+def test_fp32_refinement_reaches_fp64_accuracy(lib, torch, tol):
+    """FP32 sweeps inside FP64 iterative refinement reach the same relative
+    KKT residual as plain FP64 PCG (checked by the oracle's FP64 residual)."""
+    from paper_2304_04980_amd import lqgrid
+    p, _ = config_problem("plain", 1)
+    ctx = lqgrid.Context(p)
+    x0 = torch.as_tensor(p.x0)
+    d64, _, _, i64 = ctx.solve(x0, lqgrid.default_opts(tol=tol))
+    d32, _, _, i32 = ctx.solve(x0, lqgrid.default_opts(tol=tol, precision=lqgrid.FP32_REFINE,
+                                                       inner_tol=1e-4))
+    ops = slab.SlabOperators(p)
+    g64 = residual.kkt_residual(ops, d64.cpu().numpy().reshape(p.T + 1, -1))
+    g32 = residual.kkt_residual(ops, d32.cpu().numpy().reshape(p.T + 1, -1))
+    say(f"  tol {tol}: fp64 {i64['iterations']} it res {g64['rel2']:.2e}; fp32+refine "
+        f"{i32['iterations']} it in {i32['refinements']} passes res {g32['rel2']:.2e}")
+    assert i32["status"] == lqgrid.OK and i32["refinements"] >= 2
+    assert g32["rel2"] <= tol * 1.01 and g64["rel2"] <= tol * 1.01
+    rel = np.linalg.norm((d32 - d64).cpu().numpy()) / np.linalg.norm(d64.cpu().numpy())
+    assert rel <= 1e-3   # both within kappa * tol of delta*
