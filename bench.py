@@ -4,9 +4,12 @@
 One step = one pass of the whole path over one synthetic problem whose arrays
 are already resident in HBM: lqgrid_setup (ingest + Schur-block assembly),
 lqgrid_factor (banded block Cholesky of every Phi_bar), lqgrid_pcg_solve
-(Algorithm 1 + Algorithm 2 preconditioner to the tolerance, true-residual
-check) and the output transpose.  value = steps / wall time of the timed
-steps (solves/s).
+(Algorithm 1 + Algorithm 2 preconditioner to the tolerance, true FP64
+residual check) and the output transpose.  Both forms run in one invocation
+on the same inputs: plain FP64 PCG, then the chosen form (default: FP32
+stencil apply and sweeps inside FP64 iterative refinement).  value = steps /
+wall time of the chosen form's timed steps (solves/s); the plain figures are
+reported beside it.
 
 Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
@@ -32,24 +35,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(p, precision_bytes=8):
+def kernel_bytes(p, w=8, qt_distinct=False):
     """Algorithmic HBM bytes of one launch of each hot kernel.
 
-    U = K N n (T+1) unknowns, w = bytes per vector element.
+    U = K N n (T+1) unknowns, w = bytes per element of the vectors and of the
+    operator / factor copies the kernels read (8: FP64, 4: FP32 sweeps).
       Delta apply: read d, write y (2 U w) + the operator blocks read once:
-                   per node 13 (G) + 5 (Cdn) + 5 (Cup) + 2 (Q^-1, Q_T^-1 - Q^-1)
-                   n x n FP64 blocks.
-      Phi solve:   read tau, write theta (2 U w) + the factors of the one
-                   interior class: V K block rows x 6 (2n)^2 FP64 + Q (t = 0).
+                   per node 13 (G) + 5 (A_hat Q^-1) + 5 (Q^-1 A_hat') + 2
+                   (Q^-1, Q_T^-1 - Q^-1) n x n blocks.
+      Phi solve:   read tau, write theta (2 U w) + the factor rows of one
+                   class: per super-column and block row, 2n forward rows of
+                   32 entries (K+1 block rows) and 2n backward rows of 16
+                   entries (K block rows), + Q per node (the t = 0 solve).
+    The parked forward-sweep result w (one write and one read of U) is not
+    algorithmic and shows up as measured traffic above these figures.
     """
     K, N, T, n = p.K, p.N, p.T, p.n
     U = K * N * n * (T + 1)
     V = (N + 1) // 2
-    w = precision_bytes
     nodes = K * N
+    ncls = 2 if qt_distinct else 1
+    factors = ncls * V * 2 * n * (32 * (K + 1) + 16 * K) * w
     return {
-        "delta": 2 * U * w + nodes * 25 * n * n * 8,
-        "phi_solve": 2 * U * w + V * K * 6 * (2 * n) ** 2 * 8 + nodes * n * n * 8,
+        "delta": 2 * U * w + nodes * 25 * n * n * w,
+        "phi_solve": 2 * U * w + factors + nodes * n * n * w,
     }
 
 
@@ -61,10 +70,16 @@ def src_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_name):
+KERNEL_NAMES = {  # rocprofv3 names of the two hot kernels per element type
+    ("delta", 8): "k_delta<double, 4>", ("delta", 4): "k_delta<float, 4>",
+    ("phi_solve", 8): "k_phi_solve<double, 4>", ("phi_solve", 4): "k_phi_solve<float, 4>",
+}
+
+
+def traffic_from_profiles(kernel, w):
     """HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and
-    WRITE_SIZE (see profiles/traffic.json), only if taken on the current
-    kernel source; else None."""
+    WRITE_SIZE (profiles/traffic.json), only if taken on the current kernel
+    source; else None."""
     path = os.path.join(PROFILE_DIR, "traffic.json")
     if not os.path.exists(path):
         return None
@@ -74,7 +89,7 @@ def traffic_from_profiles(kernel_name):
         return None
     if rec.get("src_sha") != src_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel_name)
+    k = rec.get("kernels", {}).get(KERNEL_NAMES.get((kernel, w), ""))
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -113,6 +128,81 @@ def cpu_baseline(p, tol, gpu_iters):
     }
 
 
+def make_inputs(p, torch, dev):
+    f64 = dict(dtype=torch.float64, device=dev)
+    arrays = {k: torch.as_tensor(getattr(p, k)).to(**f64).contiguous()
+              for k in ("A", "A_nbr", "B", "Q", "R", "QT")}
+    x0 = torch.as_tensor(p.x0).to(**f64).contiguous()
+    return arrays, x0
+
+
+def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
+            lqgrid):
+    """Time `steps` full passes (setup + factor + solve) of one form after
+    `warmup` untimed ones; per-kernel averages from the library's HIP events
+    on its stream over the timed steps."""
+    if precision == "fp32r":
+        opts = lqgrid.default_opts(tol=tol, precision=lqgrid.FP32_REFINE,
+                                   inner_tol=inner_tol)
+    else:
+        opts = lqgrid.default_opts(tol=tol)
+    w = 4 if precision == "fp32r" else 8
+    delta = torch.empty((p.T + 1, p.N, p.K, p.n), dtype=torch.float64,
+                        device=x0.device)
+
+    def step(profile):
+        ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=False)
+        if profile:
+            ctx.profile_enable(True)
+        ctx.factor()
+        _, _, _, info = ctx.solve(x0, opts, out=delta)
+        prof = {k: ctx.profile_read(k) for k in range(4)} if profile else None
+        ctx.close()
+        return info, prof
+
+    for s in range(warmup):
+        info, _ = step(False)
+        log(f"[{precision}] warmup {s}: {info['iterations']} it, "
+            f"res {info['rel_kkt_residual']:.2e}, {info['seconds']*1e3:.1f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    infos = [r[0] for r in runs]
+    for s, info in enumerate(infos):
+        log(f"[{precision}] step {s}: status {info['status']} {info['iterations']} it, "
+            f"{info['refinements']} passes, res {info['rel_kkt_residual']:.2e}, "
+            f"solve {info['seconds']*1e3:.1f} ms")
+    names = {0: "delta", 1: "phi_solve", 2: "rhs", 3: "update"}
+    kern = {}
+    for k, nm in names.items():
+        launches = sum(r[1][k][0] for r in runs)
+        ms = sum(r[1][k][1] for r in runs)
+        kern[nm] = {"launches": launches, "total_ms": round(ms, 3),
+                    "avg_ms": ms / launches if launches else None}
+    kb = kernel_bytes(p, w)
+    per_kernel = {}
+    for nm in ("delta", "phi_solve"):
+        if kern[nm]["avg_ms"]:
+            per_kernel[nm] = {
+                "achieved": round(kb[nm] / (kern[nm]["avg_ms"] * 1e-3) / 1e9, 1),
+                "avg_launch_ms": kern[nm]["avg_ms"], "algorithmic_bytes": kb[nm],
+                "traffic": traffic_from_profiles(nm, w)}
+    dom = max(per_kernel, key=lambda k: kern[k]["total_ms"])
+    iters = sum(i["iterations"] for i in infos) / len(infos)
+    return {
+        "value": steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+        "converged": all(i["status"] == lqgrid.OK and i["rel_kkt_residual"] <= tol
+                         for i in infos),
+        "pcg_iterations": iters,
+        "refinements": sum(i["refinements"] for i in infos) / len(infos),
+        "pcg_iters_per_s": iters * steps / elapsed,
+        "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
+        "kernels": kern, "hot": per_kernel, "dominant": dom,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,9 +211,12 @@ def main():
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "plain", "tiny", "learned"])
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32r"],
-                    help="fp32r: FP32 sweeps inside FP64 iterative refinement")
+    ap.add_argument("--precision", default="fp32r", choices=["fp64", "fp32r"],
+                    help="form reported as value (fp32r: FP32 sweeps inside FP64 "
+                         "iterative refinement); plain FP64 is always measured "
+                         "beside it unless --no-plain")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=512,
                     help="size of the plain copy used to scale PMC counters")
@@ -139,116 +232,75 @@ def main():
 
     p, tol = config_problem(args.workload, args.seed)
     dev = "cuda"
-    f64 = dict(dtype=torch.float64, device=dev)
-    arrays = {k: torch.as_tensor(getattr(p, k)).to(**f64).contiguous()
-              for k in ("A", "A_nbr", "B", "Q", "R", "QT")}
-    x0 = torch.as_tensor(p.x0).to(**f64).contiguous()
+    arrays, x0 = make_inputs(p, torch, dev)
     nbytes = lqgrid.workspace_bytes(p.K, p.N, p.T, p.n, p.m)
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-    delta = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
-    if args.precision == "fp32r":
-        opts = lqgrid.default_opts(tol=tol, precision=lqgrid.FP32_REFINE,
-                                   inner_tol=args.inner_tol)
-    else:
-        opts = lqgrid.default_opts(tol=tol)
-    wbytes = 4 if args.precision == "fp32r" else 8
     torch.cuda.synchronize()
-
-    def step(profile=False):
-        ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=False)
-        if profile:
-            ctx.profile_enable(True)
-        ctx.factor()
-        _, _, _, info = ctx.solve(x0, opts, out=delta)
-        prof = None
-        if profile:
-            prof = {k: ctx.profile_read(k) for k in range(4)}
-        ctx.close()
-        return info, prof
-
     log(f"workload {args.workload}: K={p.K} N={p.N} T={p.T} n={p.n} m={p.m} "
         f"U={p.unknowns} tol={tol}")
-    for w in range(args.warmup):
-        info, _ = step()
-        log(f"warmup {w}: {info['iterations']} it, res {info['rel_kkt_residual']:.2e}, "
-            f"{info['seconds']*1e3:.1f} ms")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos, profs = [], []
-    for s in range(args.steps):
-        info, prof = step(profile=True)
-        infos.append(info)
-        profs.append(prof)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for s, info in enumerate(infos):
-        log(f"step {s}: status {info['status']} {info['iterations']} it, "
-            f"res {info['rel_kkt_residual']:.2e}, solve {info['seconds']*1e3:.1f} ms")
-    ok = all(i["status"] == lqgrid.OK and i["rel_kkt_residual"] <= tol for i in infos)
-    iters = sum(i["iterations"] for i in infos) / len(infos)
 
-    # per-kernel averages from the live HIP events over the timed steps
-    names = {0: "delta", 1: "phi_solve", 2: "rhs", 3: "update"}
-    kern = {}
-    for k, nm in names.items():
-        launches = sum(pr[k][0] for pr in profs)
-        ms = sum(pr[k][1] for pr in profs)
-        kern[nm] = {"launches": launches, "total_ms": ms,
-                    "avg_ms": ms / launches if launches else None}
-    dom = max(("delta", "phi_solve"), key=lambda k: kern[k]["total_ms"])
-    alg = kernel_bytes(p, wbytes)[dom]
-    achieved = alg / (kern[dom]["avg_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profiles(dom)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+    plain = None
+    if not args.no_plain and args.precision != "fp64":
+        plain = measure(p, tol, arrays, x0, ws, "fp64", args.inner_tol,
+                        args.steps, args.warmup, torch, lqgrid)
+    chosen = measure(p, tol, arrays, x0, ws, args.precision, args.inner_tol,
+                     args.steps, args.warmup, torch, lqgrid)
+
+    dom = chosen["dominant"]
+    hot = chosen["hot"][dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": hot["achieved"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes": alg,
-                "avg_launch_ms": kern[dom]["avg_ms"]}
-    other = "phi_solve" if dom == "delta" else "delta"
-    if kern[other]["avg_ms"]:
-        roofline["other_kernel"] = {
-            "kernel": other,
-            "achieved": round(kernel_bytes(p, wbytes)[other] / (kern[other]["avg_ms"] * 1e-3) / 1e9, 1),
-            "avg_launch_ms": kern[other]["avg_ms"]}
+                "frac": round(hot["achieved"] / HBM_PEAK_GBS, 4),
+                "traffic": hot["traffic"], "algorithmic_bytes": hot["algorithmic_bytes"],
+                "avg_launch_ms": hot["avg_launch_ms"],
+                "other_kernels": {k: v for k, v in chosen["hot"].items() if k != dom}}
 
     # plain copy of known size: reference for scaling the PMC byte counters
     nel = args.copy_ref_mib * (1 << 20) // 8
-    a = torch.ones(nel, **f64)
+    a = torch.ones(nel, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
 
+    form = ("FP32 stencil apply and sweeps, FP64 scalars, factors and outer "
+            "refinement" if args.precision == "fp32r" else "plain FP64 PCG")
     result = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": chosen["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": chosen["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: K={p.K} N={p.N} T={p.T} n={p.n} "
-                               f"m={p.m}, {'plain FP64 PCG' if args.precision == 'fp64' else 'FP32 sweeps + FP64 refinement'}, S=L=2, tol={tol}",
+                               f"m={p.m}, {form}, S=L=2, tol={tol}",
                    "K": p.K, "N": p.N, "T": p.T, "n": p.n, "m": p.m,
                    "S": 2, "L": 2, "tol": tol, "precision": args.precision,
+                   "inner_tol": args.inner_tol if args.precision == "fp32r" else None,
                    "step": "setup+factor+pcg_solve"},
-        "converged": ok,
-        "pcg_iterations": iters,
-        "refinements": sum(i["refinements"] for i in infos) / len(infos),
-        "pcg_iters_per_s": iters * args.steps / elapsed,
-        "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
-        "kernels": kern,
+        "converged": chosen["converged"],
+        "pcg_iterations": chosen["pcg_iterations"],
+        "refinements": chosen["refinements"],
+        "pcg_iters_per_s": chosen["pcg_iters_per_s"],
+        "rel_kkt_residual": chosen["rel_kkt_residual"],
+        "kernels": chosen["kernels"],
         "roofline": roofline,
+        "plain_fp64": None if plain is None else {
+            k: plain[k] for k in ("value", "ms_per_step", "converged", "pcg_iterations",
+                                  "pcg_iters_per_s", "rel_kkt_residual", "hot")},
+        "speedup_vs_plain": None if plain is None else chosen["value"] / plain["value"],
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        result["cpu_baseline"] = cpu_baseline(p, tol, int(round(iters)))
+        result["cpu_baseline"] = cpu_baseline(p, tol, int(round(
+            plain["pcg_iterations"] if plain else chosen["pcg_iterations"])))
     print(json.dumps(result), flush=True)
 
 
