@@ -203,13 +203,91 @@ def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
     }
 
 
+def bench_batched(args, torch, lqgrid):
+    """256 problems with K, N ~ U{8..64}, T ~ U{50..200} (FP64, tol 1e-8):
+    one lqgrid_batch_solve per step, against the same problems solved one
+    after another by the single-problem path (setup + factor + solve each)."""
+    from lqgrid_synth import batched_problems, BATCHED_TOL
+    probs, tol = batched_problems(), BATCHED_TOL
+    U = sum(p.unknowns for p in probs)
+    log(f"batched workload: {len(probs)} problems, {U / 1e6:.1f} M unknowns, tol {tol}")
+    opts = lqgrid.default_opts(tol=tol)
+    b = lqgrid.Batch(probs, opts=opts)
+    for w in range(args.warmup):
+        _, infos, st = b.solve()
+        log(f"warmup {w}: status {st}, {infos[0]['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [b.solve() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    infos = runs[-1][1]
+    ok = all(r[2] == lqgrid.OK for r in runs) and all(
+        i["rel_kkt_residual"] <= tol for r in runs for i in r[1])
+    its = [i["iterations"] for i in infos]
+    del b, runs
+    torch.cuda.empty_cache()
+
+    # the same problems, one after another through the single-problem path
+    seq = None
+    if not args.no_plain:
+        f64 = dict(dtype=torch.float64, device="cuda")
+        dev = []
+        for p in probs:
+            arrays, x0 = make_inputs(p, torch, "cuda")
+            dev.append((p, arrays, x0))
+        maxb = max(lqgrid.workspace_bytes(p.K, p.N, p.T, p.n, p.m) for p in probs)
+        ws = torch.empty(maxb + 256, dtype=torch.uint8, device="cuda")
+
+        def one_pass():
+            res = []
+            for p, arrays, x0 in dev:
+                ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=True)
+                out = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
+                _, _, _, info = ctx.solve(x0, opts, out=out)
+                ctx.close()
+                res.append(info)
+            return res
+
+        one_pass()  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sinfos = one_pass()
+        torch.cuda.synchronize()
+        st = time.perf_counter() - t1
+        seq = {"value": len(probs) / st, "seconds": st,
+               "pcg_iterations_total": sum(i["iterations"] for i in sinfos),
+               "converged": all(i["status"] == lqgrid.OK for i in sinfos)}
+        log(f"sequential single-problem path: {st:.3f} s for {len(probs)} solves")
+    value = len(probs) * args.steps / elapsed
+    result = {
+        "metric": "batched solves/s to 1e-8 rel. KKT residual, 256 problems "
+                  "K,N~U{8..64} T~U{50..200}",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched: {len(probs)} problems, K,N~U{{8..64}}, "
+                               f"T~U{{50..200}}, n=4, m=2, FP64 PCG, S=L=2, tol={tol}",
+                   "problems": len(probs), "unknowns": U, "tol": tol,
+                   "step": "lqgrid_batch_solve (setup+factor+solve of all problems)"},
+        "converged": ok, "pcg_iterations_min": min(its), "pcg_iterations_max": max(its),
+        "pcg_iterations_total": sum(its),
+        "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
+        "sequential_fp64": seq,
+        "speedup_vs_sequential": None if seq is None else value / seq["value"],
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "plain", "tiny", "learned"])
+                    choices=["headline", "plain", "tiny", "learned", "batched"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="fp32r", choices=["fp64", "fp32r"],
                     help="form reported as value (fp32r: FP32 sweeps inside FP64 "
@@ -230,6 +308,8 @@ def main():
     from lqgrid_synth import config_problem
     from paper_2304_04980_amd import lqgrid
 
+    if args.workload == "batched":
+        return bench_batched(args, torch, lqgrid)
     p, tol = config_problem(args.workload, args.seed)
     dev = "cuda"
     arrays, x0 = make_inputs(p, torch, dev)

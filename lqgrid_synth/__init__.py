@@ -120,6 +120,9 @@ def config_problem(name: str, seed: int = 0) -> tuple[Problem, float]:
     return make_problem(seed=seed, **c), tol
 
 
+BATCHED_TOL = 1e-8  # tolerance of the batched workload
+
+
 def batched_dims(P: int = 256, dims_seed: int = 999):
     """K, N ~ U{8..64}, T ~ U{50..200} drawn from default_rng(dims_seed)."""
     rng = np.random.default_rng(dims_seed)

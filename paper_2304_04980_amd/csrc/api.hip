@@ -22,16 +22,12 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/lqgrid.h"
-#include "launch.h"
+#include "api_common.h"
 
 using namespace lqg;
 
 namespace {
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-constexpr int kMaxPasses = 64;     // outer refinement passes per solve
 constexpr int kOpF32 = 16;         // lqgrid_apply_operator: FP32 kernels
 
 // FP64 vectors of the outer loop, then the 8 vectors of one PCG instance.
@@ -46,23 +42,6 @@ struct Plan {
   int npartial;
   size_t total;
 };
-
-bool make_dims(const lqgrid_problem_desc* d, Dims* D) {
-  if (!d || d->K < 1 || d->N < 1 || d->T < 1 || d->n < 1 || d->m < 1) return false;
-  D->K = d->K;
-  D->N = d->N;
-  D->T = d->T;
-  D->n = d->n;
-  D->m = d->m;
-  D->V = (d->N + 1) / 2;
-  D->Npad = 2 * D->V;
-  D->Tt = d->T + 1;
-  D->ldt = (D->Tt + 15) / 16 * 16;
-  D->nodes = D->Npad * d->K;
-  D->real_nodes = d->N * d->K;
-  D->vlen = (long long)D->nodes * d->n * D->ldt;
-  return true;
-}
 
 Plan make_plan(const Dims& D) {
   Plan P{};
@@ -150,22 +129,33 @@ namespace {
 
 thread_local char g_last_error[256] = "";
 
+}  // namespace
+
+namespace lqg {
+
+bool make_dims(const lqgrid_problem_desc* d, Dims* D) {
+  if (!d || d->K < 1 || d->N < 1 || d->T < 1 || d->n < 1 || d->m < 1) return false;
+  D->K = d->K;
+  D->N = d->N;
+  D->T = d->T;
+  D->n = d->n;
+  D->m = d->m;
+  D->V = (d->N + 1) / 2;
+  D->Npad = 2 * D->V;
+  D->Tt = d->T + 1;
+  D->ldt = (D->Tt + 15) / 16 * 16;
+  D->nodes = D->Npad * d->K;
+  D->real_nodes = d->N * d->K;
+  D->vlen = (long long)D->nodes * d->n * D->ldt;
+  return true;
+}
+
 int hip_fail(hipError_t e, const char* where) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where,
                 hipGetErrorString(e), (int)e);
   return LQGRID_EHIP;
 }
 
-// Drop an error left behind by earlier, unrelated runtime calls of the
-// process (e.g. a not-ready status of a query) so that the checks below see
-// only this library's launches.
-inline void clear_stale_error() { (void)hipGetLastError(); }
-
-#define HIPCHECK(x)                                          \
-  do {                                                       \
-    hipError_t e_ = (x);                                     \
-    if (e_ != hipSuccess) return hip_fail(e_, #x);           \
-  } while (0)
 
 // Optional event timing around one launch (profiling mode only).  Events are
 // recorded without synchronising and resolved after the next stream sync.
@@ -215,6 +205,10 @@ bool opts_valid(const lqgrid_solve_opts& o) {
          o.tol > 0 && std::isfinite(o.tol) &&
          (o.precision == LQGRID_FP64 || o.precision == LQGRID_FP32_REFINE);
 }
+
+}  // namespace lqg
+
+namespace {
 
 int read_scalars(lqgrid_ctx* c, const Scalars* src, Scalars* h) {
   HIPCHECK(hipMemcpyAsync(h, src, sizeof(Scalars), hipMemcpyDeviceToHost,
@@ -571,46 +565,6 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
     info->seconds = ms * 1e-3;
   }
   return status;
-}
-
-size_t lqgrid_batch_workspace_bytes(int P, const lqgrid_problem_desc* descs,
-                                    const lqgrid_solve_opts* opts) {
-  if (P < 1 || !descs) return 0;
-  size_t tot = 0;
-  for (int p = 0; p < P; ++p) {
-    const size_t b = lqgrid_workspace_bytes(&descs[p], opts);
-    if (!b) return 0;
-    tot += align_up(b);
-  }
-  return tot;
-}
-
-int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
-                       const double* const* x0s, const lqgrid_solve_opts* opts,
-                       double* const* deltas, void* workspace,
-                       size_t workspace_bytes, void* hip_stream,
-                       lqgrid_info* infos) {
-  if (P < 1 || !descs || !x0s || !deltas) return LQGRID_EINVAL;
-  if (workspace_bytes < lqgrid_batch_workspace_bytes(P, descs, opts))
-    return LQGRID_EWORKSPACE;
-  char* w = static_cast<char*>(workspace);
-  int worst = LQGRID_OK;
-  for (int p = 0; p < P; ++p) {
-    const size_t b = align_up(lqgrid_workspace_bytes(&descs[p], opts));
-    lqgrid_ctx* c = nullptr;
-    int st = lqgrid_setup(&descs[p], w, b, hip_stream, &c);
-    if (st == LQGRID_OK) st = lqgrid_factor(c);
-    lqgrid_info inf{};
-    if (st == LQGRID_OK)
-      st = lqgrid_pcg_solve(c, x0s[p], opts, nullptr, deltas[p], nullptr,
-                            nullptr, &inf);
-    inf.status = st;
-    if (infos) infos[p] = inf;
-    if (st != LQGRID_OK) worst = st;
-    lqgrid_destroy(c);
-    w += b;
-  }
-  return worst;
 }
 
 int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,

@@ -1,0 +1,459 @@
+// Per-tile bodies of the hot-path kernels of one PCG iteration (Algorithm 1)
+// and of the NBJM preconditioner (Algorithm 2), generic over the vector
+// element type T (double for FP64, float for the FP32 sweeps of the
+// precision form; partial sums are always accumulated in FP64).  The
+// single-problem kernels (ops.hip) and the batched kernels (batch.hip) call
+// the same bodies; they differ only in how a workgroup finds its problem
+// and tile.
+//
+// Work mapping: a wavefront owns one grid node (or one row of a super-column
+// block row for the block solve) and 64 consecutive time steps, one per lane.
+// The operator blocks are time invariant, so every coefficient address is
+// wave-uniform; the vectors are time-fastest, so each lane's accesses form
+// one contiguous segment per (node, component).  The t = 0 and t = T special
+// cases of Delta (Psi_hat_0 = Q^-1, no t-1 / t+1 neighbour) are lane
+// predicates.
+#pragma once
+#include "launch.h"
+
+namespace lqg {
+namespace dev {
+
+template <int NS, typename T>
+__device__ __forceinline__ void load_node(const T* __restrict__ v, int p, int t,
+                                          int ldt, T (&x)[NS]) {
+  const T* b = v + (size_t)p * NS * ldt + t;
+#pragma unroll
+  for (int c = 0; c < NS; ++c) x[c] = b[(size_t)c * ldt];
+}
+template <int NS, typename T>
+__device__ __forceinline__ void store_node(T* __restrict__ v, int p, int t,
+                                           int ldt, const T (&x)[NS]) {
+  T* b = v + (size_t)p * NS * ldt + t;
+#pragma unroll
+  for (int c = 0; c < NS; ++c) b[(size_t)c * ldt] = x[c];
+}
+// acc += M x   (M: NS x NS row-major, wave-uniform)
+template <int NS, typename T>
+__device__ __forceinline__ void mv_add(const T* __restrict__ M, const T (&x)[NS],
+                                       T (&acc)[NS]) {
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int b = 0; b < NS; ++b) acc[a] = fma(M[a * NS + b], x[b], acc[a]);
+}
+template <int NS, typename T>
+__device__ __forceinline__ void mv_sub(const T* __restrict__ M, const T (&x)[NS],
+                                       T (&acc)[NS]) {
+#pragma unroll
+  for (int a = 0; a < NS; ++a)
+#pragma unroll
+    for (int b = 0; b < NS; ++b) acc[a] = fma(-M[a * NS + b], x[b], acc[a]);
+}
+
+__device__ __forceinline__ bool is_done(const Scalars* sc, int check) {
+  return check && __builtin_nontemporal_load(&sc->done) != 0;
+}
+
+// Node tiles: 4 nodes (one per wavefront of a 256-thread workgroup) x 64
+// consecutive time steps (one per lane).  Tile (group, chunk) covers nodes
+// 4 group .. 4 group + 3 and t = 64 chunk .. 64 chunk + 63.
+__host__ __device__ inline int node_groups(const Dims& D) {
+  return (D.real_nodes + 3) / 4;
+}
+__host__ __device__ inline int time_chunks(const Dims& D) {
+  return (D.Tt + kWave - 1) / kWave;
+}
+__device__ __forceinline__ void node_coords(int group, int chunk, int* p, int* t) {
+  *p = uniform(group * 4 + (threadIdx.x >> 6));
+  *t = chunk * kWave + (threadIdx.x & (kWave - 1));
+}
+
+// ---------------------------------------------------------------------------
+// y = Delta d on one node tile; the tile's FP64 partial sum of y'd is written
+// to *partial (when non-null) by thread 0.  Every thread of the workgroup
+// must call this (it contains a workgroup reduction).
+//   y_t(p) = Q_t^-1 d_t(p)
+//          + [t>=1] ( sum_13 G[p][k] d_t(p+o_k) - sum_5 Cdn[p][k] d_{t-1}(p+o_k) )
+//          - [t<T]  sum_5 Cup[p][k] d_{t+1}(p+o_k)
+template <typename T, int NS>
+__device__ __forceinline__ void delta_tile(const Dims& D, const OpCoef<T>& C,
+                                           const T* __restrict__ d,
+                                           T* __restrict__ y,
+                                           double* __restrict__ partial,
+                                           int group, int chunk) {
+  int p, t;
+  node_coords(group, chunk, &p, &t);
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const size_t nn = (size_t)NS * NS;
+  double dot = 0.0;
+  if (p < D.real_nodes && t < D.Tt) {
+    const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+    T self[NS], acc[NS], nb[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
+    load_node<NS>(d, p, t, ldt, self);
+    mv_add<NS>(C.Qi + p * nn, self, acc);
+    if (t == T_) mv_add<NS>(C.QTd + p * nn, self, acc);
+    if (t >= 1) {
+#pragma unroll
+      for (int k = 0; k < 13; ++k) {
+        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_node<NS>(d, jq * K + iq, t, ldt, nb);
+        mv_add<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_node<NS>(d, jq * K + iq, t - 1, ldt, nb);
+        mv_sub<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
+      }
+    }
+    if (t < T_) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_node<NS>(d, jq * K + iq, t + 1, ldt, nb);
+        mv_sub<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
+      }
+    }
+    store_node<NS>(y, p, t, ldt, acc);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
+  }
+  dot = block_sum<256>(dot);
+  if (partial && threadIdx.x == 0) *partial = dot;
+}
+
+// tau = rho + Omega~ theta on one node tile, Omega~ = Phi~ - Psi~: minus the
+// blocks of Psi_hat_t (t >= 1) that couple different super-columns;
+// Omega_hat_0 = 0.  rho may be null (zero).
+template <typename T, int NS>
+__device__ __forceinline__ void omega_tile(const Dims& D, const OpCoef<T>& C,
+                                           const T* __restrict__ rho,
+                                           const T* __restrict__ th,
+                                           T* __restrict__ tau, int group,
+                                           int chunk) {
+  int p, t;
+  node_coords(group, chunk, &p, &t);
+  const int ldt = D.ldt, K = D.K, N = D.N;
+  const size_t nn = (size_t)NS * NS;
+  if (p >= D.real_nodes || t >= D.Tt) return;
+  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  T acc[NS], nb[NS];
+  if (rho) load_node<NS>(rho, p, t, ldt, acc);
+  else
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
+  if (t >= 1) {
+#pragma unroll
+    for (int k = 0; k < 13; ++k) {
+      const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+      if ((jq >> 1) == (j >> 1)) continue;  // same super-column: inside Phi~
+      load_node<NS>(th, jq * K + iq, t, ldt, nb);
+      mv_sub<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
+    }
+  }
+  store_node<NS>(tau, p, t, ldt, acc);
+}
+
+// rho = r + Xi~ dl on one node tile, Xi~ = Psi~ - Delta:
+//   (Xi~ dl)_t(p) = [t>=1] sum_5 Cdn[p][k] dl_{t-1}(q) + [t<T] sum_5 Cup[p][k] dl_{t+1}(q)
+// r may be null (zero).
+template <typename T, int NS>
+__device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
+                                        const T* __restrict__ r,
+                                        const T* __restrict__ dl,
+                                        T* __restrict__ rho, int group,
+                                        int chunk) {
+  int p, t;
+  node_coords(group, chunk, &p, &t);
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const size_t nn = (size_t)NS * NS;
+  if (p >= D.real_nodes || t >= D.Tt) return;
+  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  T acc[NS], nb[NS];
+  if (r) load_node<NS>(r, p, t, ldt, acc);
+  else
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
+  if (t >= 1) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+      load_node<NS>(dl, jq * K + iq, t - 1, ldt, nb);
+      mv_add<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
+    }
+  }
+  if (t < T_) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+      load_node<NS>(dl, jq * K + iq, t + 1, ldt, nb);
+      mv_add<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
+    }
+  }
+  store_node<NS>(rho, p, t, ldt, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Buffer-resource access for the block solve: a lane outside the current
+// factor class uses an out-of-range offset, whose loads return 0 and whose
+// stores are dropped, so the sweeps have no divergent branches.
+constexpr int kPre = 4;
+constexpr unsigned kOob = 0x80000000u;     // beyond every vector (< 2 GiB)
+constexpr int kRsrcWord3 = 0x00020000;     // raw buffer, 32-bit dwords
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p,
+                                                            long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                           (int)bytes, kRsrcWord3);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r,
+                                                 unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r,
+                                               unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                       double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
+                                       float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+// Coefficient j of a factor row whose dwords are spread one per lane.
+template <typename T>
+__device__ __forceinline__ T coef(unsigned reg, int j);
+template <>
+__device__ __forceinline__ double coef<double>(unsigned reg, int j) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j + 1);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <>
+__device__ __forceinline__ float coef<float>(unsigned reg, int j) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane((int)reg, j));
+}
+
+// Forward/backward substitution with the banded block Cholesky factor of
+// Phi_bar_{v,cls} (eq. "decomposed_problem") for the 64 time steps of this
+// workgroup.  The 2n rows of each block row are split over 2n wavefronts,
+// one row per wavefront (R selects it at compile time), one time step per
+// lane.  Per block row the wavefronts exchange their row of z_i (theta_i)
+// through LDS with one barrier:
+//   z_i     = Linv_i tau_i - M1_i z_{i-1} - M2_i z_{i-2}
+//   w_i     = Linv_i' z_i                  (parked in `out`)
+//   theta_i = w_i - N1_i theta_{i+1} - N2_i theta_{i+2}
+// Latency hiding: a row's 32 (16) factor coefficients of a block row are one
+// coalesced vector load, lane k holding dword k; they are prefetched kPre
+// block rows ahead in a register ring and moved to scalar registers with
+// v_readlane when used, so no scalar-memory wait is tied to the LDS
+// exchange.  tau and w are prefetched the same way.
+template <typename T, int NS, int R>
+__device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
+                                          int cls, int v, int lane, int t,
+                                          bool act, __amdgpu_buffer_rsrc_t rtau,
+                                          __amdgpu_buffer_rsrc_t rout,
+                                          T (*zb)[2 * NS][kWave]) {
+  constexpr int NB = 2 * NS;
+  constexpr int NT = R + 1;  // rows of tau that row R of z needs
+  constexpr int ES = sizeof(T);
+  constexpr int FD = kFwRow * ES / 4, BD = kBwRow * ES / 4;  // dwords per row
+  const int K = D.K;
+  const unsigned istride = (unsigned)(NS * D.ldt * ES);  // bytes per block row
+  unsigned rb[NT];  // byte offset of row c of block row 0 (node (0, 2v + c/NS))
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+    rb[c] = act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * ES)
+                : kOob;
+  const unsigned ro = act ? (unsigned)((((size_t)(2 * v + R / NS) * K * NS + (R % NS)) * D.ldt + t) * ES)
+                          : kOob;
+  // this row's factor coefficients: block row i at fw + i * fstep dwords
+  const size_t rows0 = ((size_t)cls * D.V + v) * K;
+  const size_t frows0 = ((size_t)cls * D.V + v) * (K + 1);
+  const unsigned* fw = reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow) + (lane % FD);
+  const unsigned* bw = reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow) + (lane % BD);
+  const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
+
+  // ---------------------------------------------------------- forward
+  // Block row i uses ring slot i % kPre; loads for row i + kPre (clamped)
+  // go into the slot just consumed.  The main loop covers whole chunks of
+  // kPre rows with straight-line code, so every wait on a prefetched slot
+  // is an exact in-order vmcnt count.
+  T z1[NB], z2[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) z1[b] = z2[b] = T(0);
+  unsigned cring[kPre];
+  T tring[kPre][NT];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    cring[u] = fw[(size_t)min(u, K) * fstep];
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+      tring[u][c] = buf_ld<T>(rtau, rb[c] + (unsigned)min(u, K - 1) * istride);
+  }
+  auto fstep_body = [&](int i, int s, bool has_prev) {
+    const unsigned cf = cring[s];
+    T ti[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) ti[c] = tring[s][c];
+    const int in = min(i + kPre, K);
+    cring[s] = fw[(size_t)in * fstep];
+    const int it = min(in, K - 1);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) tring[s][c] = buf_ld<T>(rtau, rb[c] + (unsigned)it * istride);
+    if (has_prev) {  // w_{i-1} = row R of Linv_{i-1}' times z_{i-1}
+      T acc = T(0);
+#pragma unroll
+      for (int c = R; c < NB; ++c) acc = fma(coef<T>(cf, 24 + c), z1[c], acc);
+      buf_st(rout, ro + (unsigned)(i - 1) * istride, acc);
+    }
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c <= R) a0 = fma(coef<T>(cf, 16 + c), ti[c], a0);
+      a1 = fma(coef<T>(cf, c), z1[c], a1);
+      a2 = fma(coef<T>(cf, 8 + c), z2[c], a2);
+    }
+    zb[i & 1][R][lane] = a0 - a1 - a2;
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      z2[b] = z1[b];
+      z1[b] = zb[i & 1][b][lane];
+    }
+  };
+  fstep_body(0, 0, false);
+  int i = 1;
+  for (; i + kPre <= K; i += kPre) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) fstep_body(i + u, (1 + u) % kPre, true);
+  }
+#pragma unroll
+  for (int u = 0; u < kPre - 1; ++u)
+    if (i + u < K) fstep_body(i + u, (1 + u) % kPre, true);
+  {  // w_{K-1}: block row K of Fw carries Linv_{K-1}'
+    const unsigned cf = fw[(size_t)K * fstep];
+    T acc = T(0);
+#pragma unroll
+    for (int c = R; c < NB; ++c) acc = fma(coef<T>(cf, 24 + c), z1[c], acc);
+    buf_st(rout, ro + (unsigned)(K - 1) * istride, acc);
+  }
+  lds_barrier();  // every wavefront is done reading zb before it is reused
+
+  // ---------------------------------------------------------- backward
+  T t1[NB], t2[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) t1[b] = t2[b] = T(0);
+  unsigned bring[kPre];
+  T wring[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int iu = K - 1 - u >= 0 ? K - 1 - u : 0;
+    bring[u] = bw[(size_t)iu * bstep];
+    wring[u] = buf_ld<T>(rout, ro + (unsigned)iu * istride);
+  }
+  auto bstep_body = [&](int i, int s) {
+    const unsigned cb = bring[s];
+    const T wi = wring[s];
+    const int in = max(i - kPre, 0);
+    bring[s] = bw[(size_t)in * bstep];
+    wring[s] = buf_ld<T>(rout, ro + (unsigned)in * istride);
+    T a1 = T(0), a2 = T(0);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      a1 = fma(coef<T>(cb, c), t1[c], a1);
+      a2 = fma(coef<T>(cb, 8 + c), t2[c], a2);
+    }
+    const T th = wi - a1 - a2;
+    buf_st(rout, ro + (unsigned)i * istride, th);
+    zb[i & 1][R][lane] = th;
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      t2[b] = t1[b];
+      t1[b] = zb[i & 1][b][lane];
+    }
+  };
+  int j = K - 1;  // block row K-1-u uses slot u % kPre
+  for (; j - kPre + 1 >= 0; j -= kPre) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) bstep_body(j - u, u);
+  }
+#pragma unroll
+  for (int u = 0; u < kPre - 1; ++u)
+    if (j - u >= 0) bstep_body(j - u, u);
+  lds_barrier();
+}
+
+template <typename T, int NS, int R = 0>
+__device__ __forceinline__ void sweep_dispatch(int w, const Dims& D,
+                                               const OpCoef<T>& C, int cls,
+                                               int v, int lane, int t, bool act,
+                                               __amdgpu_buffer_rsrc_t rtau,
+                                               __amdgpu_buffer_rsrc_t rout,
+                                               T (*zb)[2 * NS][kWave]) {
+  if constexpr (R < 2 * NS) {
+    if (w == R) sweep_row<T, NS, R>(D, C, cls, v, lane, t, act, rtau, rout, zb);
+    else sweep_dispatch<T, NS, R + 1>(w, D, C, cls, v, lane, t, act, rtau, rout, zb);
+  }
+}
+
+// out = Phi~^-1 tau for super-column v and time steps 64 chunk .. 64 chunk
+// + 63, by one workgroup of 2n wavefronts (zb: the workgroup's LDS exchange
+// buffer).  t = 0: Phi_bar_{v,0} = blkdiag(Q^-1), so theta = Q tau per node.
+// t = T uses the second factor class when Q_T != Q.
+template <typename T, int NS>
+__device__ __forceinline__ void phi_tile(const Dims& D, const OpCoef<T>& C,
+                                         const T* __restrict__ tau,
+                                         T* __restrict__ out, int qt_distinct,
+                                         int v, int chunk,
+                                         T (*zb)[2 * NS][kWave]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x >> 6);
+  const int t0 = chunk * kWave;
+  const int t = t0 + lane;
+  const int T_ = D.T;
+  const bool valid = t < D.Tt;
+  const long long bytes = D.vlen * (long long)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rtau = make_rsrc(tau, bytes);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, bytes);
+  sweep_dispatch<T, NS>(w, D, C, 0, v, lane, t,
+                        valid && t >= 1 && !(qt_distinct && t == T_), rtau, rout, zb);
+  if (qt_distinct && t0 <= T_ && T_ < t0 + kWave)
+    sweep_dispatch<T, NS>(w, D, C, 1, v, lane, t, valid && t == T_, rtau, rout, zb);
+  if (chunk == 0) {
+    // t = 0 for every block row: independent n x n products, one block row
+    // per lane; wavefront w computes row w of the pair
+    const size_t nn = (size_t)NS * NS;
+    const int h = w / NS, a = w % NS;
+    for (int i = lane; i < D.K; i += kWave) {
+      const int p = (2 * v + h) * D.K + i;
+      const T* Qp = C.Qm + p * nn + a * NS;
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < NS; ++b)
+        acc = fma(Qp[b], tau[((size_t)p * NS + b) * D.ldt], acc);
+      out[((size_t)p * NS + a) * D.ldt] = acc;
+    }
+  }
+}
+
+}  // namespace dev
+}  // namespace lqg

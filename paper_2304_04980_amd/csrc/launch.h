@@ -68,8 +68,65 @@ enum ScalarMode {
   kModeRr = 2,    // rr = sum; iter++; convergence / max_iter test
   kModeMu = 3,    // mu' = sum; beta = mu'/mu; mu = mu'
   kModeMuInit = 4,// mu = sum; beta = 0; done = 0
-  kModeTrue = 5   // rr = sum, rinf = max (true residual), no state change
+  kModeTrue = 5,  // rr = sum, rinf = max (true residual), no state change
+  kModeRd2Rel = 6 // as kModeRd2 with the relative target of a refinement
+                  // pass, tol_rel = min(tol ||r_delta|| / ||r||, 1/2), taken
+                  // from the outer scalars
 };
+
+// The scalar update of Algorithm 1 selected by mode, given the reduced sum s
+// and maximum m.  `outer` (kModeRd2Rel only) holds the true residual of the
+// outer loop.
+__device__ inline void scalar_apply(int mode, double s, double m, Scalars* sc,
+                                    const Scalars* outer, double tol) {
+  switch (mode) {
+    case kModeRd2:
+    case kModeRd2Rel: {
+      double tr = tol;
+      if (mode == kModeRd2Rel)
+        tr = fmin(tol * sqrt(outer->rd2 / outer->rr), 0.5);
+      sc->rd2 = s;
+      sc->rdinf = m;
+      sc->rr = s;     // residual of the zero start
+      sc->rinf = m;
+      sc->tol2 = tr * tr * s;
+      sc->done = kRunning;
+      break;
+    }
+    case kModeYd:
+      sc->yd = s;
+      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->mu)) sc->done = kBreakdown;
+      else sc->theta = sc->mu / s;
+      break;
+    case kModeRr:
+      sc->rr = s;
+      sc->iter += 1;
+      if (!isfinite(s)) sc->done = kBreakdown;
+      else if (s <= sc->tol2) sc->done = kConverged;
+      else if (sc->iter >= sc->max_iter) sc->done = kMaxIter;
+      break;
+    case kModeMu:
+      if (!(s > 0.0) || !isfinite(s)) {
+        sc->done = kBreakdown;
+      } else {
+        sc->beta = s / sc->mu;
+        sc->mu = s;
+      }
+      break;
+    case kModeMuInit:
+      sc->mu = s;
+      sc->beta = 0.0;
+      sc->done = (s > 0.0 && isfinite(s)) ? kRunning : kBreakdown;
+      break;
+    case kModeTrue:
+      sc->rr = s;
+      sc->rinf = m;
+      break;
+  }
+}
+__host__ __device__ inline bool scalar_mode_gated(int mode) {
+  return mode == kModeYd || mode == kModeRr || mode == kModeMu;
+}
 void scalar_step(int mode, const double* psum, const double* pmax, int np,
                  Scalars* sc, double tol, hipStream_t s);
 
@@ -78,5 +135,82 @@ void scalar_step(int mode, const double* psum, const double* pmax, int np,
 void to_internal(const Dims& D, const double* abi, double* internal,
                  hipStream_t s);
 void to_abi(const Dims& D, const double* internal, double* abi, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent problems (uniform n; K, N, T, m free) in one
+// set of launches.  Every problem keeps its own coefficient blocks, factors,
+// vectors and PCG scalars; kernels walk flattened (problem, tile) work lists.
+enum BatchVec { kBX, kBR, kBD, kBY, kBA, kBB, kBC, kBE, kBRd, kBDl, kBRt, kBYt,
+                kNumBatchVec };
+struct BatchProb {
+  Dims D;
+  Coef C;
+  ProblemIn in;
+  const double* x0;
+  double* delta_out;
+  double* v[kNumBatchVec];
+  Scalars* sc;   // the PCG instance
+  Scalars* sco;  // the outer (true residual) loop
+  int first[3];  // first original work item of each kind
+  int count[3];
+};
+// One work item: problem, two coordinates (node items: node group, time
+// chunk; solve items: super-column, time chunk; flat items: element range
+// [a, b)), and the slot of its partial sums (its index in the original list).
+struct Item {
+  int prob, a, b, slot;
+};
+enum ItemKind { kItemNode = 0, kItemSolve = 1, kItemFlat = 2, kNumItemKinds = 3 };
+// Unit items of the setup kernels: problem and unit range [a, b).
+enum UnitKind { kUnitPrep = 0, kUnitStencil = 1, kUnitRhs = 2, kUnitFactor = 3,
+                kUnitAbi = 4, kNumUnitKinds = 5 };
+
+struct BatchDev {
+  BatchProb* probs;
+  int P;
+  Item* orig[kNumItemKinds];
+  int norig[kNumItemKinds];
+  Item* live[kNumItemKinds];
+  int* nlive;      // [kNumItemKinds + 1]: live items per kind, running problems
+  int* live_flag;  // [P]
+  int* live_off;   // [kNumItemKinds][P]
+  int* host_in;    // [2 P] staging: active flags, iteration limits
+  Item* units[kNumUnitKinds];
+  int nunits[kNumUnitKinds];
+  double *psum_node, *psum_flat, *pmax_flat;
+};
+
+enum FlatOp {
+  kFlatDir = 0,     // b = a + beta b
+  kFlatUpdate = 1,  // x(c) += theta a, r(d) -= theta b, partial |r|^2
+  kFlatDot = 2,     // partial a'b
+  kFlatNorms = 3,   // partial |a|^2, max |a|
+  kFlatSubNorm = 4, // c = a - b, partial |c|^2, max |c|
+  kFlatScale = 5,   // b = a / ||r|| (outer scalars)
+  kFlatAxpy = 6,    // b += ||r|| a (outer scalars)
+  kFlatZero = 7     // a = 0
+};
+
+// batch.hip launchers.  `check` selects the gate: 0 = every live item, 1 =
+// only problems whose PCG instance is still running.  grid = persistent
+// workgroup count.
+void batch_delta(const BatchDev& B, int n, int in, int out, int partial,
+                 int check, int grid, hipStream_t s);
+void batch_omega(const BatchDev& B, int n, int rho, int th, int tau, int check,
+                 int grid, hipStream_t s);
+void batch_xi(const BatchDev& B, int n, int r, int dl, int rho, int check,
+              int grid, hipStream_t s);
+void batch_solve(const BatchDev& B, int n, int tau, int out, int check,
+                 int grid, hipStream_t s);
+void batch_flat(const BatchDev& B, int op, int a, int b, int c, int d,
+                int check, int grid, hipStream_t s);
+void batch_scalar(const BatchDev& B, int mode, int kind, int outer, double tol,
+                  hipStream_t s);
+void batch_compact(const BatchDev& B, int running_only, hipStream_t s);
+void batch_set_active(const BatchDev& B, hipStream_t s);
+void batch_setup(const BatchDev& B, hipStream_t s);
+void batch_factor(const BatchDev& B, hipStream_t s);
+void batch_rhs_init(const BatchDev& B, hipStream_t s);
+void batch_to_abi(const BatchDev& B, hipStream_t s);
 
 }  // namespace lqg

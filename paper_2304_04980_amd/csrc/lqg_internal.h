@@ -95,7 +95,8 @@ struct Scalars {
   int max_iter;
   int flag_notspd; // factor pivot failure
   int qt_differs;  // QT != Q somewhere
-  int pad[3];
+  int active;      // batched form: the problem takes part in the current phase
+  int pad[2];
 };
 
 enum Done { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIter = 3 };

@@ -1,355 +1,25 @@
-// Setup kernels: ingest of the problem arrays, assembly of the time-invariant
-// blocks of Delta and of its splittings, and the banded block Cholesky
-// factorisation of every distinct Phi_bar_{v,t}.
-//
-//   Psi_hat_t = Q_t^-1 + A_hat Q^-1 A_hat' + B_hat R^-1 B_hat'   (t >= 1)
-//   Psi_hat_0 = Q_0^-1,  Xi_hat_t = -A_hat Q^-1                (eq. "structure_of_Delta")
-//   Phi_bar_{v,t} = diagonal super-block of Psi_hat_t over the column pair of v
-//                                          (eq. "constructing_Phi_Omega_matrices")
-//   each Phi_bar_{v,t} is factored by block Cholesky once per solve (Sec. IV-B)
-#include "launch.h"
+// Single-problem setup kernels (the bodies are shared with the batched
+// form): ingest and assembly, the banded block Cholesky factorisation of
+// every distinct Phi_bar_{v,t}, and the right-hand side r_delta.
+#include "bodies_setup.h"
 
 namespace lqg {
 namespace {
+using namespace dev;
 
-// Pointer to the n x n block A_hat[p, s] (p's dynamics coupling to s) in the
-// caller's [N][K][...] arrays, or nullptr when s is not p or one of its four
-// in-grid neighbours.
-__device__ const double* ahat_block(const ProblemIn& P, int ip, int jp, int is,
-                                    int js) {
-  const int K = P.K, N = P.N, n = P.n;
-  if (is < 0 || is >= K || js < 0 || js >= N) return nullptr;
-  const size_t node = (size_t)jp * K + ip;
-  const size_t nn = (size_t)n * n;
-  if (is == ip && js == jp) return P.A + node * nn;
-  int slot = -1;
-  if (is == ip && js == jp - 1) slot = 0;       // E
-  else if (is == ip && js == jp + 1) slot = 1;  // F
-  else if (is == ip - 1 && js == jp) slot = 2;  // G
-  else if (is == ip + 1 && js == jp) slot = 3;  // H
-  if (slot < 0) return nullptr;
-  return P.A_nbr + (node * 4 + slot) * nn;
-}
-
-// In-place inverse of a small SPD matrix by Gauss-Jordan with partial
-// pivoting (setup only; sizes <= 8).  Returns false on a zero pivot.
-__device__ bool small_inverse(double* M, int n) {
-  double W[kMaxM * 2 * kMaxM];
-  const int w2 = 2 * n;
-  for (int r = 0; r < n; ++r)
-    for (int c = 0; c < w2; ++c)
-      W[r * w2 + c] = c < n ? M[r * n + c] : (c - n == r ? 1.0 : 0.0);
-  for (int c = 0; c < n; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < n; ++r)
-      if (fabs(W[r * w2 + c]) > fabs(W[piv * w2 + c])) piv = r;
-    if (!(fabs(W[piv * w2 + c]) > 0.0)) return false;
-    if (piv != c)
-      for (int k = 0; k < w2; ++k) {
-        double tmp = W[c * w2 + k];
-        W[c * w2 + k] = W[piv * w2 + k];
-        W[piv * w2 + k] = tmp;
-      }
-    const double inv = 1.0 / W[c * w2 + c];
-    for (int k = 0; k < w2; ++k) W[c * w2 + k] *= inv;
-    for (int r = 0; r < n; ++r) {
-      if (r == c) continue;
-      const double f = W[r * w2 + c];
-      if (f != 0.0)
-        for (int k = 0; k < w2; ++k) W[r * w2 + k] -= f * W[c * w2 + k];
-    }
-  }
-  for (int r = 0; r < n; ++r)
-    for (int c = 0; c < n; ++c) M[r * n + c] = W[r * w2 + n + c];
-  return true;
-}
-
-// True when the small symmetric matrix M (n x n) has a Cholesky
-// factorisation with positive pivots (the problem statement requires
-// Q, Q_T, R positive definite).
-__device__ bool small_spd(const double* M, int n) {
-  double L[kMaxM * kMaxM];
-  for (int c = 0; c < n; ++c) {
-    double s = M[c * n + c];
-    for (int k = 0; k < c; ++k) s -= L[c * n + k] * L[c * n + k];
-    if (!(s > 0.0) || !isfinite(s)) return false;
-    const double dg = sqrt(s);
-    L[c * n + c] = dg;
-    for (int r = c + 1; r < n; ++r) {
-      double t = M[r * n + c];
-      for (int k = 0; k < c; ++k) t -= L[r * n + k] * L[c * n + k];
-      L[r * n + c] = t / dg;
-    }
-  }
-  return true;
-}
-
-// One thread per node: Q^-1, Q_T^-1, Q_T^-1 - Q^-1, Q, R^-1 B'.
 __global__ void k_node_prep(Dims D, ProblemIn P, Coef C, Scalars* sc) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= D.nodes) return;
-  const int n = D.n, m = D.m;
-  const size_t nn = (size_t)n * n;
-  double* Qi = C.Qi + p * nn;
-  double* QTi = C.QTi + p * nn;
-  double* QTd = C.QTd + p * nn;
-  double* Qm = C.Qm + p * nn;
-  double* RiBT = C.RiBT + (size_t)p * m * n;
-  if (p >= D.real_nodes) {  // dummy column: all zero
-    for (size_t k = 0; k < nn; ++k) Qi[k] = QTi[k] = QTd[k] = Qm[k] = 0.0;
-    for (int k = 0; k < m * n; ++k) RiBT[k] = 0.0;
-    return;
-  }
-  double q[kMaxM * kMaxM], qt[kMaxM * kMaxM], r[kMaxM * kMaxM];
-  const double* Qs = P.Q + p * nn;
-  const double* QTs = (P.QT ? P.QT : P.Q) + p * nn;
-  bool differs = false;
-  for (size_t k = 0; k < nn; ++k) {
-    q[k] = Qs[k];
-    qt[k] = QTs[k];
-    Qm[k] = Qs[k];
-    differs |= (q[k] != qt[k]);
-  }
-  for (int k = 0; k < m * m; ++k) r[k] = P.R[(size_t)p * m * m + k];
-  bool ok = small_spd(q, n) && small_spd(qt, n) && small_spd(r, m);
-  ok = small_inverse(q, n) && small_inverse(qt, n) && small_inverse(r, m) && ok;
-  for (size_t k = 0; k < nn; ++k) {
-    Qi[k] = q[k];
-    QTi[k] = qt[k];
-    QTd[k] = qt[k] - q[k];
-  }
-  const double* Bp = P.B + (size_t)p * n * m;  // [n][m]
-  for (int a = 0; a < m; ++a)
-    for (int b = 0; b < n; ++b) {
-      double s = 0.0;
-      for (int k = 0; k < m; ++k) s += r[a * m + k] * Bp[b * m + k];
-      RiBT[a * n + b] = s;
-    }
-  if (differs) atomicOr(&sc->qt_differs, 1);
-  if (!ok) atomicOr(&sc->flag_notspd, 1);
+  node_prep(D, P, C, sc, blockIdx.x * blockDim.x + threadIdx.x);
 }
-
-// One thread per (node, block): k < 13 -> G13[p][k]; 13 <= k < 18 -> the
-// 5-point blocks Cdn, AT5, Cup for k5 = k - 13.
 __global__ void k_stencil(Dims D, ProblemIn P, Coef C) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long long)D.nodes * 18) return;
-  const int p = (int)(gid / 18), k = (int)(gid % 18);
-  const int n = D.n, K = D.K, N = D.N;
-  const size_t nn = (size_t)n * n;
-  const int j = p / K, i = p - j * K;
-  double out[kMaxN * kMaxN];
-  double out2[kMaxN * kMaxN];
-  double out3[kMaxN * kMaxN];
-  for (size_t e = 0; e < nn; ++e) out[e] = out2[e] = out3[e] = 0.0;
-  const bool real = p < D.real_nodes;
-  if (k < 13) {
-    const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-    if (real && iq >= 0 && iq < K && jq >= 0 && jq < N) {
-      // sum over s in N1[p] ∩ N1[q] of A_hat[p,s] Q_s^-1 A_hat[q,s]'
-      for (int k5 = 0; k5 < 5; ++k5) {
-        const int is = i + kOff5[k5][0], js = j + kOff5[k5][1];
-        const double* Aps = ahat_block(P, i, j, is, js);
-        const double* Aqs = ahat_block(P, iq, jq, is, js);
-        if (!Aps || !Aqs) continue;
-        const double* Qis = C.Qi + ((size_t)js * K + is) * nn;
-        double tmp[kMaxN * kMaxN];
-        for (int a = 0; a < n; ++a)  // tmp = A_ps Q_s^-1
-          for (int b = 0; b < n; ++b) {
-            double s = 0.0;
-            for (int c = 0; c < n; ++c) s += Aps[a * n + c] * Qis[c * n + b];
-            tmp[a * n + b] = s;
-          }
-        for (int a = 0; a < n; ++a)  // out += tmp A_qs'
-          for (int b = 0; b < n; ++b) {
-            double s = 0.0;
-            for (int c = 0; c < n; ++c) s += tmp[a * n + c] * Aqs[b * n + c];
-            out[a * n + b] += s;
-          }
-      }
-      if (k == 0) {  // + B R^-1 B' = B (R^-1 B')
-        const double* Bp = P.B + (size_t)p * n * D.m;
-        const double* RiBT = C.RiBT + (size_t)p * D.m * n;
-        for (int a = 0; a < n; ++a)
-          for (int b = 0; b < n; ++b) {
-            double s = 0.0;
-            for (int c = 0; c < D.m; ++c) s += Bp[a * D.m + c] * RiBT[c * n + b];
-            out[a * n + b] += s;
-          }
-      }
-    }
-    double* G = C.G13 + ((size_t)p * 13 + k) * nn;
-    for (size_t e = 0; e < nn; ++e) G[e] = out[e];
-    return;
-  }
-  const int k5 = k - 13;
-  const int iq = i + kOff5[k5][0], jq = j + kOff5[k5][1];
-  if (real && iq >= 0 && iq < K && jq >= 0 && jq < N) {
-    const double* Apq = ahat_block(P, i, j, iq, jq);  // p's coupling to q
-    const double* Aqp = ahat_block(P, iq, jq, i, j);  // q's coupling to p
-    const double* Qiq = C.Qi + ((size_t)jq * K + iq) * nn;
-    const double* Qip = C.Qi + (size_t)p * nn;
-    for (int a = 0; a < n; ++a)
-      for (int b = 0; b < n; ++b) {
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += Apq[a * n + c] * Qiq[c * n + b];
-        out[a * n + b] = s;                 // Cdn = A_hat[p,q] Q_q^-1
-        out2[a * n + b] = Aqp[b * n + a];   // AT5 = A_hat[q,p]'
-      }
-    for (int a = 0; a < n; ++a)
-      for (int b = 0; b < n; ++b) {
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += Qip[a * n + c] * out2[c * n + b];
-        out3[a * n + b] = s;                // Cup = Q_p^-1 A_hat[q,p]'
-      }
-  }
-  double* Cd = C.Cdn + ((size_t)p * 5 + k5) * nn;
-  double* At = C.AT5 + ((size_t)p * 5 + k5) * nn;
-  double* Cu = C.Cup + ((size_t)p * 5 + k5) * nn;
-  for (size_t e = 0; e < nn; ++e) {
-    Cd[e] = out[e];
-    At[e] = out2[e];
-    Cu[e] = out3[e];
-  }
+  stencil(D, P, C, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
-
-// Entry (r, c) of the block Phi_bar[i, i+di] (di = 0, -1, -2) of super-column
-// v in (i, column-in-pair, component) order, class cls (0: Q^-1 on the
-// diagonal, 1: Q_T^-1).  Dummy nodes get an identity diagonal and no coupling.
-__device__ double phi_entry(const Dims& D, const Coef& C, int cls, int v,
-                            int i, int di, int r, int c) {
-  const int n = D.n, K = D.K;
-  const int h = r / n, a = r - h * n;
-  const int h2 = c / n, b = c - h2 * n;
-  const int j = 2 * v + h, j2 = 2 * v + h2;
-  const bool dummy1 = j >= D.N, dummy2 = j2 >= D.N;
-  if (dummy1 || dummy2)
-    return (di == 0 && h == h2 && a == b && dummy1) ? 1.0 : 0.0;
-  const int k = off13_index(di, h2 - h);
-  if (k < 0) return 0.0;
-  const size_t p = (size_t)j * K + i;
-  const size_t nn = (size_t)n * n;
-  double val = C.G13[(p * 13 + k) * nn + a * n + b];
-  if (di == 0 && h == h2)
-    val += (cls == 0 ? C.Qi : C.QTi)[p * nn + a * n + b];
-  return val;
-}
-
-// Banded block Cholesky of Phi_bar_{v,cls}, one 64-thread block per
-// (v, cls).  Block rows of size NB = 2n; block bandwidth 2 (Psi_hat couples
-// nodes at Manhattan distance <= 2, so rows i and i-2 meet only in the same
-// column).  For each block row i:
-//   L_{i,i-2} = Phi[i,i-2] L_{i-2,i-2}^-T
-//   L_{i,i-1} = (Phi[i,i-1] - L_{i,i-2} L_{i-1,i-2}') L_{i-1,i-1}^-T
-//   L_ii L_ii' = Phi[i,i] - L_{i,i-1} L_{i,i-1}' - L_{i,i-2} L_{i,i-2}'
+// one 64-thread workgroup per (v, cls)
 __global__ __launch_bounds__(64) void k_factor(Dims D, Coef C, Scalars* sc) {
-  const int v = blockIdx.x, cls = blockIdx.y;
-  const int NB = 2 * D.n, NB2 = NB * NB, K = D.K;
-  const int tid = threadIdx.x;
-  const int r = tid / NB, c = tid - (tid / NB) * NB;
-  const bool act = tid < NB2;
-  __shared__ double S1[64], S2[64], Dm[64], L1[64], L2[64], T1[64];
-  __shared__ double Lp1[64], Lp2[64], L1p[64], Lc[64], Li[64];
-  __shared__ int bad;
-  if (tid == 0) bad = 0;
-  if (act) Lp1[tid] = Lp2[tid] = L1p[tid] = 0.0;
-  __syncthreads();
-  for (int i = 0; i < K; ++i) {
-    if (act) {
-      Dm[tid] = phi_entry(D, C, cls, v, i, 0, r, c);
-      S1[tid] = i >= 1 ? phi_entry(D, C, cls, v, i, -1, r, c) : 0.0;
-      S2[tid] = i >= 2 ? phi_entry(D, C, cls, v, i, -2, r, c) : 0.0;
-    }
-    __syncthreads();
-    if (act) {  // L2 = S2 Linv_{i-2}'
-      double s = 0.0;
-      for (int k = 0; k < NB; ++k) s += S2[r * NB + k] * Lp2[c * NB + k];
-      L2[tid] = s;
-    }
-    __syncthreads();
-    if (act) {  // T1 = S1 - L2 L1p'
-      double s = S1[tid];
-      for (int k = 0; k < NB; ++k) s -= L2[r * NB + k] * L1p[c * NB + k];
-      T1[tid] = s;
-    }
-    __syncthreads();
-    if (act) {  // L1 = T1 Linv_{i-1}'
-      double s = 0.0;
-      for (int k = 0; k < NB; ++k) s += T1[r * NB + k] * Lp1[c * NB + k];
-      L1[tid] = s;
-    }
-    __syncthreads();
-    if (act) {  // Dm -= L1 L1' + L2 L2'
-      double s = Dm[tid];
-      for (int k = 0; k < NB; ++k)
-        s -= L1[r * NB + k] * L1[c * NB + k] + L2[r * NB + k] * L2[c * NB + k];
-      Dm[tid] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {  // Cholesky of Dm and inverse of the factor
-      for (int e = 0; e < NB2; ++e) Lc[e] = Li[e] = 0.0;
-      for (int cc = 0; cc < NB; ++cc) {
-        double s = Dm[cc * NB + cc];
-        for (int k = 0; k < cc; ++k) s -= Lc[cc * NB + k] * Lc[cc * NB + k];
-        if (!(s > 0.0) || !isfinite(s)) {
-          bad = 1;
-          s = 1.0;
-        }
-        const double dg = sqrt(s);
-        Lc[cc * NB + cc] = dg;
-        for (int rr = cc + 1; rr < NB; ++rr) {
-          double t = Dm[rr * NB + cc];
-          for (int k = 0; k < cc; ++k) t -= Lc[rr * NB + k] * Lc[cc * NB + k];
-          Lc[rr * NB + cc] = t / dg;
-        }
-      }
-      for (int cc = 0; cc < NB; ++cc) {
-        Li[cc * NB + cc] = 1.0 / Lc[cc * NB + cc];
-        for (int rr = cc + 1; rr < NB; ++rr) {
-          double t = 0.0;
-          for (int k = cc; k < rr; ++k) t += Lc[rr * NB + k] * Li[k * NB + cc];
-          Li[rr * NB + cc] = -t / Lc[rr * NB + rr];
-        }
-      }
-    }
-    __syncthreads();
-    if (act) {
-      double m1 = 0.0, m2 = 0.0, n1 = 0.0, n2 = 0.0;
-      for (int k = 0; k < NB; ++k) {
-        m1 += Li[r * NB + k] * L1[k * NB + c];    // Linv_i L_{i,i-1}
-        m2 += Li[r * NB + k] * L2[k * NB + c];    // Linv_i L_{i,i-2}
-        n1 += Lp1[k * NB + r] * L1[c * NB + k];   // Linv_{i-1}' L_{i,i-1}'
-        n2 += Lp2[k * NB + r] * L2[c * NB + k];   // Linv_{i-2}' L_{i,i-2}'
-      }
-      const size_t rows = ((size_t)cls * D.V + v) * K;         // Bw rows of (cls, v)
-      const size_t frows = ((size_t)cls * D.V + v) * (K + 1);  // Fw rows of (cls, v)
-      double* fw = C.Fw + ((frows + i) * NB + r) * kFwRow;
-      fw[c] = m1;
-      fw[8 + c] = m2;
-      fw[16 + c] = Li[r * NB + c];
-      // Linv_i' is used one block row later (w_i needs all of z_i)
-      C.Fw[((frows + i + 1) * NB + r) * kFwRow + 24 + c] = Li[c * NB + r];
-      if (i >= 1) C.Bw[((rows + i - 1) * NB + r) * kBwRow + c] = n1;
-      if (i >= 2) C.Bw[((rows + i - 2) * NB + r) * kBwRow + 8 + c] = n2;
-    }
-    __syncthreads();
-    if (act) {
-      Lp2[tid] = Lp1[tid];
-      Lp1[tid] = Li[tid];
-      L1p[tid] = L1[tid];
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && bad) atomicOr(&sc->flag_notspd, 1);
+  factor(D, C, sc, blockIdx.x, blockIdx.y);
 }
-
-// r_delta = col(-gamma_hat, 0, ..., 0) in the internal layout (the vector is
-// zeroed beforehand).
 __global__ void k_rhs_init(Dims D, const double* __restrict__ x0,
                            double* __restrict__ rd) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= D.real_nodes * D.n) return;
-  rd[(size_t)g * D.ldt] = -x0[g];  // g = p*n + c in both layouts
+  rhs_init(D, x0, rd, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace

@@ -128,8 +128,7 @@ __global__ __launch_bounds__(256) void k_scalar(int mode,
                                                 const double* __restrict__ psum,
                                                 const double* __restrict__ pmax,
                                                 int np, Scalars* sc, double tol) {
-  const bool gated = (mode == kModeYd || mode == kModeRr || mode == kModeMu);
-  if (gated && sc->done) return;
+  if (scalar_mode_gated(mode) && sc->done) return;
   double s = 0.0, m = 0.0;
   for (int k = threadIdx.x; k < np; k += blockDim.x) {
     s += psum[k];
@@ -138,45 +137,7 @@ __global__ __launch_bounds__(256) void k_scalar(int mode,
   s = block_sum<256>(s);
   if (pmax) m = block_max<256>(m);
   if (threadIdx.x != 0) return;
-  switch (mode) {
-    case kModeRd2:
-      sc->rd2 = s;
-      sc->rdinf = m;
-      sc->rr = s;     // residual of the zero start
-      sc->rinf = m;
-      sc->tol2 = tol * tol * s;
-      sc->done = kRunning;
-      break;
-    case kModeYd:
-      sc->yd = s;
-      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->mu)) sc->done = kBreakdown;
-      else sc->theta = sc->mu / s;
-      break;
-    case kModeRr:
-      sc->rr = s;
-      sc->iter += 1;
-      if (!isfinite(s)) sc->done = kBreakdown;
-      else if (s <= sc->tol2) sc->done = kConverged;
-      else if (sc->iter >= sc->max_iter) sc->done = kMaxIter;
-      break;
-    case kModeMu:
-      if (!(s > 0.0) || !isfinite(s)) {
-        sc->done = kBreakdown;
-      } else {
-        sc->beta = s / sc->mu;
-        sc->mu = s;
-      }
-      break;
-    case kModeMuInit:
-      sc->mu = s;
-      sc->beta = 0.0;
-      sc->done = (s > 0.0 && isfinite(s)) ? kRunning : kBreakdown;
-      break;
-    case kModeTrue:
-      sc->rr = s;
-      sc->rinf = m;
-      break;
-  }
+  scalar_apply(mode, s, m, sc, nullptr, tol);
 }
 
 // interface [T+1][N][K][n] -> internal [p][c][t]

@@ -252,34 +252,50 @@ class Context:
             pass
 
 
+class Batch:
+    """Inputs, outputs and workspace of one lqgrid_batch_solve, resident on
+    the device so that repeated solves time only the library call."""
+
+    def __init__(self, problems, x0s=None, device="cuda", opts: SolveOpts | None = None):
+        import torch
+        self.L = load()
+        f64 = dict(dtype=torch.float64, device=device)
+        P = len(problems)
+        self.P = P
+        self.keep = []
+        self.descs = (ProblemDesc * P)()
+        self.x0p = (c_void_p * P)()
+        self.outp = (c_void_p * P)()
+        self.outs = []
+        for k, p in enumerate(problems):
+            a = {nm: torch.as_tensor(getattr(p, nm)).to(**f64).contiguous()
+                 for nm in ("A", "A_nbr", "B", "Q", "R", "QT")}
+            self.keep.append(a)
+            self.descs[k] = problem_desc(p.K, p.N, p.T, p.n, p.m, a["A"], a["A_nbr"],
+                                         a["B"], a["Q"], a["R"], a["QT"])
+            x0 = torch.as_tensor(p.x0 if x0s is None else x0s[k]).to(**f64).contiguous()
+            self.keep.append(x0)
+            self.x0p[k] = x0.data_ptr()
+            o = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
+            self.outs.append(o)
+            self.outp[k] = o.data_ptr()
+        self.opts = default_opts() if opts is None else opts
+        self.nbytes = self.L.lqgrid_batch_workspace_bytes(P, self.descs, byref(self.opts))
+        if self.nbytes == 0:
+            raise LqgridError(EINVAL, "lqgrid_batch_workspace_bytes")
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        self.wp = (self.ws.data_ptr() + 255) // 256 * 256
+
+    def solve(self, opts: SolveOpts | None = None):
+        """Returns (list of delta tensors [T+1][N][K][n], list of info dicts,
+        overall status)."""
+        o = self.opts if opts is None else opts
+        infos = (Info * self.P)()
+        st = self.L.lqgrid_batch_solve(self.P, self.descs, self.x0p, byref(o), self.outp,
+                                       c_void_p(self.wp), self.nbytes, _stream(), infos)
+        return self.outs, [i.as_dict() for i in infos], st
+
+
 def batch_solve(problems, x0s=None, opts: SolveOpts | None = None, device="cuda"):
-    """lqgrid_batch_solve over a list of problems sharing n and m."""
-    import torch
-    L = load()
-    f64 = dict(dtype=torch.float64, device=device)
-    keep = []
-    descs = (ProblemDesc * len(problems))()
-    x0p = (c_void_p * len(problems))()
-    outp = (c_void_p * len(problems))()
-    outs = []
-    for k, p in enumerate(problems):
-        a = {nm: torch.as_tensor(getattr(p, nm)).to(**f64).contiguous()
-             for nm in ("A", "A_nbr", "B", "Q", "R", "QT")}
-        keep.append(a)
-        descs[k] = problem_desc(p.K, p.N, p.T, p.n, p.m, a["A"], a["A_nbr"],
-                                a["B"], a["Q"], a["R"], a["QT"])
-        x0 = torch.as_tensor(p.x0 if x0s is None else x0s[k]).to(**f64).contiguous()
-        keep.append(x0)
-        x0p[k] = x0.data_ptr()
-        o = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
-        outs.append(o)
-        outp[k] = o.data_ptr()
-    if opts is None:
-        opts = default_opts()
-    nbytes = L.lqgrid_batch_workspace_bytes(len(problems), descs, byref(opts))
-    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-    wp = (ws.data_ptr() + 255) // 256 * 256
-    infos = (Info * len(problems))()
-    st = L.lqgrid_batch_solve(len(problems), descs, x0p, byref(opts), outp,
-                              c_void_p(wp), nbytes, _stream(), infos)
-    return outs, [i.as_dict() for i in infos], st
+    """lqgrid_batch_solve over a list of problems sharing n."""
+    return Batch(problems, x0s, device, opts).solve()

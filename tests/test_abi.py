@@ -85,3 +85,31 @@ def test_null_context_and_status_strings():
     for s in range(8):
         assert len(L.lqgrid_status_string(s)) > 0
     L.lqgrid_destroy(None)
+
+
+def test_batch_rejects_bad_arguments_without_gpu():
+    L = lqgrid.load()
+    descs = (lqgrid.ProblemDesc * 3)(_desc(n=4, m=2), _desc(K=7, N=3, T=70, n=4, m=1),
+                                     _desc(K=1, N=1, T=1, n=4, m=2))
+    ws = L.lqgrid_batch_workspace_bytes(3, descs, None)
+    assert ws > 0
+    # the batch workspace covers at least each problem's single-problem vectors
+    assert ws > L.lqgrid_workspace_bytes(ctypes.byref(descs[1]), None) // 4
+    assert L.lqgrid_batch_workspace_bytes(0, descs, None) == 0
+    bad = (lqgrid.ProblemDesc * 2)(_desc(n=4), _desc(K=0, n=4))
+    assert L.lqgrid_batch_workspace_bytes(2, bad, None) == 0
+    ptrs = (ctypes.c_void_p * 3)(8, 8, 8)
+    infos = (lqgrid.Info * 3)()
+
+    def call(P, d, opts, nbytes=ws, wp=256):
+        return L.lqgrid_batch_solve(P, d, ptrs, ctypes.byref(opts), ptrs,
+                                    ctypes.c_void_p(wp), nbytes, None, infos)
+
+    assert call(0, descs, lqgrid.default_opts()) == lqgrid.EINVAL
+    assert call(3, descs, lqgrid.default_opts(inner_L=3)) == lqgrid.EINVAL
+    assert call(3, descs, lqgrid.default_opts(precision=lqgrid.FP32_REFINE)) == \
+        lqgrid.EUNSUPPORTED
+    mixed = (lqgrid.ProblemDesc * 2)(_desc(n=4), _desc(n=2))
+    assert call(2, mixed, lqgrid.default_opts()) == lqgrid.EUNSUPPORTED
+    assert call(3, descs, lqgrid.default_opts(), nbytes=ws - 1) == lqgrid.EWORKSPACE
+    assert call(3, descs, lqgrid.default_opts(), wp=264) == lqgrid.EWORKSPACE
