@@ -29,47 +29,57 @@ __device__ __forceinline__ void share(int n, int* lo, int* hi) {
   *hi = min(n, *lo + per);
 }
 
-__device__ __forceinline__ bool gated_out(const BatchProb& P, int check) {
-  return check && __builtin_nontemporal_load(&P.sc->done) != kRunning;
+// Per-problem records, work lists and counts are passed as separate
+// read-only, non-aliasing kernel arguments: nothing a kernel stores can
+// alias them, so their uniform fields are read through the scalar cache
+// instead of vector loads that would wait behind the previous item's stores.
+// The convergence flags are not written while these kernels run.
+#define LQG_BATCH_ARGS                                                   \
+  const BatchProb* __restrict__ probs, const Scalars* __restrict__ scs,   \
+      const Item* __restrict__ live, const int* __restrict__ nlive
+__device__ __forceinline__ bool gated_out(const Scalars& sc, int check) {
+  return check && sc.done != kRunning;
 }
 
 template <int NS>
-__global__ __launch_bounds__(256) void kb_delta(BatchDev B, int in, int out,
-                                                int partial, int check) {
+__global__ __launch_bounds__(256) void kb_delta(LQG_BATCH_ARGS,
+                                                double* __restrict__ psum,
+                                                int in, int out, int partial,
+                                                int check) {
   int lo, hi;
-  share(B.nlive[kItemNode], &lo, &hi);
+  share(*nlive, &lo, &hi);
   for (int it = lo; it < hi; ++it) {
-    const Item w = B.live[kItemNode][it];
-    const BatchProb& P = B.probs[uniform(w.prob)];
-    if (gated_out(P, check)) continue;
+    const Item w = live[it];
+    const BatchProb& P = probs[w.prob];
+    if (gated_out(scs[w.prob], check)) continue;
     delta_tile<double, NS>(P.D, op64(P.C), P.v[in], P.v[out],
-                           partial ? B.psum_node + w.slot : nullptr, w.a, w.b);
+                           partial ? psum + w.slot : nullptr, w.a, w.b);
   }
 }
 
 template <int NS>
-__global__ __launch_bounds__(256) void kb_omega(BatchDev B, int rho, int th,
+__global__ __launch_bounds__(256) void kb_omega(LQG_BATCH_ARGS, int rho, int th,
                                                 int tau, int check) {
   int lo, hi;
-  share(B.nlive[kItemNode], &lo, &hi);
+  share(*nlive, &lo, &hi);
   for (int it = lo; it < hi; ++it) {
-    const Item w = B.live[kItemNode][it];
-    const BatchProb& P = B.probs[uniform(w.prob)];
-    if (gated_out(P, check)) continue;
+    const Item w = live[it];
+    const BatchProb& P = probs[w.prob];
+    if (gated_out(scs[w.prob], check)) continue;
     omega_tile<double, NS>(P.D, op64(P.C), rho >= 0 ? P.v[rho] : nullptr,
                            P.v[th], P.v[tau], w.a, w.b);
   }
 }
 
 template <int NS>
-__global__ __launch_bounds__(256) void kb_xi(BatchDev B, int r, int dl, int rho,
-                                             int check) {
+__global__ __launch_bounds__(256) void kb_xi(LQG_BATCH_ARGS, int r, int dl,
+                                             int rho, int check) {
   int lo, hi;
-  share(B.nlive[kItemNode], &lo, &hi);
+  share(*nlive, &lo, &hi);
   for (int it = lo; it < hi; ++it) {
-    const Item w = B.live[kItemNode][it];
-    const BatchProb& P = B.probs[uniform(w.prob)];
-    if (gated_out(P, check)) continue;
+    const Item w = live[it];
+    const BatchProb& P = probs[w.prob];
+    if (gated_out(scs[w.prob], check)) continue;
     xi_tile<double, NS>(P.D, op64(P.C), r >= 0 ? P.v[r] : nullptr, P.v[dl],
                         P.v[rho], w.a, w.b);
   }
@@ -78,32 +88,35 @@ __global__ __launch_bounds__(256) void kb_xi(BatchDev B, int r, int dl, int rho,
 // Block-solve items are dealt out round-robin (item = lb + k G) so that the
 // long sweeps of large-K problems spread over all workgroups.
 template <int NS>
-__global__ __launch_bounds__(2 * NS * kWave) void kb_solve(BatchDev B, int tau,
-                                                           int out, int check) {
+__global__ __launch_bounds__(2 * NS * kWave) void kb_solve(LQG_BATCH_ARGS,
+                                                           int tau, int out,
+                                                           int check) {
   __shared__ double zb[2][2 * NS][kWave];
-  const int n = B.nlive[kItemSolve];
+  const int n = *nlive;
   for (int it = xcd_block(); it < n; it += gridDim.x) {
-    const Item w = B.live[kItemSolve][it];
-    const BatchProb& P = B.probs[uniform(w.prob)];
-    if (gated_out(P, check)) continue;
+    const Item w = live[it];
+    const BatchProb& P = probs[w.prob];
+    if (gated_out(scs[w.prob], check)) continue;
     phi_tile<double, NS>(P.D, op64(P.C), P.v[tau], P.v[out],
-                         __builtin_nontemporal_load(&P.sc->qt_differs) != 0,
-                         w.a, w.b, zb);
+                         scs[w.prob].qt_differs != 0, w.a, w.b, zb);
   }
 }
 
 // Flat vector operations on element ranges of one problem's vectors; the
 // step lengths come from that problem's scalars.
-__global__ __launch_bounds__(256) void kb_flat(BatchDev B, int op, int ra,
-                                               int rb, int rc, int rd,
-                                               int check) {
+__global__ __launch_bounds__(256) void kb_flat(LQG_BATCH_ARGS,
+                                               const Scalars* __restrict__ scos,
+                                               double* __restrict__ psum,
+                                               double* __restrict__ pmax,
+                                               int op, int ra, int rb, int rc,
+                                               int rd, int check) {
   int lo, hi;
-  share(B.nlive[kItemFlat], &lo, &hi);
+  share(*nlive, &lo, &hi);
   for (int it = lo; it < hi; ++it) {
-    const Item w = B.live[kItemFlat][it];
-    const BatchProb& P = B.probs[uniform(w.prob)];
-    if (gated_out(P, check)) continue;
-    const Scalars* sc = P.sc;
+    const Item w = live[it];
+    const BatchProb& P = probs[w.prob];
+    if (gated_out(scs[w.prob], check)) continue;
+    const Scalars& sc = scs[w.prob];
     double* a = P.v[ra];
     double* b = rb >= 0 ? P.v[rb] : nullptr;
     double* c = rc >= 0 ? P.v[rc] : nullptr;
@@ -112,13 +125,13 @@ __global__ __launch_bounds__(256) void kb_flat(BatchDev B, int op, int ra,
     const int e0 = w.a, e1 = w.b;
     switch (op) {
       case kFlatDir: {
-        const double beta = sc->beta;
+        const double beta = sc.beta;
         for (int g = e0 + threadIdx.x; g < e1; g += blockDim.x)
           b[g] = fma(beta, b[g], a[g]);
         break;
       }
       case kFlatUpdate: {
-        const double th = sc->theta;
+        const double th = sc.theta;
         for (int g = e0 + threadIdx.x; g < e1; g += blockDim.x) {
           c[g] = fma(th, a[g], c[g]);
           const double rn = fma(-th, b[g], d[g]);
@@ -146,12 +159,12 @@ __global__ __launch_bounds__(256) void kb_flat(BatchDev B, int op, int ra,
         }
         break;
       case kFlatScale: {
-        const double s = 1.0 / sqrt(P.sco->rr);
+        const double s = 1.0 / sqrt(scos[w.prob].rr);
         for (int g = e0 + threadIdx.x; g < e1; g += blockDim.x) b[g] = s * a[g];
         break;
       }
       case kFlatAxpy: {
-        const double s = sqrt(P.sco->rr);
+        const double s = sqrt(scos[w.prob].rr);
         for (int g = e0 + threadIdx.x; g < e1; g += blockDim.x)
           b[g] = fma(s, a[g], b[g]);
         break;
@@ -165,9 +178,9 @@ __global__ __launch_bounds__(256) void kb_flat(BatchDev B, int op, int ra,
       acc = block_sum<256>(acc);
       if (op == kFlatNorms || op == kFlatSubNorm) {
         mx = block_max<256>(mx);
-        if (threadIdx.x == 0) B.pmax_flat[w.slot] = mx;
+        if (threadIdx.x == 0) pmax[w.slot] = mx;
       }
-      if (threadIdx.x == 0) B.psum_flat[w.slot] = acc;
+      if (threadIdx.x == 0) psum[w.slot] = acc;
     }
   }
 }
@@ -333,37 +346,44 @@ __global__ void kb_to_abi(BatchDev B) {
 
 void batch_delta(const BatchDev& B, int n, int in, int out, int partial,
                  int check, int grid, hipStream_t s) {
-#define CALL(NS) \
-  hipLaunchKernelGGL(kb_delta<NS>, dim3(grid), dim3(256), 0, s, B, in, out, partial, check)
+#define CALL(NS)                                                              \
+  hipLaunchKernelGGL(kb_delta<NS>, dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
+                     B.live[kItemNode], B.nlive + kItemNode, B.psum_node, in, \
+                     out, partial, check)
   LQG_DISPATCH_N(n, CALL)
 #undef CALL
 }
 void batch_omega(const BatchDev& B, int n, int rho, int th, int tau, int check,
                  int grid, hipStream_t s) {
-#define CALL(NS) \
-  hipLaunchKernelGGL(kb_omega<NS>, dim3(grid), dim3(256), 0, s, B, rho, th, tau, check)
+#define CALL(NS)                                                         \
+  hipLaunchKernelGGL(kb_omega<NS>, dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
+                     B.live[kItemNode], B.nlive + kItemNode, rho, th, tau, check)
   LQG_DISPATCH_N(n, CALL)
 #undef CALL
 }
 void batch_xi(const BatchDev& B, int n, int r, int dl, int rho, int check,
               int grid, hipStream_t s) {
-#define CALL(NS) \
-  hipLaunchKernelGGL(kb_xi<NS>, dim3(grid), dim3(256), 0, s, B, r, dl, rho, check)
+#define CALL(NS)                                                      \
+  hipLaunchKernelGGL(kb_xi<NS>, dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
+                     B.live[kItemNode], B.nlive + kItemNode, r, dl, rho, check)
   LQG_DISPATCH_N(n, CALL)
 #undef CALL
 }
 void batch_solve(const BatchDev& B, int n, int tau, int out, int check,
                  int grid, hipStream_t s) {
-#define CALL(NS)                                                               \
-  hipLaunchKernelGGL(kb_solve<NS>, dim3(grid), dim3(2 * NS * kWave), 0, s, B, \
-                     tau, out, check)
+#define CALL(NS)                                                            \
+  hipLaunchKernelGGL(kb_solve<NS>, dim3(grid), dim3(2 * NS * kWave), 0, s, \
+                     B.probs, B.sc, B.live[kItemSolve], B.nlive + kItemSolve, \
+                     tau, \
+                     out, check)
   LQG_DISPATCH_N(n, CALL)
 #undef CALL
 }
 void batch_flat(const BatchDev& B, int op, int a, int b, int c, int d,
                 int check, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(kb_flat, dim3(grid), dim3(256), 0, s, B, op, a, b, c, d,
-                     check);
+  hipLaunchKernelGGL(kb_flat, dim3(grid), dim3(256), 0, s, B.probs, B.sc,
+                     B.live[kItemFlat], B.nlive + kItemFlat, B.sco, B.psum_flat,
+                     B.pmax_flat, op, a, b, c, d, check);
 }
 void batch_scalar(const BatchDev& B, int mode, int kind, int outer, double tol,
                   hipStream_t s) {

@@ -491,6 +491,8 @@ int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
   B.pmax_flat = reinterpret_cast<double*>(w + Lay.pmax_flat);
   Scalars* sc = reinterpret_cast<Scalars*>(w + Lay.sc);
   Scalars* sco = reinterpret_cast<Scalars*>(w + Lay.sco);
+  B.sc = sc;
+  B.sco = sco;
 
   std::vector<BatchProb> hp(P);
   for (int p = 0; p < P; ++p) {

@@ -19,32 +19,59 @@
 namespace lqg {
 namespace dev {
 
+// Address spaces.  Vectors live in global memory; the operator blocks and
+// factors are time invariant and no kernel writes them while it runs, so
+// they are read through the constant address space, which lets every
+// wave-uniform coefficient load be a scalar load.  Stating both explicitly
+// keeps the code generation the same whether a pointer is a kernel argument
+// (single problem) or was read from a per-problem record (batched form),
+// where the compiler could otherwise prove neither and fall back to flat
+// vector loads.
+template <typename T>
+using gptr = T __attribute__((address_space(1)))*;
+template <typename T>
+using kptr = const T __attribute__((address_space(4)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> glob(T* p) {
+  return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<const T> glob(const T* p) {
+  return (gptr<const T>)p;
+}
+template <typename T>
+__device__ __forceinline__ kptr<T> invariant(const T* p) {
+  return (kptr<T>)p;
+}
+
 template <int NS, typename T>
 __device__ __forceinline__ void load_node(const T* __restrict__ v, int p, int t,
                                           int ldt, T (&x)[NS]) {
-  const T* b = v + (size_t)p * NS * ldt + t;
+  gptr<const T> b = glob(v) + (size_t)p * NS * ldt + t;
 #pragma unroll
   for (int c = 0; c < NS; ++c) x[c] = b[(size_t)c * ldt];
 }
 template <int NS, typename T>
 __device__ __forceinline__ void store_node(T* __restrict__ v, int p, int t,
                                            int ldt, const T (&x)[NS]) {
-  T* b = v + (size_t)p * NS * ldt + t;
+  gptr<T> b = glob(v) + (size_t)p * NS * ldt + t;
 #pragma unroll
   for (int c = 0; c < NS; ++c) b[(size_t)c * ldt] = x[c];
 }
 // acc += M x   (M: NS x NS row-major, wave-uniform)
 template <int NS, typename T>
-__device__ __forceinline__ void mv_add(const T* __restrict__ M, const T (&x)[NS],
+__device__ __forceinline__ void mv_add(const T* Mg, const T (&x)[NS],
                                        T (&acc)[NS]) {
+  kptr<T> M = invariant(Mg);
 #pragma unroll
   for (int a = 0; a < NS; ++a)
 #pragma unroll
     for (int b = 0; b < NS; ++b) acc[a] = fma(M[a * NS + b], x[b], acc[a]);
 }
 template <int NS, typename T>
-__device__ __forceinline__ void mv_sub(const T* __restrict__ M, const T (&x)[NS],
+__device__ __forceinline__ void mv_sub(const T* Mg, const T (&x)[NS],
                                        T (&acc)[NS]) {
+  kptr<T> M = invariant(Mg);
 #pragma unroll
   for (int a = 0; a < NS; ++a)
 #pragma unroll
@@ -287,8 +314,10 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
   // this row's factor coefficients: block row i at fw + i * fstep dwords
   const size_t rows0 = ((size_t)cls * D.V + v) * K;
   const size_t frows0 = ((size_t)cls * D.V + v) * (K + 1);
-  const unsigned* fw = reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow) + (lane % FD);
-  const unsigned* bw = reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow) + (lane % BD);
+  gptr<const unsigned> fw =
+      glob(reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow)) + (lane % FD);
+  gptr<const unsigned> bw =
+      glob(reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow)) + (lane % BD);
   const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
 
   // ---------------------------------------------------------- forward
@@ -443,14 +472,16 @@ __device__ __forceinline__ void phi_tile(const Dims& D, const OpCoef<T>& C,
     // per lane; wavefront w computes row w of the pair
     const size_t nn = (size_t)NS * NS;
     const int h = w / NS, a = w % NS;
+    gptr<const T> tg = glob(tau);
+    gptr<T> og = glob(out);
     for (int i = lane; i < D.K; i += kWave) {
       const int p = (2 * v + h) * D.K + i;
-      const T* Qp = C.Qm + p * nn + a * NS;
+      gptr<const T> Qp = glob(C.Qm) + p * nn + a * NS;  // per-lane rows
       T acc = T(0);
 #pragma unroll
       for (int b = 0; b < NS; ++b)
-        acc = fma(Qp[b], tau[((size_t)p * NS + b) * D.ldt], acc);
-      out[((size_t)p * NS + a) * D.ldt] = acc;
+        acc = fma(Qp[b], tg[((size_t)p * NS + b) * D.ldt], acc);
+      og[((size_t)p * NS + a) * D.ldt] = acc;
     }
   }
 }

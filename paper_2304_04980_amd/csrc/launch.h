@@ -167,6 +167,8 @@ enum UnitKind { kUnitPrep = 0, kUnitStencil = 1, kUnitRhs = 2, kUnitFactor = 3,
 
 struct BatchDev {
   BatchProb* probs;
+  Scalars* sc;     // [P] PCG instances (probs[p].sc == sc + p)
+  Scalars* sco;    // [P] outer loops
   int P;
   Item* orig[kNumItemKinds];
   int norig[kNumItemKinds];
