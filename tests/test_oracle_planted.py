@@ -83,3 +83,73 @@ def test_missing_terminal_weight_is_caught(monkeypatch):
     monkeypatch.setattr(stack, "Q_hat", lambda _p, t: stack._blkdiag_nodes(_p, _p.Q))
     bad = kkt.solve_kkt(p)
     assert np.abs(bad["x"].reshape(11, 2) - R["x"]).max() > 1e-4
+
+
+# ------------------------------------------------------------ warm start
+def _fd_check_fails(monkeypatch_fn=None):
+    """Runs the network finite-difference pin; returns True when it fails."""
+    import test_oracle_warmstart as t
+    try:
+        t.test_network_gradient_matches_finite_differences()
+    except AssertionError:
+        return True
+    return False
+
+
+def test_flipped_input_gradient_tap_is_caught(monkeypatch):
+    from oracle import warmstart as ws
+    real = ws.conv3x3_backward
+
+    def bad(x, W, dy):
+        dW, db, dx = real(x, W[:, ::-1, ::-1, :].copy(), dy)   # taps not flipped back
+        return real(x, W, dy)[0], db, dx
+    monkeypatch.setattr(ws, "conv3x3_backward", bad)
+    assert _fd_check_fails()
+
+
+def test_missing_relu_mask_is_caught(monkeypatch):
+    from oracle import warmstart as ws
+    real_forward = ws.forward
+
+    def no_mask_backward(params, x, acts, dout, round_bf16=False):
+        grads = [None] * len(params)
+        dy = dout
+        for li in range(len(params) - 1, -1, -1):
+            xin = x if li == 0 else acts[li - 1]
+            dW, db, dx = ws.conv3x3_backward(xin, params[li][0], dy)
+            grads[li] = (dW, db)
+            dy = dx                                  # ReLU mask dropped
+        return grads
+    monkeypatch.setattr(ws, "backward", no_mask_backward)
+    assert real_forward is ws.forward
+    assert _fd_check_fails()
+
+
+def test_wrong_chebyshev_recurrence_is_caught(monkeypatch):
+    from oracle import warmstart as ws
+    import test_oracle_warmstart as t
+
+    def bad_basis(T, k):
+        tau = 2.0 * np.arange(T + 1) / T - 1.0
+        B = np.empty((T + 1, k))
+        B[:, 0] = 1.0
+        B[:, 1] = tau
+        for c in range(2, k):
+            B[:, c] = tau * B[:, c - 1] - B[:, c - 2]      # factor 2 dropped
+        return B
+    monkeypatch.setattr(ws, "cheb_basis", bad_basis)
+    with pytest.raises(AssertionError):
+        t.test_chebyshev_basis_matches_numpy_chebval()
+
+
+def test_truncating_bf16_is_caught(monkeypatch):
+    from oracle import warmstart as ws
+    import test_oracle_warmstart as t
+
+    def trunc(x):
+        f = np.asarray(x, dtype=np.float32)
+        u = (f.view(np.uint32) >> 16) << 16
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    monkeypatch.setattr(ws, "bf16", trunc)
+    with pytest.raises(AssertionError):
+        t.test_bf16_rounding()
