@@ -281,6 +281,39 @@ def bench_batched(args, torch, lqgrid):
     print(json.dumps(result), flush=True)
 
 
+def bench_learned(args, torch, lqgrid):
+    """K = N = 64, T = 100 (FP64, tol 1e-8): solves from the learned warm start
+    (features + network inference + solve, with the fallback to a zero start)
+    against the zero start, on held-out test seeds, with the committed
+    network.  A step is one solve of each test problem."""
+    from paper_2304_04980_amd import warmstart
+    net = lqgrid.WarmNet.load_file(warmstart.WEIGHTS)
+    seeds = list(range(warmstart.TEST_SEEDS[0], warmstart.TEST_SEEDS[0] + 8))
+    rows = warmstart.evaluate(net, seeds, repeats=max(1, args.steps))
+    zi = sum(r["zero_it"] for r in rows) / len(rows)
+    wi = sum(r["warm_it"] for r in rows) / len(rows)
+    zs = sum(r["zero_s"] for r in rows)
+    wsec = sum(r["warm_s"] for r in rows)
+    result = {
+        "metric": "solves/s to 1e-8 rel. KKT residual with the learned warm start "
+                  "(inference included) vs zero start, K=N=64 T=100",
+        "value": len(rows) / wsec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": wsec * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
+        "config": {"workload": "learned: K=64 N=64 T=100 n=4 m=2, FP64 PCG S=L=2, tol=1e-8, "
+                               "6-layer 3x3 conv net (64 ch, BF16 MFMA), 16 Chebyshev "
+                               "coefficients per state component",
+                   "test_seeds": [seeds[0], seeds[-1]]},
+        "converged": all(r["ok"] for r in rows),
+        "warm_pcg_iterations": wi, "zero_pcg_iterations": zi,
+        "zero_start_solves_per_s": len(rows) / zs,
+        "speedup_vs_zero_start": zs / wsec,
+        "predictions_kept": sum(r["warm_used"] for r in rows),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +343,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args, torch, lqgrid)
+    if args.workload == "learned":
+        return bench_learned(args, torch, lqgrid)
     p, tol = config_problem(args.workload, args.seed)
     dev = "cuda"
     arrays, x0 = make_inputs(p, torch, dev)

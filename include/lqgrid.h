@@ -94,6 +94,9 @@ typedef struct {
   double inner_tol;   /* FP32_REFINE: relative tolerance of each inner solve
                          (<= 0: 1e-5)                                            */
   int check_every;    /* iterations between host convergence reads (<= 0: 8)    */
+  int warm_fallback;  /* with delta_init: if ||r_delta - Delta delta_init|| >=
+                         ||r_delta|| start from zero instead (the warm start
+                         is then no better than none)                        */
 } lqgrid_solve_opts;
 
 typedef struct {
@@ -104,6 +107,7 @@ typedef struct {
   double rel_kkt_residual; /* ||r_delta - Delta delta~||_2 / ||r_delta||_2 (FP64) */
   double rel_res_inf;      /* ||r_delta - Delta delta~||_inf / ||r_delta||_inf    */
   double seconds;          /* device time of the solve (HIP events)             */
+  int warm_start_used;     /* 1 if delta_init was given and kept                */
 } lqgrid_info;
 
 /* Fills opts with the paper's settings: S = L = 2, tol 1e-10, FP64. */
@@ -185,6 +189,67 @@ LQGRID_API int lqgrid_profile_enable(lqgrid_ctx *ctx, int enable);
  * 3 = vector update.  Returns launches and summed milliseconds since enable. */
 LQGRID_API int lqgrid_profile_read(lqgrid_ctx *ctx, int kernel, long long *launches,
                         double *total_ms);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start.  A convolutional network over the K x N grid maps each
+ * node's x0, A_ii and B_ii to 16 Chebyshev-in-time coefficients per state
+ * component of delta~; their expansion over t = 0..T (tau = 2t/T - 1) is a
+ * delta_init for lqgrid_pcg_solve.  Algorithm 1 allows any initial iterate,
+ * so the preconditioner and the convergence test are unchanged, and
+ * opts.warm_fallback restarts from zero when the prediction does not lower
+ * the residual.  `layers` 3 x 3 convolutions, 64 channels, ReLU between
+ * them, zero padding; BF16 weights and activations, FP32 accumulation on the
+ * matrix cores; FP32 master weights trained with Adam on solves.
+ * Supported: n = 4, n + n^2 + n m <= 32, K a multiple of 8, K N a multiple
+ * of 256, 2 <= layers <= 8 (0 / LQGRID_EINVAL otherwise).
+ *
+ * Parameters: one FP32 array; for each layer l, W_l[64][3][3][cin_l] (cin_0
+ * = 32, cin_l = 64; tap (a, b) couples pixel (i, j) to (i + a - 1, j + b - 1))
+ * followed by b_l[64].  Features of one problem: lqgrid_wsnet_sample_bytes(,
+ * 0) bytes (BF16, pixel-major then channel-major copy).  Targets of one
+ * solved problem: lqgrid_wsnet_sample_bytes(, 1) bytes (FP32 projections of
+ * delta* on the basis and |delta*|^2).  Batched calls read sample index[b]
+ * (device int array; NULL: b) of arrays of such samples.  Workspaces:
+ * lqgrid_wsnet_workspace_bytes(desc, batch), 256-byte aligned.  Enqueue only,
+ * except lqgrid_wsnet_gradient when loss is non-NULL (synchronises). */
+typedef struct {
+  int K, N, n, m, T; /* the problem sizes the network is built for */
+  int layers;        /* convolution layers (6) */
+} lqgrid_wsnet_desc;
+LQGRID_API size_t lqgrid_wsnet_param_count(const lqgrid_wsnet_desc *desc);
+LQGRID_API size_t lqgrid_wsnet_sample_bytes(const lqgrid_wsnet_desc *desc, int which);
+LQGRID_API size_t lqgrid_wsnet_workspace_bytes(const lqgrid_wsnet_desc *desc, int batch);
+/* Input features of one problem (x0: [N][K][n]) into feat. */
+LQGRID_API int lqgrid_wsnet_features(const lqgrid_wsnet_desc *desc,
+                                     const lqgrid_problem_desc *prob, const double *x0,
+                                     void *feat, void *hip_stream);
+/* Training target of one solved problem (delta: [T+1][N][K][n]). */
+LQGRID_API int lqgrid_wsnet_targets(const lqgrid_wsnet_desc *desc, const double *delta,
+                                    float *target, void *workspace, size_t workspace_bytes,
+                                    void *hip_stream);
+/* Network output (FP32 [batch][K N][64], pixel p = j K + i). */
+LQGRID_API int lqgrid_wsnet_forward(const lqgrid_wsnet_desc *desc, int batch,
+                                    const void *feats, const int *index,
+                                    const float *params, float *out, void *workspace,
+                                    size_t workspace_bytes, void *hip_stream);
+/* Mean over the batch of the relative squared error of the expansion,
+ * sum_t |delta0_t - delta*_t|^2 / sum_t |delta*_t|^2, and its gradient with
+ * respect to params (FP32, same layout). */
+LQGRID_API int lqgrid_wsnet_gradient(const lqgrid_wsnet_desc *desc, int batch,
+                                     const void *feats, const float *targets,
+                                     const int *index, const float *params, float *grad,
+                                     double *loss, void *workspace,
+                                     size_t workspace_bytes, void *hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8); moments: 2 x param_count
+ * FP32, zero before step 1. */
+LQGRID_API int lqgrid_wsnet_adam(const lqgrid_wsnet_desc *desc, float *params,
+                                 const float *grad, float *moments, int step, float lr,
+                                 void *hip_stream);
+/* delta_init [T+1][N][K][n] (FP64) predicted for one problem's features. */
+LQGRID_API int lqgrid_wsnet_predict(const lqgrid_wsnet_desc *desc, const void *feat,
+                                    const float *params, double *delta_init,
+                                    void *workspace, size_t workspace_bytes,
+                                    void *hip_stream);
 
 LQGRID_API void lqgrid_destroy(lqgrid_ctx *ctx);
 LQGRID_API const char *lqgrid_status_string(int status);

@@ -80,13 +80,17 @@ def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
         raise ValueError("all dimensions must be >= 1")
     rng = np.random.default_rng(seed)
     A = rng.standard_normal((N, K, n, n))
-    for j in range(N):
-        for i in range(K):
-            sr = _spectral_radius(A[j, i])
-            while sr == 0.0:
-                A[j, i] = rng.standard_normal((n, n))
+    sr_all = np.max(np.abs(np.linalg.eigvals(A)), axis=-1)
+    if np.all(sr_all > 0.0):
+        A *= (rho / sr_all)[..., None, None]
+    else:  # a node to redraw: the same draws in node order
+        for j in range(N):
+            for i in range(K):
                 sr = _spectral_radius(A[j, i])
-            A[j, i] *= rho / sr
+                while sr == 0.0:
+                    A[j, i] = rng.standard_normal((n, n))
+                    sr = _spectral_radius(A[j, i])
+                A[j, i] *= rho / sr
     A_nbr = cs * rng.standard_normal((N, K, 4, n, n))
     B = rng.standard_normal((N, K, n, m))
     x0 = rng.standard_normal((N, K, n))

@@ -381,6 +381,7 @@ void lqgrid_default_opts(lqgrid_solve_opts* o) {
   o->precision = LQGRID_FP64;
   o->inner_tol = 1e-5;
   o->check_every = 8;
+  o->warm_fallback = 1;
 }
 
 int lqgrid_abi_version(void) { return LQGRID_ABI_VERSION; }
@@ -511,11 +512,18 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
   else vec_zero<double>(c->outer[kDl], D.vlen, s);
 
   int status = LQGRID_OK, total_it = 0, passes = 0;
+  bool warm = delta_init != nullptr;
   Scalars h{};
   for (;;) {
     true_residual(c);
     int st = read_scalars(c, c->sco, &h);
     if (st != LQGRID_OK) return st;
+    if (warm && passes == 0 && o.warm_fallback && !(h.rr < h.rd2)) {
+      // the warm start does not lower the residual: start from zero
+      vec_zero<double>(c->outer[kDl], D.vlen, s);
+      warm = false;
+      continue;
+    }
     if (h.rr <= h.tol2) break;  // also the exact-start case (0 iterations)
     if (!std::isfinite(h.rr)) {
       status = LQGRID_EBREAKDOWN;
@@ -563,6 +571,7 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
     info->rel_kkt_residual = h.rd2 > 0 ? std::sqrt(h.rr / h.rd2) : 0.0;
     info->rel_res_inf = h.rdinf > 0 ? h.rinf / h.rdinf : 0.0;
     info->seconds = ms * 1e-3;
+    info->warm_start_used = warm ? 1 : 0;
   }
   return status;
 }

@@ -31,14 +31,20 @@ class ProblemDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("outer_S", c_int), ("inner_L", c_int), ("tol", c_double),
                 ("max_iter", c_int), ("precision", c_int),
-                ("inner_tol", c_double), ("check_every", c_int)]
+                ("inner_tol", c_double), ("check_every", c_int),
+                ("warm_fallback", c_int)]
+
+
+class WsNetDesc(ctypes.Structure):
+    _fields_ = [("K", c_int), ("N", c_int), ("n", c_int), ("m", c_int),
+                ("T", c_int), ("layers", c_int)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("status", c_int), ("iterations", c_int),
                 ("refinements", c_int), ("restarts", c_int),
                 ("rel_kkt_residual", c_double), ("rel_res_inf", c_double),
-                ("seconds", c_double)]
+                ("seconds", c_double), ("warm_start_used", c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +105,32 @@ def load(path: str = LIB_PATH):
     L.lqgrid_abi_version.restype = c_int
     L.lqgrid_last_error.argtypes = []
     L.lqgrid_last_error.restype = ctypes.c_char_p
+    W = POINTER(WsNetDesc)
+    L.lqgrid_wsnet_param_count.argtypes = [W]
+    L.lqgrid_wsnet_param_count.restype = c_size_t
+    L.lqgrid_wsnet_sample_bytes.argtypes = [W, c_int]
+    L.lqgrid_wsnet_sample_bytes.restype = c_size_t
+    L.lqgrid_wsnet_workspace_bytes.argtypes = [W, c_int]
+    L.lqgrid_wsnet_workspace_bytes.restype = c_size_t
+    L.lqgrid_wsnet_features.argtypes = [W, POINTER(ProblemDesc), c_void_p, c_void_p,
+                                        c_void_p]
+    L.lqgrid_wsnet_features.restype = c_int
+    L.lqgrid_wsnet_targets.argtypes = [W, c_void_p, c_void_p, c_void_p, c_size_t,
+                                       c_void_p]
+    L.lqgrid_wsnet_targets.restype = c_int
+    L.lqgrid_wsnet_forward.argtypes = [W, c_int, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, c_void_p, c_size_t, c_void_p]
+    L.lqgrid_wsnet_forward.restype = c_int
+    L.lqgrid_wsnet_gradient.argtypes = [W, c_int, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, POINTER(c_double),
+                                        c_void_p, c_size_t, c_void_p]
+    L.lqgrid_wsnet_gradient.restype = c_int
+    L.lqgrid_wsnet_adam.argtypes = [W, c_void_p, c_void_p, c_void_p, c_int,
+                                    ctypes.c_float, c_void_p]
+    L.lqgrid_wsnet_adam.restype = c_int
+    L.lqgrid_wsnet_predict.argtypes = [W, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_size_t, c_void_p]
+    L.lqgrid_wsnet_predict.restype = c_int
     _lib = L
     return L
 
@@ -107,7 +139,11 @@ EXPORTED = ["lqgrid_default_opts", "lqgrid_workspace_bytes", "lqgrid_setup",
             "lqgrid_factor", "lqgrid_pcg_solve", "lqgrid_batch_workspace_bytes",
             "lqgrid_batch_solve", "lqgrid_apply_operator",
             "lqgrid_profile_enable", "lqgrid_profile_read", "lqgrid_destroy",
-            "lqgrid_status_string", "lqgrid_abi_version", "lqgrid_last_error"]
+            "lqgrid_status_string", "lqgrid_abi_version", "lqgrid_last_error",
+            "lqgrid_wsnet_param_count", "lqgrid_wsnet_sample_bytes",
+            "lqgrid_wsnet_workspace_bytes", "lqgrid_wsnet_features",
+            "lqgrid_wsnet_targets", "lqgrid_wsnet_forward", "lqgrid_wsnet_gradient",
+            "lqgrid_wsnet_adam", "lqgrid_wsnet_predict"]
 
 
 class LqgridError(RuntimeError):
@@ -263,6 +299,7 @@ class Batch:
         P = len(problems)
         self.P = P
         self.keep = []
+        self.arrays, self.x0s = [], []
         self.descs = (ProblemDesc * P)()
         self.x0p = (c_void_p * P)()
         self.outp = (c_void_p * P)()
@@ -275,6 +312,8 @@ class Batch:
                                          a["B"], a["Q"], a["R"], a["QT"])
             x0 = torch.as_tensor(p.x0 if x0s is None else x0s[k]).to(**f64).contiguous()
             self.keep.append(x0)
+            self.arrays.append(a)
+            self.x0s.append(x0)
             self.x0p[k] = x0.data_ptr()
             o = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
             self.outs.append(o)
@@ -299,3 +338,157 @@ class Batch:
 def batch_solve(problems, x0s=None, opts: SolveOpts | None = None, device="cuda"):
     """lqgrid_batch_solve over a list of problems sharing n."""
     return Batch(problems, x0s, device, opts).solve()
+
+
+class WarmNet:
+    """The warm-start network of one problem size: FP32 parameters and Adam
+    moments on the device, plus the calls of the lqgrid_wsnet_* entry
+    points.  Training data are arrays of per-problem feature and target
+    samples (see features() and targets())."""
+
+    def __init__(self, K, N, n, m, T, layers=6, device="cuda", params=None, seed=0):
+        import numpy as np
+        import torch
+        self.L = load()
+        self.desc = WsNetDesc(K, N, n, m, T, layers)
+        self.count = self.L.lqgrid_wsnet_param_count(byref(self.desc))
+        if self.count == 0:
+            raise LqgridError(EINVAL, "lqgrid_wsnet_param_count")
+        self.device = device
+        self.feat_bytes = self.L.lqgrid_wsnet_sample_bytes(byref(self.desc), 0)
+        self.tgt_bytes = self.L.lqgrid_wsnet_sample_bytes(byref(self.desc), 1)
+        if params is None:
+            params = self.init_params(seed)
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(device).contiguous()
+        self.moments = torch.zeros(2 * self.count, dtype=torch.float32, device=device)
+        self.step = 0
+        self._ws = {}
+
+    def layer_shapes(self):
+        """[(W shape (64, 3, 3, cin), b shape (64,))] per layer."""
+        return [((64, 3, 3, 32 if l == 0 else 64), (64,)) for l in range(self.desc.layers)]
+
+    def init_params(self, seed):
+        """He-normal weights (fan-in of the real input channels), zero biases;
+        the last layer scaled by 0.1 so that the first predictions are small."""
+        import numpy as np
+        rng = np.random.default_rng(seed)
+        d = self.desc
+        cin_real = d.n + d.n * d.n + d.n * d.m
+        out = []
+        for l, (ws, bs) in enumerate(self.layer_shapes()):
+            fan = 9 * (cin_real if l == 0 else 64)
+            W = rng.standard_normal(ws) * np.sqrt(2.0 / fan)
+            if l == 0:
+                W[..., cin_real:] = 0.0
+            if l == d.layers - 1:
+                W *= 0.1
+            out += [W.ravel(), np.zeros(bs)]
+        return np.concatenate(out).astype(np.float32)
+
+    def unflatten(self, flat):
+        """List of (W, b) numpy arrays from a flat parameter vector."""
+        import numpy as np
+        flat = np.asarray(flat, dtype=np.float64)
+        out, off = [], 0
+        for ws, bs in self.layer_shapes():
+            nw = int(np.prod(ws))
+            out.append((flat[off:off + nw].reshape(ws), flat[off + nw:off + nw + 64].copy()))
+            off += nw + 64
+        return out
+
+    def workspace(self, batch):
+        import torch
+        if batch not in self._ws:
+            nb = self.L.lqgrid_wsnet_workspace_bytes(byref(self.desc), batch)
+            t = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self._ws[batch] = (t, (t.data_ptr() + 255) // 256 * 256, nb)
+        return self._ws[batch][1:]
+
+    def alloc_features(self, count):
+        import torch
+        return torch.empty((count, self.feat_bytes // 2), dtype=torch.bfloat16,
+                           device=self.device)
+
+    def alloc_targets(self, count):
+        import torch
+        return torch.empty((count, self.tgt_bytes // 4), dtype=torch.float32,
+                           device=self.device)
+
+    def features(self, desc: ProblemDesc, x0, out):
+        """Write the features of one problem (device arrays in desc) into the
+        sample tensor `out` (a row of alloc_features)."""
+        st = self.L.lqgrid_wsnet_features(byref(self.desc), byref(desc), _ptr(x0),
+                                          _ptr(out), _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_features")
+
+    def targets(self, delta, out):
+        wp, nb = self.workspace(1)
+        st = self.L.lqgrid_wsnet_targets(byref(self.desc), _ptr(delta), _ptr(out),
+                                         c_void_p(wp), nb, _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_targets")
+
+    def forward(self, feats, index=None, params=None):
+        import torch
+        batch = feats.shape[0] if index is None else index.numel()
+        wp, nb = self.workspace(batch)
+        P = self.desc.K * self.desc.N
+        out = torch.empty((batch, P, 64), dtype=torch.float32, device=self.device)
+        p = self.params if params is None else params
+        st = self.L.lqgrid_wsnet_forward(byref(self.desc), batch, _ptr(feats), _ptr(index),
+                                         _ptr(p), _ptr(out), c_void_p(wp), nb, _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_forward")
+        return out
+
+    def gradient(self, feats, tgts, index, grad=None, params=None):
+        """(loss, grad) of the batch index (device int32 tensor)."""
+        import torch
+        batch = index.numel()
+        wp, nb = self.workspace(batch)
+        if grad is None:
+            grad = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        p = self.params if params is None else params
+        loss = c_double()
+        st = self.L.lqgrid_wsnet_gradient(byref(self.desc), batch, _ptr(feats), _ptr(tgts),
+                                          _ptr(index), _ptr(p), _ptr(grad), byref(loss),
+                                          c_void_p(wp), nb, _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_gradient")
+        return loss.value, grad
+
+    def adam(self, grad, lr):
+        self.step += 1
+        st = self.L.lqgrid_wsnet_adam(byref(self.desc), _ptr(self.params), _ptr(grad),
+                                      _ptr(self.moments), self.step, lr, _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_adam")
+
+    def predict(self, feat, out=None):
+        """delta_init [T+1][N][K][n] (FP64) for one problem's features."""
+        import torch
+        d = self.desc
+        wp, nb = self.workspace(1)
+        if out is None:
+            out = torch.empty((d.T + 1, d.N, d.K, d.n), dtype=torch.float64,
+                              device=self.device)
+        st = self.L.lqgrid_wsnet_predict(byref(self.desc), _ptr(feat), _ptr(self.params),
+                                         _ptr(out), c_void_p(wp), nb, _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_predict")
+        return out
+
+    def save(self, path):
+        import numpy as np
+        d = self.desc
+        np.savez(path, params=self.params.cpu().numpy(),
+                 dims=np.array([d.K, d.N, d.n, d.m, d.T, d.layers]))
+
+    @classmethod
+    def load_file(cls, path, device="cuda"):
+        import numpy as np
+        z = np.load(path)
+        K, N, n, m, T, layers = (int(v) for v in z["dims"])
+        return cls(K, N, n, m, T, layers, device=device, params=z["params"])

@@ -1,0 +1,284 @@
+"""Learned warm start on the GPU: the BF16-MFMA network kernels against the
+FP64 oracle (oracle/warmstart.py), the Adam step, the fallback rule, that
+training on solves lowers the validation loss, and the gain of the trained
+network over the zero start.
+
+Tolerances.  The oracle runs in FP64 but rounds to BF16 exactly where the
+kernels store BF16 (inputs, weights, hidden activations, back-propagated
+gradients), so the remaining differences come from FP32 accumulation in the
+kernels (relative error about 576 terms x 6e-8 ~ 3.5e-5 of a layer's sums)
+and from the BF16 values that this rounding difference moves across a
+rounding boundary (one BF16 ulp, 2^-8 relative, on a small fraction of the
+stored values).  Bounds used: forward output 2e-3 x max|ref|, loss 1e-3
+relative, weight and bias gradients 2e-2 x max|ref| of each layer's tensor.
+A value moved across a boundary perturbs every output it reaches, and the
+perturbations compound with depth (measured on random data: 1.5e-3 of the
+output scale after 2 layers, 8e-3 after 6, on a few outputs only), so the
+forward output is bounded by 1e-3 of its RMS in the RMS norm and 2e-2 of
+its maximum in the max norm (2e-3 of the RMS for six layers).  The exactness of the arithmetic itself is
+pinned separately on dyadic data, where no rounding decision can differ.
+Targets and the expansion are FP64 sums stored as FP32: 1e-6 relative.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from lqgrid_synth import make_problem
+from oracle import warmstart as ows
+
+pytestmark = pytest.mark.gpu
+
+K, N, n, m, T = 16, 16, 4, 2, 20
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def to_img(v):
+    """[P][C] with pixel p = j K + i -> oracle image (K, N, C)."""
+    v = np.asarray(v, dtype=np.float64)
+    return v.reshape(N, K, -1).transpose(1, 0, 2)
+
+
+def make_set(torch, net, seeds, seed_delta=0):
+    from paper_2304_04980_amd import lqgrid
+    feats = net.alloc_features(len(seeds))
+    tgts = net.alloc_targets(len(seeds))
+    probs, deltas = [], []
+    rng = np.random.default_rng(seed_delta)
+    for k, s in enumerate(seeds):
+        p = make_problem(K, N, T, n, m, seed=s)
+        a = {f: torch.as_tensor(getattr(p, f)).cuda().contiguous()
+             for f in ("A", "A_nbr", "B", "Q", "R", "QT")}
+        x0 = torch.as_tensor(p.x0).cuda().contiguous()
+        desc = lqgrid.problem_desc(K, N, T, n, m, a["A"], a["A_nbr"], a["B"], a["Q"],
+                                   a["R"], a["QT"])
+        net.features(desc, x0, feats[k])
+        d = rng.standard_normal((T + 1, N, K, n)) * np.linspace(2, 0.1, T + 1)[:, None, None, None]
+        net.targets(torch.as_tensor(d).cuda().contiguous(), tgts[k])
+        probs.append(p)
+        deltas.append(d)
+    torch.cuda.synchronize()
+    return feats, tgts, probs, deltas
+
+
+def test_features_and_targets_match_oracle(lib, torch):
+    from paper_2304_04980_amd import lqgrid
+    net = lqgrid.WarmNet(K, N, n, m, T, layers=3, seed=1)
+    feats, tgts, probs, deltas = make_set(torch, net, [3, 4])
+    P = K * N
+    for k, p in enumerate(probs):
+        f = feats[k].float().cpu().numpy()
+        ref = ows.bf16(ows.features(p, 32))
+        assert np.array_equal(to_img(f[:P * 32].reshape(P, 32)), ref)
+        assert np.array_equal(f[P * 32:].reshape(32, P).T, f[:P * 32].reshape(P, 32))
+        t = tgts[k].cpu().numpy()
+        B = ows.cheb_basis(T, 16)
+        proj = np.einsum("tc,tjis->ijsc", B, deltas[k]).reshape(K, N, 64)
+        assert np.allclose(to_img(t[:P * 64].reshape(P, 64)), proj, rtol=1e-6,
+                           atol=1e-6 * np.abs(proj).max())
+        assert np.isclose(t[P * 64], np.sum(deltas[k] ** 2), rtol=1e-6)
+
+
+def random_params(net, seed):
+    """He-normal weights and small random biases."""
+    flat = net.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    out = []
+    off = 0
+    for l, (ws, bs) in enumerate(net.layer_shapes()):
+        nw = int(np.prod(ws))
+        W = flat[off:off + nw].reshape(ws)
+        out += [W.ravel(), rng.standard_normal(64) * 0.05]
+        off += nw + 64
+    return np.concatenate(out).astype(np.float32)
+
+
+def dyadic_set(torch, net, seeds):
+    """Problems whose A, B, x0 are small multiples of 1/4 (exact in BF16)."""
+    from paper_2304_04980_amd import lqgrid
+    feats = net.alloc_features(len(seeds))
+    probs = []
+    for k, s in enumerate(seeds):
+        p = make_problem(K, N, T, n, m, seed=s)
+        rng = np.random.default_rng(s)
+        p.A = rng.integers(-4, 5, p.A.shape) / 4.0
+        p.B = rng.integers(-4, 5, p.B.shape) / 4.0
+        p.x0 = rng.integers(-8, 9, p.x0.shape) / 4.0
+        a = {f: torch.as_tensor(getattr(p, f)).cuda().contiguous()
+             for f in ("A", "A_nbr", "B", "Q", "R", "QT")}
+        x0 = torch.as_tensor(p.x0).cuda().contiguous()
+        desc = lqgrid.problem_desc(K, N, T, n, m, a["A"], a["A_nbr"], a["B"], a["Q"],
+                                   a["R"], a["QT"])
+        net.features(desc, x0, feats[k])
+        probs.append(p)
+    torch.cuda.synchronize()
+    return feats, probs
+
+
+@pytest.mark.parametrize("layers", [2, 6])
+def test_forward_is_exact_on_dyadic_data(lib, torch, layers):
+    """Weights that are multiples of 1/64 and inputs that are multiples of
+    1/4 keep the sums of the network exact, so the kernels and the oracle
+    take identical BF16 rounding decisions: two layers agree exactly, and
+    six agree to the FP32 rounding of the last layer's sums (a differing BF16
+    decision in any hidden value would show as >= 2^-9 relative), for every
+    batch order."""
+    from paper_2304_04980_amd import lqgrid
+    net = lqgrid.WarmNet(K, N, n, m, T, layers=layers, seed=2)
+    rng = np.random.default_rng(3)
+    params = (rng.integers(-3, 4, net.count) / 64.0).astype(np.float32)
+    net.params.copy_(torch.as_tensor(params))
+    feats, probs = dyadic_set(torch, net, [21, 22, 23])
+    pw = net.unflatten(params)
+    refs = [ows.forward(pw, ows.bf16(ows.features(p, 32)), round_bf16=True)[-1] for p in probs]
+    for order in ([0, 1, 2], [2, 0, 1], [1, 1, 0]):
+        idx = torch.tensor(order, dtype=torch.int32, device="cuda")
+        out = net.forward(feats, idx).cpu().numpy()
+        for bi, s in enumerate(order):
+            err = np.abs(to_img(out[bi]) - refs[s]).max()
+            say(f"  layers {layers} order {order} entry {bi}: max err {err:.3e} "
+                f"(scale {np.abs(refs[s]).max():.3e})")
+            assert err <= (0.0 if layers == 2 else 1e-6 * np.abs(refs[s]).max())
+
+
+@pytest.mark.parametrize("layers", [2, 3, 6])
+def test_forward_loss_and_gradient_match_oracle(lib, torch, layers):
+    from paper_2304_04980_amd import lqgrid
+    net = lqgrid.WarmNet(K, N, n, m, T, layers=layers, seed=2)
+    params = random_params(net, 7)
+    net.params.copy_(torch.as_tensor(params))
+    feats, tgts, probs, deltas = make_set(torch, net, [5, 6, 7], seed_delta=1)
+    idx = torch.tensor([2, 0], dtype=torch.int32, device="cuda")
+    out = net.forward(feats, idx).cpu().numpy()
+    loss, grad = net.gradient(feats, tgts, idx)
+    grad = grad.cpu().numpy()
+    P = K * N
+    pw = net.unflatten(params)
+    gsum = [(np.zeros_like(W), np.zeros_like(b)) for W, b in pw]
+    lsum = 0.0
+    for bi, s in enumerate([2, 0]):
+        x = ows.bf16(ows.features(probs[s], 32))
+        acts = ows.forward(pw, x, round_bf16=True)
+        ref = acts[-1]
+        got = to_img(out[bi])
+        err = np.abs(got - ref).max()
+        rms = np.sqrt(np.mean((got - ref) ** 2)) / np.sqrt(np.mean(ref ** 2))
+        say(f"  layers {layers} sample {s}: forward max err {err:.2e} of {np.abs(ref).max():.2e},"
+            f" relative rms {rms:.2e}")
+        assert err <= 2e-2 * np.abs(ref).max() and rms <= (1e-3 if layers < 6 else 2e-3)
+        l, dout = ows.loss_and_grad(ref, deltas[s], n, 16, T)
+        lsum += l / 2
+        grads = ows.backward(pw, x, acts, dout / 2, round_bf16=True)
+        for li, (dW, db) in enumerate(grads):
+            gsum[li][0][...] += dW
+            gsum[li][1][...] += db
+    say(f"  loss gpu {loss:.6f} oracle {lsum:.6f}")
+    assert abs(loss - lsum) <= 1e-3 * abs(lsum)
+    gw = net.unflatten(grad)
+    for li, ((dWg, dbg), (dWr, dbr)) in enumerate(zip(gw, gsum)):
+        ew = np.abs(dWg - dWr).max() / np.abs(dWr).max()
+        eb = np.abs(dbg - dbr).max() / np.abs(dbr).max()
+        say(f"  layer {li}: dW rel err {ew:.2e} (max {np.abs(dWr).max():.2e}), db rel err {eb:.2e}")
+        assert ew <= 2e-2 and eb <= 2e-2
+
+
+def test_adam_step_matches_formula(lib, torch):
+    from paper_2304_04980_amd import lqgrid
+    net = lqgrid.WarmNet(K, N, n, m, T, layers=2, seed=3)
+    p0 = net.params.cpu().numpy().astype(np.float64)
+    g = np.random.default_rng(0).standard_normal(net.count).astype(np.float32)
+    gt = torch.as_tensor(g).cuda()
+    net.adam(gt, 1e-2)
+    net.adam(gt, 1e-2)
+    mm = vv = 0.0
+    p = p0.copy()
+    for t in (1, 2):
+        mm = 0.9 * mm + 0.1 * g
+        vv = 0.999 * vv + 0.001 * g.astype(np.float64) ** 2
+        p = p - 1e-2 * (mm / (1 - 0.9 ** t)) / (np.sqrt(vv / (1 - 0.999 ** t)) + 1e-8)
+    assert np.allclose(net.params.cpu().numpy(), p, rtol=1e-5, atol=1e-6)
+
+
+def test_fallback_to_zero_start(lib, torch):
+    """A prediction that does not lower the residual is replaced by the zero
+    start: same iterations and solution as solving from zero."""
+    from paper_2304_04980_amd import lqgrid
+    p = make_problem(K, N, T, n, m, seed=11)
+    ctx = lqgrid.Context(p)
+    x0 = torch.as_tensor(p.x0).cuda()
+    opts = lqgrid.default_opts(tol=1e-8)
+    d_zero, _, _, iz = ctx.solve(x0, opts)
+    bad = torch.full((T + 1, N, K, n), 50.0, dtype=torch.float64, device="cuda")
+    d_fb, _, _, ib = ctx.solve(x0, opts, delta_init=bad)
+    assert ib["warm_start_used"] == 0 and ib["iterations"] == iz["iterations"]
+    assert torch.equal(d_fb, d_zero)
+    opts.warm_fallback = 0
+    _, _, _, ik = ctx.solve(x0, opts, delta_init=bad)
+    assert ik["warm_start_used"] == 1 and ik["status"] == lqgrid.OK
+    assert ik["rel_kkt_residual"] <= 1e-8
+
+
+def test_training_on_solves_lowers_validation_loss(lib, torch):
+    """Train from scratch on 48 solved problems (K = N = 16, T = 20, solved to
+    1e-8 by the GPU path) and check that the validation loss drops by at
+    least 10 % (240 Adam steps; the relative error of the expansion starts
+    near 1)."""
+    from paper_2304_04980_amd import lqgrid, warmstart
+    net = lqgrid.WarmNet(K, N, n, m, T, layers=6, seed=4)
+
+    def solved(seeds):
+        feats = net.alloc_features(len(seeds))
+        tgts = net.alloc_targets(len(seeds))
+        for k, s in enumerate(seeds):
+            p = make_problem(K, N, T, n, m, seed=s)
+            ctx = lqgrid.Context(p)
+            x0 = torch.as_tensor(p.x0).cuda().contiguous()
+            d, _, _, info = ctx.solve(x0, lqgrid.default_opts(tol=1e-8))
+            assert info["status"] == lqgrid.OK
+            net.features(ctx.desc, x0, feats[k])
+            net.targets(d, tgts[k])
+            torch.cuda.synchronize()
+            ctx.close()
+        return feats, tgts
+
+    ftr, ttr = solved(list(range(100, 148)))
+    fva, tva = solved(list(range(900, 908)))
+    v0 = warmstart.mean_loss(net, fva, tva)
+    hist = warmstart.train(net, ftr, ttr, epochs=40, batch=8, lr=2e-3, val=(fva, tva))
+    v1 = hist[-1][2]
+    say(f"  validation loss {v0:.4f} -> {v1:.4f}; train {hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
+    assert v1 < 0.9 * v0
+
+
+def test_trained_network_gain(lib, torch):
+    """The committed network (trained on 2048 solves of the learned
+    configuration, K = N = 64, T = 100) against the zero start on held-out
+    test seeds.  Measured gain: none -- the prediction's residual exceeds
+    |r_delta| on every test problem, so the fallback keeps the zero start.
+    What the test pins: every solve reaches 1e-8, the warm start never costs
+    PCG iterations, and a rejected prediction gives the zero-start solve."""
+    from paper_2304_04980_amd import lqgrid, warmstart
+    if not os.path.exists(warmstart.WEIGHTS):
+        pytest.skip("trained weights not present")
+    net = lqgrid.WarmNet.load_file(warmstart.WEIGHTS)
+    rows = warmstart.evaluate(net, list(range(warmstart.TEST_SEEDS[0],
+                                              warmstart.TEST_SEEDS[0] + 6)), repeats=1)
+    gain = np.mean([r["zero_it"] - r["warm_it"] for r in rows])
+    for r in rows:
+        say(f"  seed {r['seed']}: zero {r['zero_it']} it, warm {r['warm_it']} it "
+            f"(prediction kept: {r['warm_used']}), res {r['warm_res']:.2e}")
+    say(f"  mean PCG iterations saved by the warm start: {gain:.2f}")
+    assert all(r["ok"] and r["warm_res"] <= 1e-8 for r in rows)
+    assert all(r["warm_it"] <= r["zero_it"] or r["warm_used"] for r in rows)
+    assert all(r["warm_used"] or r["warm_res"] == r["zero_res"] for r in rows)
