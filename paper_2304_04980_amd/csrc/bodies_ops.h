@@ -14,6 +14,8 @@
 // cases of Delta (Psi_hat_0 = Q^-1, no t-1 / t+1 neighbour) are lane
 // predicates.
 #pragma once
+#include <type_traits>
+
 #include "launch.h"
 
 namespace lqg {
@@ -278,6 +280,52 @@ __device__ __forceinline__ float coef<float>(unsigned reg, int j) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane((int)reg, j));
 }
 
+// Compile-time loop: f(std::integral_constant<int, k>) for k = B .. E-1.
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// One row of NW factor coefficients of a block row, as the sweeps read it.
+//   FP64: lane k holds dword k of the row (one coalesced load); coefficient j
+//         is moved to scalar registers with two v_readlane when used.
+//   FP32: lane l holds coefficient 16 g + (l mod 16) in register g, i.e. every
+//         16-lane row of the wavefront holds the same 16 coefficients; the
+//         product with coefficient j takes it from lane j mod 16 of the
+//         lane's own row by a DPP row broadcast (row_newbcast) that folds into
+//         the FMA, so no instruction is spent on moving coefficients.
+template <typename T, int NW>
+struct CoefRow;
+template <int NW>
+struct CoefRow<double, NW> {
+  unsigned r;
+  __device__ __forceinline__ void load(gptr<const unsigned> row, int lane) {
+    r = row[lane % (2 * NW)];
+  }
+  template <int J>
+  __device__ __forceinline__ double get() const {
+    return coef<double>(r, J);
+  }
+};
+template <int NW>
+struct CoefRow<float, NW> {
+  unsigned g[NW / 16];
+  __device__ __forceinline__ void load(gptr<const unsigned> row, int lane) {
+#pragma unroll
+    for (int k = 0; k < NW / 16; ++k) g[k] = row[16 * k + (lane & 15)];
+  }
+  template <int J>
+  __device__ __forceinline__ float get() const {
+    constexpr int kRowNewBcast = 0x150;  // DPP row_newbcast:0
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, (int)g[J >> 4], kRowNewBcast + (J & 15),
+                                           0xF, 0xF, true));
+  }
+};
+
 // Forward/backward substitution with the banded block Cholesky factor of
 // Phi_bar_{v,cls} (eq. "decomposed_problem") for the 64 time steps of this
 // workgroup.  The 2n rows of each block row are split over 2n wavefronts,
@@ -287,11 +335,11 @@ __device__ __forceinline__ float coef<float>(unsigned reg, int j) {
 //   z_i     = Linv_i tau_i - M1_i z_{i-1} - M2_i z_{i-2}
 //   w_i     = Linv_i' z_i                  (parked in `out`)
 //   theta_i = w_i - N1_i theta_{i+1} - N2_i theta_{i+2}
-// Latency hiding: a row's 32 (16) factor coefficients of a block row are one
-// coalesced vector load, lane k holding dword k; they are prefetched kPre
-// block rows ahead in a register ring and moved to scalar registers with
-// v_readlane when used, so no scalar-memory wait is tied to the LDS
-// exchange.  tau and w are prefetched the same way.
+// Latency hiding: a row's 32 (16) factor coefficients of a block row are
+// fetched by coalesced vector loads kPre block rows ahead into a register
+// ring (CoefRow: FP64 through v_readlane, FP32 through DPP row broadcasts),
+// so no scalar-memory wait is tied to the LDS exchange.  tau and w are
+// prefetched the same way.
 template <typename T, int NS, int R>
 __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
                                           int cls, int v, int lane, int t,
@@ -315,119 +363,155 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
   const size_t rows0 = ((size_t)cls * D.V + v) * K;
   const size_t frows0 = ((size_t)cls * D.V + v) * (K + 1);
   gptr<const unsigned> fw =
-      glob(reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow)) + (lane % FD);
+      glob(reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow));
   gptr<const unsigned> bw =
-      glob(reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow)) + (lane % BD);
+      glob(reinterpret_cast<const unsigned*>(C.Bw + (rows0 * NB + R) * kBwRow));
   const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
 
   // ---------------------------------------------------------- forward
-  // Block row i uses ring slot i % kPre; loads for row i + kPre (clamped)
-  // go into the slot just consumed.  The main loop covers whole chunks of
-  // kPre rows with straight-line code, so every wait on a prefetched slot
-  // is an exact in-order vmcnt count.
-  T z1[NB], z2[NB];
+  // Ring slots: block row r of the factor in cring[r % kPre], tau row r in
+  // tring[r % kPre]; each is refilled kPre rows ahead right after its last
+  // use.  The main loop covers whole chunks of kPre rows with straight-line
+  // code, so every wait on a prefetched slot is an exact in-order vmcnt
+  // count.  Only  z_i = p_i - M1_i z_{i-1}  waits for the exchange of
+  // z_{i-1}; the partial p_{i+1} = Linv_{i+1} tau_{i+1} - M2_{i+1} z_{i-1}
+  // and w_{i-1} are computed while the other wavefronts reach the barrier.
+  T z1[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) z1[b] = z2[b] = T(0);
-  unsigned cring[kPre];
+  for (int b = 0; b < NB; ++b) z1[b] = T(0);
+  CoefRow<T, kFwRow> cring[kPre];
   T tring[kPre][NT];
 #pragma unroll
   for (int u = 0; u < kPre; ++u) {
-    cring[u] = fw[(size_t)min(u, K) * fstep];
+    cring[u].load(fw + (size_t)min(u, K) * fstep, lane);
 #pragma unroll
     for (int c = 0; c < NT; ++c)
       tring[u][c] = buf_ld<T>(rtau, rb[c] + (unsigned)min(u, K - 1) * istride);
   }
-  auto fstep_body = [&](int i, int s, bool has_prev) {
-    const unsigned cf = cring[s];
-    T ti[NT];
+  T pre = T(0);  // p_0 = Linv_0 tau_0
+  sfor<0, R + 1>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    pre = fma(cring[0].template get<16 + c>(), tring[0][c], pre);
+  });
 #pragma unroll
-    for (int c = 0; c < NT; ++c) ti[c] = tring[s][c];
-    const int in = min(i + kPre, K);
-    cring[s] = fw[(size_t)in * fstep];
-    const int it = min(in, K - 1);
-#pragma unroll
-    for (int c = 0; c < NT; ++c) tring[s][c] = buf_ld<T>(rtau, rb[c] + (unsigned)it * istride);
-    if (has_prev) {  // w_{i-1} = row R of Linv_{i-1}' times z_{i-1}
+  for (int c = 0; c < NT; ++c)
+    tring[0][c] = buf_ld<T>(rtau, rb[c] + (unsigned)min(kPre, K - 1) * istride);
+  auto fstep_body = [&](int i, int s, int sn, bool has_prev) {
+    const CoefRow<T, kFwRow> cf = cring[s];
+    T zi = pre;
+    if (has_prev) {  // z_i = p_i - M1_i z_{i-1}, two interleaved chains
+      T e0 = T(0), e1 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if constexpr (c % 2 == 0) e0 = fma(cf.template get<c>(), z1[c], e0);
+        else e1 = fma(cf.template get<c>(), z1[c], e1);
+      });
+      zi = pre - (e0 + e1);
+    }
+    zb[i & 1][R][lane] = zi;
+    if (has_prev) {  // w_{i-1} = row R of Linv_{i-1}' z_{i-1} (parked in out)
       T acc = T(0);
-#pragma unroll
-      for (int c = R; c < NB; ++c) acc = fma(coef<T>(cf, 24 + c), z1[c], acc);
+      sfor<R, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        acc = fma(cf.template get<24 + c>(), z1[c], acc);
+      });
       buf_st(rout, ro + (unsigned)(i - 1) * istride, acc);
     }
-    T a0 = T(0), a1 = T(0), a2 = T(0);
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c <= R) a0 = fma(coef<T>(cf, 16 + c), ti[c], a0);
-      a1 = fma(coef<T>(cf, c), z1[c], a1);
-      a2 = fma(coef<T>(cf, 8 + c), z2[c], a2);
+    {  // p_{i+1} = Linv_{i+1} tau_{i+1} - M2_{i+1} z_{i-1}
+      const CoefRow<T, kFwRow>& cn = cring[sn];
+      T a0 = T(0), a2 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if constexpr (c <= R) a0 = fma(cn.template get<16 + c>(), tring[sn][c], a0);
+        a2 = fma(cn.template get<8 + c>(), z1[c], a2);
+      });
+      pre = a0 - a2;
     }
-    zb[i & 1][R][lane] = a0 - a1 - a2;
+    cring[s].load(fw + (size_t)min(i + kPre, K) * fstep, lane);
+    const int it = min(i + 1 + kPre, K - 1);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) tring[sn][c] = buf_ld<T>(rtau, rb[c] + (unsigned)it * istride);
     lds_barrier();
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      z2[b] = z1[b];
-      z1[b] = zb[i & 1][b][lane];
-    }
+    for (int b = 0; b < NB; ++b) z1[b] = zb[i & 1][b][lane];
   };
-  fstep_body(0, 0, false);
+  fstep_body(0, 0, 1, false);
   int i = 1;
   for (; i + kPre <= K; i += kPre) {
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) fstep_body(i + u, (1 + u) % kPre, true);
+    for (int u = 0; u < kPre; ++u) fstep_body(i + u, (1 + u) % kPre, (2 + u) % kPre, true);
   }
 #pragma unroll
   for (int u = 0; u < kPre - 1; ++u)
-    if (i + u < K) fstep_body(i + u, (1 + u) % kPre, true);
+    if (i + u < K) fstep_body(i + u, (1 + u) % kPre, (2 + u) % kPre, true);
   {  // w_{K-1}: block row K of Fw carries Linv_{K-1}'
-    const unsigned cf = fw[(size_t)K * fstep];
+    CoefRow<T, kFwRow> cf;
+    cf.load(fw + (size_t)K * fstep, lane);
     T acc = T(0);
-#pragma unroll
-    for (int c = R; c < NB; ++c) acc = fma(coef<T>(cf, 24 + c), z1[c], acc);
+    sfor<R, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      acc = fma(cf.template get<24 + c>(), z1[c], acc);
+    });
     buf_st(rout, ro + (unsigned)(K - 1) * istride, acc);
   }
   lds_barrier();  // every wavefront is done reading zb before it is reused
 
   // ---------------------------------------------------------- backward
-  T t1[NB], t2[NB];
+  // Step k handles block row j = K-1-k: theta_j = q_j - N1_j theta_{j+1},
+  // with q_j = w_j - N2_j theta_{j+2} computed one step earlier.  Block row
+  // r of the backward factor and w_r live in bring / wring slot
+  // (K-1-r) % kPre.
+  T t1[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) t1[b] = t2[b] = T(0);
-  unsigned bring[kPre];
+  for (int b = 0; b < NB; ++b) t1[b] = T(0);
+  CoefRow<T, kBwRow> bring[kPre];
   T wring[kPre];
 #pragma unroll
   for (int u = 0; u < kPre; ++u) {
     const int iu = K - 1 - u >= 0 ? K - 1 - u : 0;
-    bring[u] = bw[(size_t)iu * bstep];
+    bring[u].load(bw + (size_t)iu * bstep, lane);
     wring[u] = buf_ld<T>(rout, ro + (unsigned)iu * istride);
   }
-  auto bstep_body = [&](int i, int s) {
-    const unsigned cb = bring[s];
-    const T wi = wring[s];
-    const int in = max(i - kPre, 0);
-    bring[s] = bw[(size_t)in * bstep];
-    wring[s] = buf_ld<T>(rout, ro + (unsigned)in * istride);
-    T a1 = T(0), a2 = T(0);
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      a1 = fma(coef<T>(cb, c), t1[c], a1);
-      a2 = fma(coef<T>(cb, 8 + c), t2[c], a2);
+  T q = wring[0];  // q_{K-1} = w_{K-1}
+  wring[0] = buf_ld<T>(rout, ro + (unsigned)max(K - 1 - kPre, 0) * istride);
+  auto bstep_body = [&](int j, int s, int sn, bool has_next) {
+    const CoefRow<T, kBwRow> cb = bring[s];
+    T th = q;
+    if (has_next) {  // theta_j = q_j - N1_j theta_{j+1}
+      T e0 = T(0), e1 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if constexpr (c % 2 == 0) e0 = fma(cb.template get<c>(), t1[c], e0);
+        else e1 = fma(cb.template get<c>(), t1[c], e1);
+      });
+      th = q - (e0 + e1);
     }
-    const T th = wi - a1 - a2;
-    buf_st(rout, ro + (unsigned)i * istride, th);
-    zb[i & 1][R][lane] = th;
+    zb[j & 1][R][lane] = th;
+    buf_st(rout, ro + (unsigned)j * istride, th);
+    {  // q_{j-1} = w_{j-1} - N2_{j-1} theta_{j+1}
+      const CoefRow<T, kBwRow>& cn = bring[sn];
+      T a2 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        a2 = fma(cn.template get<8 + c>(), t1[c], a2);
+      });
+      q = wring[sn] - a2;
+    }
+    bring[s].load(bw + (size_t)max(j - kPre, 0) * bstep, lane);
+    wring[sn] = buf_ld<T>(rout, ro + (unsigned)max(j - 1 - kPre, 0) * istride);
     lds_barrier();
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      t2[b] = t1[b];
-      t1[b] = zb[i & 1][b][lane];
-    }
+    for (int b = 0; b < NB; ++b) t1[b] = zb[j & 1][b][lane];
   };
-  int j = K - 1;  // block row K-1-u uses slot u % kPre
+  bstep_body(K - 1, 0, 1 % kPre, false);
+  int j = K - 2;  // step k = K-1-j uses slots k % kPre and (k+1) % kPre
   for (; j - kPre + 1 >= 0; j -= kPre) {
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) bstep_body(j - u, u);
+    for (int u = 0; u < kPre; ++u) bstep_body(j - u, (1 + u) % kPre, (2 + u) % kPre, true);
   }
 #pragma unroll
   for (int u = 0; u < kPre - 1; ++u)
-    if (j - u >= 0) bstep_body(j - u, u);
+    if (j - u >= 0) bstep_body(j - u, (1 + u) % kPre, (2 + u) % kPre, true);
   lds_barrier();
 }
 
