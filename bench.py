@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("solves/s to 1e-8 rel. KKT residual, K=N=128 T=200 (plain vs chosen); "
           "HBM %")
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
+TWIST_MIN = 8                # block rows from which Phi_bar is solved in the twisted order
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
@@ -45,8 +46,10 @@ def kernel_bytes(p, w=8, qt_distinct=False):
                    (Q^-1, Q_T^-1 - Q^-1) n x n blocks.
       Phi solve:   read tau, write theta (2 U w) + the factor rows of one
                    class: per super-column and block row, 2n forward rows of
-                   32 entries (K+1 block rows) and 2n backward rows of 16
-                   entries (K block rows), + Q per node (the t = 0 solve).
+                   32 entries and 2n backward rows of 16 entries (K block
+                   rows), + Q per node (the t = 0 solve).  The forward table
+                   has K+1 block rows in the one-chain order, K+2 plus one
+                   row of middle couplings in the twisted order (K >= 8).
     The parked forward-sweep result w (one write and one read of U) is not
     algorithmic and shows up as measured traffic above these figures.
     """
@@ -55,7 +58,8 @@ def kernel_bytes(p, w=8, qt_distinct=False):
     V = (N + 1) // 2
     nodes = K * N
     ncls = 2 if qt_distinct else 1
-    factors = ncls * V * 2 * n * (32 * (K + 1) + 16 * K) * w
+    fw_rows = K + 3 if K >= TWIST_MIN else K + 1
+    factors = ncls * V * 2 * n * (32 * fw_rows + 16 * K) * w
     return {
         "delta": 2 * U * w + nodes * 25 * n * n * w,
         "phi_solve": 2 * U * w + factors + nodes * n * n * w,
@@ -64,7 +68,7 @@ def kernel_bytes(p, w=8, qt_distinct=False):
 
 def src_hash():
     h = hashlib.sha256()
-    for f in ("ops.hip", "lqg_internal.h"):
+    for f in ("ops.hip", "bodies_ops.h", "lqg_internal.h"):
         with open(os.path.join(ROOT, "paper_2304_04980_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -72,7 +76,8 @@ def src_hash():
 
 KERNEL_NAMES = {  # rocprofv3 names of the two hot kernels per element type
     ("delta", 8): "k_delta<double, 4>", ("delta", 4): "k_delta<float, 4>",
-    ("phi_solve", 8): "k_phi_solve<double, 4>", ("phi_solve", 4): "k_phi_solve<float, 4>",
+    ("phi_solve", 8): "k_phi_solve_twisted<double, 4>",
+    ("phi_solve", 4): "k_phi_solve_twisted<float, 4>",
 }
 
 

@@ -35,8 +35,8 @@ enum OuterVec { kRd, kDl, kRt, kYt, kNumOuter };
 enum PcgVec { kX, kR, kD, kY, kBufA, kBufB, kBufC, kBufD, kNumPcg };
 
 struct Plan {
-  size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Fw, Bw;
-  size_t G13f, Cdnf, Cupf, Qif, QTdf, Qmf, Fwf, Bwf;
+  size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Fw, Bw, Xw;
+  size_t G13f, Cdnf, Cupf, Qif, QTdf, Qmf, Fwf, Bwf, Xwf;
   size_t outer[kNumOuter], p64[kNumPcg], p32[kNumPcg];
   size_t psum, pmax, scal, scal_outer;
   int npartial;
@@ -52,8 +52,9 @@ Plan make_plan(const Dims& D) {
     return o;
   };
   const size_t nn = (size_t)D.n * D.n, nodes = D.nodes, NB = 2 * D.n;
-  const size_t fw = (size_t)2 * D.V * (D.K + 1) * NB * kFwRow;
+  const size_t fw = (size_t)2 * D.V * fw_rows(D.K) * NB * kFwRow;
   const size_t bw = (size_t)2 * D.V * D.K * NB * kBwRow;
+  const size_t xw = (size_t)2 * D.V * NB * kFwRow;
   P.scal = take(sizeof(Scalars));
   P.scal_outer = take(sizeof(Scalars));
   P.G13 = take(nodes * 13 * nn * 8);
@@ -67,6 +68,7 @@ Plan make_plan(const Dims& D) {
   P.RiBT = take(nodes * (size_t)D.m * D.n * 8);
   P.Fw = take(fw * 8);
   P.Bw = take(bw * 8);
+  P.Xw = take(xw * 8);
   P.G13f = take(nodes * 13 * nn * 4);
   P.Cdnf = take(nodes * 5 * nn * 4);
   P.Cupf = take(nodes * 5 * nn * 4);
@@ -75,6 +77,7 @@ Plan make_plan(const Dims& D) {
   P.Qmf = take(nodes * nn * 4);
   P.Fwf = take(fw * 4);
   P.Bwf = take(bw * 4);
+  P.Xwf = take(xw * 4);
   const int apply_blocks = padded_grid(((D.real_nodes + 3) / 4) * ((D.Tt + 63) / 64));
   P.npartial = std::max(apply_blocks, kFlatBlocks);
   P.psum = take((size_t)P.npartial * 8);
@@ -363,8 +366,9 @@ void make_f32_blocks(lqgrid_ctx* c, bool factors) {
     copy_to_float(c->C.QTd, fp(P.QTdf), nodes * nn, c->stream);
     copy_to_float(c->C.Qm, fp(P.Qmf), nodes * nn, c->stream);
   } else {
-    copy_to_float(c->C.Fw, fp(P.Fwf), 2LL * D.V * (D.K + 1) * NB * kFwRow, c->stream);
+    copy_to_float(c->C.Fw, fp(P.Fwf), 2LL * D.V * fw_rows(D.K) * NB * kFwRow, c->stream);
     copy_to_float(c->C.Bw, fp(P.Bwf), 2LL * D.V * D.K * NB * kBwRow, c->stream);
+    copy_to_float(c->C.Xw, fp(P.Xwf), 2LL * D.V * NB * kFwRow, c->stream);
   }
 }
 
@@ -435,11 +439,11 @@ int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
   c->sc = reinterpret_cast<Scalars*>(w + P.scal);
   c->sco = reinterpret_cast<Scalars*>(w + P.scal_outer);
   c->C = Coef{dp(P.G13), dp(P.Cdn), dp(P.Cup), dp(P.AT5), dp(P.Qi), dp(P.QTi),
-              dp(P.QTd), dp(P.Qm), dp(P.RiBT), dp(P.Fw), dp(P.Bw)};
+              dp(P.QTd), dp(P.Qm), dp(P.RiBT), dp(P.Fw), dp(P.Bw), dp(P.Xw)};
   c->op64 = OpCoef<double>{c->C.G13, c->C.Cdn, c->C.Cup, c->C.Qi, c->C.QTd,
-                           c->C.Qm, c->C.Fw, c->C.Bw};
+                           c->C.Qm, c->C.Fw, c->C.Bw, c->C.Xw};
   c->op32 = OpCoef<float>{fp(P.G13f), fp(P.Cdnf), fp(P.Cupf), fp(P.Qif),
-                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf)};
+                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf), fp(P.Xwf)};
   for (int v = 0; v < kNumOuter; ++v) c->outer[v] = dp(P.outer[v]);
   for (int v = 0; v < kNumPcg; ++v) {
     c->b64.v[v] = dp(P.p64[v]);
@@ -474,8 +478,9 @@ int lqgrid_factor(lqgrid_ctx* c) {
   // entries never written by the factorisation (padding, N1/N2 of the last
   // block rows) must read as zero
   const long long NB = 2 * c->D.n;
-  vec_zero<double>(c->C.Fw, 2LL * c->D.V * (c->D.K + 1) * NB * kFwRow, c->stream);
+  vec_zero<double>(c->C.Fw, 2LL * c->D.V * fw_rows(c->D.K) * NB * kFwRow, c->stream);
   vec_zero<double>(c->C.Bw, 2LL * c->D.V * c->D.K * NB * kBwRow, c->stream);
+  vec_zero<double>(c->C.Xw, 2LL * c->D.V * NB * kFwRow, c->stream);
   launch_factor(c->D, c->C, c->sc, c->stream);
   make_f32_blocks(c, true);
   HIPCHECK(hipGetLastError());

@@ -17,7 +17,7 @@ namespace {
 using namespace dev;
 
 __device__ __forceinline__ OpCoef<double> op64(const Coef& C) {
-  return OpCoef<double>{C.G13, C.Cdn, C.Cup, C.Qi, C.QTd, C.Qm, C.Fw, C.Bw};
+  return OpCoef<double>{C.G13, C.Cdn, C.Cup, C.Qi, C.QTd, C.Qm, C.Fw, C.Bw, C.Xw};
 }
 
 // Contiguous share [*lo, *hi) of n items for this workgroup (XCD-remapped, so

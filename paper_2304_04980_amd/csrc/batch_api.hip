@@ -66,7 +66,7 @@ size_t coef_bytes(const Dims& D) {
   b += 3 * align_up(nodes * 5 * nn * 8);        // Cdn, Cup, AT5
   b += 4 * align_up(nodes * nn * 8);            // Qi, QTi, QTd, Qm
   b += align_up(nodes * (size_t)D.m * D.n * 8); // RiBT
-  b += align_up((size_t)2 * D.V * (D.K + 1) * NB * kFwRow * 8);
+  b += align_up((size_t)2 * D.V * fw_rows(D.K) * NB * kFwRow * 8);
   b += align_up((size_t)2 * D.V * D.K * NB * kBwRow * 8);
   return b;
 }
@@ -89,8 +89,9 @@ Coef coef_at(char* base, const Dims& D) {
   C.QTd = take(nodes * nn * 8);
   C.Qm = take(nodes * nn * 8);
   C.RiBT = take(nodes * (size_t)D.m * D.n * 8);
-  C.Fw = take((size_t)2 * D.V * (D.K + 1) * NB * kFwRow * 8);
+  C.Fw = take((size_t)2 * D.V * fw_rows(D.K) * NB * kFwRow * 8);
   C.Bw = take((size_t)2 * D.V * D.K * NB * kBwRow * 8);
+  C.Xw = nullptr;  // the batched form uses the one-chain factorisation
   return C;
 }
 

@@ -361,7 +361,7 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
                           : kOob;
   // this row's factor coefficients: block row i at fw + i * fstep dwords
   const size_t rows0 = ((size_t)cls * D.V + v) * K;
-  const size_t frows0 = ((size_t)cls * D.V + v) * (K + 1);
+  const size_t frows0 = ((size_t)cls * D.V + v) * fw_rows(K);
   gptr<const unsigned> fw =
       glob(reinterpret_cast<const unsigned*>(C.Fw + (frows0 * NB + R) * kFwRow));
   gptr<const unsigned> bw =
@@ -528,6 +528,269 @@ __device__ __forceinline__ void sweep_dispatch(int w, const Dims& D,
   }
 }
 
+// Forward/backward substitution with the twisted factor of Phi_bar_{v,cls}
+// (factor_twisted: block rows ordered [0 .. m-1 | K-1 .. m+2 | m, m+1],
+// m = (K-2)/2, |B| = K-2-m bottom rows).  4n wavefronts: the top chain on
+// wavefronts 0 .. 2n-1, the bottom chain on 2n .. 4n-1, one row R each, so
+// the two chains run side by side and each wavefront passes about K/2
+// exchange barriers per direction instead of K.  Each half exchanges its z
+// (theta) rows through its own LDS buffer `zo`; the two middle block rows
+// read the other half's buffer `zx`.  The work between barriers b-1 and b is
+// step b, and step b writes slot b & 1, so a slot is rewritten only after
+// every reader has passed the next barrier.  Steps (both halves pass the
+// same 2 |B| + 5 barriers):
+//   0 .. |B|-1     top positions 0 .. m-1 (after |B| - m idle steps),
+//                  bottom positions 0 .. |B|-1 (rows K-1 .. m+2)
+//   |B|            top: z_m = p_m - M1_m z_{m-1} - X_t z_{m+2};
+//                  bottom: p_{m+1} -= M1 z_{m+2} + X_b1 z_{m-1}
+//   |B|+1          top: w_m;  bottom: z_{m+1} = p_{m+1} - X_b2 z_m
+//   |B|+2          bottom: theta_{m+1} = Linv_{m+1}' z_{m+1}
+//   |B|+3 ..       top: theta_m, theta_{m-1}, .., theta_0;  bottom (one step
+//                  later, once theta_m is known): theta_{m+2} .. theta_{K-1}
+// Coefficients, tau and w are prefetched kPre positions ahead as in
+// sweep_row; the middle rows' coefficients sit in registers from the start.
+template <typename T, int NS, int R>
+__device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
+                                              int cls, int v, int lane, int t,
+                                              bool act, bool top,
+                                              __amdgpu_buffer_rsrc_t rtau,
+                                              __amdgpu_buffer_rsrc_t rout,
+                                              T (*zo)[2 * NS][kWave],
+                                              T (*zx)[2 * NS][kWave]) {
+  constexpr int NB = 2 * NS;
+  constexpr int NT = R + 1;
+  constexpr int ES = sizeof(T);
+  constexpr int FD = kFwRow * ES / 4, BD = kBwRow * ES / 4;
+  const int K = D.K;
+  const int m = (K - 2) / 2, nbot = K - 2 - m, pad = nbot - m;
+  const int len = top ? m + 1 : nbot + 1;  // chain positions, middle row last
+  const int rbase = top ? 0 : K - 1, rdir = top ? 1 : -1;
+  const unsigned istride = (unsigned)(NS * D.ldt * ES);
+  auto roff = [&](int k) { return (unsigned)(rbase + rdir * k) * istride; };
+  unsigned rb[NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c)
+    rb[c] = act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * ES)
+                : kOob;
+  const unsigned ro = act ? (unsigned)((((size_t)(2 * v + R / NS) * K * NS + (R % NS)) * D.ldt + t) * ES)
+                          : kOob;
+  const size_t cv = (size_t)cls * D.V + v;
+  gptr<const unsigned> fw = glob(reinterpret_cast<const unsigned*>(
+      C.Fw + ((cv * fw_rows(K) + (top ? 0 : m + 2)) * NB + R) * kFwRow));
+  gptr<const unsigned> bw = glob(reinterpret_cast<const unsigned*>(
+      C.Bw + ((cv * K + (top ? 0 : m + 1)) * NB + R) * kBwRow));
+  const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
+  CoefRow<T, kFwRow> cx, cmid, clast;
+  cx.load(glob(reinterpret_cast<const unsigned*>(C.Xw + (cv * NB + R) * kFwRow)), lane);
+  cmid.load(fw + (size_t)(len - 1) * fstep, lane);
+  clast.load(fw + (size_t)len * fstep, lane);
+
+  // ---------------------------------------------------------- forward
+  const int fso = top ? pad : 0;  // step of position 0
+  for (int u = 0; u < fso; ++u) lds_barrier();
+  T z1[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) z1[b] = T(0);
+  CoefRow<T, kFwRow> cring[kPre];
+  T tring[kPre][NT];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    cring[u].load(fw + (size_t)min(u, len) * fstep, lane);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) tring[u][c] = buf_ld<T>(rtau, rb[c] + roff(min(u, len - 1)));
+  }
+  T pre = T(0);
+  sfor<0, R + 1>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    pre = fma(cring[0].template get<16 + c>(), tring[0][c], pre);
+  });
+#pragma unroll
+  for (int c = 0; c < NT; ++c) tring[0][c] = buf_ld<T>(rtau, rb[c] + roff(min(kPre, len - 1)));
+  auto w_of = [&](const CoefRow<T, kFwRow>& cf, const T* z) {  // row R of Linv' z
+    T acc = T(0);
+    sfor<R, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      acc = fma(cf.template get<24 + c>(), z[c], acc);
+    });
+    return acc;
+  };
+  auto fstep_body = [&](int i, int s, int sn, bool has_prev) {
+    const CoefRow<T, kFwRow> cf = cring[s];
+    T zi = pre;
+    if (has_prev) {
+      T e0 = T(0), e1 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if constexpr (c % 2 == 0) e0 = fma(cf.template get<c>(), z1[c], e0);
+        else e1 = fma(cf.template get<c>(), z1[c], e1);
+      });
+      zi = pre - (e0 + e1);
+    }
+    zo[(i + fso) & 1][R][lane] = zi;
+    if (has_prev) buf_st(rout, ro + roff(i - 1), w_of(cf, z1));
+    {
+      const CoefRow<T, kFwRow>& cn = cring[sn];
+      T a0 = T(0), a2 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if constexpr (c <= R) a0 = fma(cn.template get<16 + c>(), tring[sn][c], a0);
+        a2 = fma(cn.template get<8 + c>(), z1[c], a2);
+      });
+      pre = a0 - a2;
+    }
+    cring[s].load(fw + (size_t)min(i + kPre, len) * fstep, lane);
+    const int it = min(i + 1 + kPre, len - 1);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) tring[sn][c] = buf_ld<T>(rtau, rb[c] + roff(it));
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) z1[b] = zo[(i + fso) & 1][b][lane];
+  };
+  fstep_body(0, 0, 1, false);
+  int i = 1;
+  for (; i + kPre <= len - 1; i += kPre) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) fstep_body(i + u, (1 + u) % kPre, (2 + u) % kPre, true);
+  }
+#pragma unroll
+  for (int u = 0; u < kPre - 1; ++u)
+    if (i + u < len - 1) fstep_body(i + u, (1 + u) % kPre, (2 + u) % kPre, true);
+
+  // ---------------------------------------------------------- middle rows
+  const int sm = nbot;  // step of z_m
+  T zy[NB];
+  if (top) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) zy[b] = zx[(sm - 1) & 1][b][lane];  // z_{m+2}
+    T e0 = T(0), e1 = T(0);
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      e0 = fma(cmid.template get<c>(), z1[c], e0);
+      e1 = fma(cx.template get<c>(), zy[c], e1);
+    });
+    zo[sm & 1][R][lane] = pre - (e0 + e1);
+    buf_st(rout, ro + roff(len - 2), w_of(cmid, z1));  // w_{m-1}
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) z1[b] = zo[sm & 1][b][lane];
+    buf_st(rout, ro + roff(len - 1), w_of(clast, z1));  // w_m
+    lds_barrier();
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) zy[b] = zx[(sm - 1) & 1][b][lane];  // z_{m-1}
+    T e0 = T(0), e1 = T(0);
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      e0 = fma(cmid.template get<c>(), z1[c], e0);
+      e1 = fma(cx.template get<8 + c>(), zy[c], e1);
+    });
+    pre -= e0 + e1;
+    buf_st(rout, ro + roff(len - 2), w_of(cmid, z1));  // w_{m+2}
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) zy[b] = zx[sm & 1][b][lane];  // z_m
+    T e2 = T(0), e3 = T(0);
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c % 2 == 0) e2 = fma(cx.template get<16 + c>(), zy[c], e2);
+      else e3 = fma(cx.template get<16 + c>(), zy[c], e3);
+    });
+    zo[(sm + 1) & 1][R][lane] = pre - (e2 + e3);
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) z1[b] = zo[(sm + 1) & 1][b][lane];  // z_{m+1}
+    const T th = w_of(clast, z1);  // theta_{m+1}
+    zo[(sm + 2) & 1][R][lane] = th;
+    buf_st(rout, ro + roff(len - 1), th);
+  }
+  lds_barrier();  // step sm + 2
+
+  // ---------------------------------------------------------- backward
+  // Backward step kk handles position bs - kk: theta = q - N1 theta_next,
+  // with q = w - N2 theta_next_next prepared one step earlier.
+  T t1[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) t1[b] = (top ? zx : zo)[(sm + 2) & 1][b][lane];  // theta_{m+1}
+  const int bs = top ? len - 1 : len - 2, cnt = bs + 1;
+  const int bso = top ? sm + 3 : sm + 4;  // step of backward step 0
+  CoefRow<T, kBwRow> bring[kPre];
+  T wring[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int iu = max(bs - u, 0);
+    bring[u].load(bw + (size_t)iu * bstep, lane);
+    wring[u] = buf_ld<T>(rout, ro + roff(iu));
+  }
+  T q = wring[0];
+  wring[0] = buf_ld<T>(rout, ro + roff(max(bs - kPre, 0)));
+  auto bstep_body = [&](int kk, int s, int sn) {
+    const int p = bs - kk;
+    const CoefRow<T, kBwRow> cb = bring[s];
+    T e0 = T(0), e1 = T(0);
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c % 2 == 0) e0 = fma(cb.template get<c>(), t1[c], e0);
+      else e1 = fma(cb.template get<c>(), t1[c], e1);
+    });
+    const T th = q - (e0 + e1);
+    zo[(kk + bso) & 1][R][lane] = th;
+    buf_st(rout, ro + roff(p), th);
+    {
+      const CoefRow<T, kBwRow>& cn = bring[sn];
+      T a2 = T(0);
+      sfor<0, NB>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        a2 = fma(cn.template get<8 + c>(), t1[c], a2);
+      });
+      q = wring[sn] - a2;
+    }
+    bring[s].load(bw + (size_t)max(p - kPre, 0) * bstep, lane);
+    wring[sn] = buf_ld<T>(rout, ro + roff(max(p - 1 - kPre, 0)));
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) t1[b] = zo[(kk + bso) & 1][b][lane];
+  };
+  if (!top) {  // step sm + 3: wait for theta_m, then fold N2 theta_m into q
+    lds_barrier();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) zy[b] = zx[(sm + 3) & 1][b][lane];
+    T a2 = T(0);
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      a2 = fma(bring[0].template get<8 + c>(), zy[c], a2);
+    });
+    q -= a2;
+  }
+  bstep_body(0, 0, 1);
+  int kk = 1;
+  for (; kk + kPre <= cnt; kk += kPre) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) bstep_body(kk + u, (1 + u) % kPre, (2 + u) % kPre);
+  }
+#pragma unroll
+  for (int u = 0; u < kPre - 1; ++u)
+    if (kk + u < cnt) bstep_body(kk + u, (1 + u) % kPre, (2 + u) % kPre);
+  for (int u = 0; u < (top ? pad : 0); ++u) lds_barrier();
+  lds_barrier();  // every wavefront is done reading the buffers
+}
+
+template <typename T, int NS, int R = 0>
+__device__ __forceinline__ void twisted_dispatch(int w, const Dims& D,
+                                                 const OpCoef<T>& C, int cls,
+                                                 int v, int lane, int t, bool act,
+                                                 bool top,
+                                                 __amdgpu_buffer_rsrc_t rtau,
+                                                 __amdgpu_buffer_rsrc_t rout,
+                                                 T (*zo)[2 * NS][kWave],
+                                                 T (*zx)[2 * NS][kWave]) {
+  if constexpr (R < 2 * NS) {
+    if (w == R)
+      sweep_twisted<T, NS, R>(D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
+    else
+      twisted_dispatch<T, NS, R + 1>(w, D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
+  }
+}
+
 // out = Phi~^-1 tau for super-column v and time steps 64 chunk .. 64 chunk
 // + 63, by one workgroup of 2n wavefronts (zb: the workgroup's LDS exchange
 // buffer).  t = 0: Phi_bar_{v,0} = blkdiag(Q^-1), so theta = Q tau per node.
@@ -561,6 +824,51 @@ __device__ __forceinline__ void phi_tile(const Dims& D, const OpCoef<T>& C,
     for (int i = lane; i < D.K; i += kWave) {
       const int p = (2 * v + h) * D.K + i;
       gptr<const T> Qp = glob(C.Qm) + p * nn + a * NS;  // per-lane rows
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < NS; ++b)
+        acc = fma(Qp[b], tg[((size_t)p * NS + b) * D.ldt], acc);
+      og[((size_t)p * NS + a) * D.ldt] = acc;
+    }
+  }
+}
+
+// phi_tile with the twisted factor: 4n wavefronts per workgroup, zb holds
+// the two halves' exchange buffers.
+template <typename T, int NS>
+__device__ __forceinline__ void phi_tile_twisted(const Dims& D, const OpCoef<T>& C,
+                                                 const T* __restrict__ tau,
+                                                 T* __restrict__ out, int qt_distinct,
+                                                 int v, int chunk,
+                                                 T (*zb)[2][2 * NS][kWave]) {
+  constexpr int NB = 2 * NS;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x >> 6);
+  const bool top = w < NB;
+  const int R = top ? w : w - NB;
+  const int t0 = chunk * kWave;
+  const int t = t0 + lane;
+  const int T_ = D.T;
+  const bool valid = t < D.Tt;
+  const long long bytes = D.vlen * (long long)sizeof(T);
+  const __amdgpu_buffer_rsrc_t rtau = make_rsrc(tau, bytes);
+  const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, bytes);
+  T(*zo)[NB][kWave] = zb[top ? 0 : 1];
+  T(*zx)[NB][kWave] = zb[top ? 1 : 0];
+  twisted_dispatch<T, NS>(R, D, C, 0, v, lane, t,
+                          valid && t >= 1 && !(qt_distinct && t == T_), top, rtau, rout,
+                          zo, zx);
+  if (qt_distinct && t0 <= T_ && T_ < t0 + kWave)
+    twisted_dispatch<T, NS>(R, D, C, 1, v, lane, t, valid && t == T_, top, rtau, rout, zo,
+                            zx);
+  if (chunk == 0) {  // t = 0: theta = Q tau per node, block rows split over the halves
+    const size_t nn = (size_t)NS * NS;
+    const int h = R / NS, a = R % NS;
+    gptr<const T> tg = glob(tau);
+    gptr<T> og = glob(out);
+    for (int i = lane + (top ? 0 : kWave); i < D.K; i += 2 * kWave) {
+      const int p = (2 * v + h) * D.K + i;
+      gptr<const T> Qp = glob(C.Qm) + p * nn + a * NS;
       T acc = T(0);
 #pragma unroll
       for (int b = 0; b < NS; ++b)

@@ -322,7 +322,7 @@ __device__ inline void factor(const Dims& D, const Coef& C, Scalars* sc, int v,
         n2 += Lp2[k * NB + r] * L2[c * NB + k];   // Linv_{i-2}' L_{i,i-2}'
       }
       const size_t rows = ((size_t)cls * D.V + v) * K;         // Bw rows of (cls, v)
-      const size_t frows = ((size_t)cls * D.V + v) * (K + 1);  // Fw rows of (cls, v)
+      const size_t frows = ((size_t)cls * D.V + v) * fw_rows(K);  // Fw rows of (cls, v)
       double* fw = C.Fw + ((frows + i) * NB + r) * kFwRow;
       fw[c] = m1;
       fw[8 + c] = m2;
@@ -342,6 +342,250 @@ __device__ inline void factor(const Dims& D, const Coef& C, Scalars* sc, int v,
   }
   if (tid == 0 && bad) atomicOr(&sc->flag_notspd, 1);
   __syncthreads();  // the shared arrays may be reused by the next unit
+}
+
+// ---------------------------------------------------------------------------
+// Twisted factorisation of Phi_bar_{v,cls} (K >= kTwistMin block rows): the
+// same banded block Cholesky in the row order [0 .. m-1 (top chain),
+// K-1 down to m+2 (bottom chain), m, m+1 (middle)], m = (K-2)/2.  In this
+// order the two chains do not couple, so their substitutions run
+// concurrently, each over about K/2 block rows.  Rows m and m+1 couple to
+// the last two rows of each chain:
+//   L_{m,m-2}, L_{m,m-1}  (top chain, as its continuation),   L_{m,m+2};
+//   L_{m+1,m+3}, L_{m+1,m+2} (bottom chain, as its continuation),
+//   L_{m+1,m-1}, L_{m+1,m}
+// (every other block of the two middle rows is zero: Phi couples rows at
+// most two apart, and a coupling to the last row of a chain does not fill
+// back into it).
+//
+// Stored (per class and super-column), in the substitution-product form of
+// factor():
+//   Fw rows 0 .. m+1      top chain positions k = 0 .. m (row i = k), row
+//                         m+1 holding only Linv_m'
+//   Fw rows m+2 .. K+1    bottom chain positions k = 0 .. |B| (row
+//                         i = K-1-k, position |B| = row m+1), the last row
+//                         holding only Linv_{m+1}'
+//   Bw rows 0 .. m        top positions: N1 = Linv_i' L_{i+1,i}',
+//                         N2 = Linv_i' L_{i+2,i}' (row m: N1 = Linv_m'
+//                         L_{m+1,m}', N2 = 0)
+//   Bw rows m+1 .. K-1    bottom positions: N1 = Linv_i' L_{i-1,i}',
+//                         N2 = Linv_i' L_{i-2,i}' (row m+1: zero)
+//   Xw                    Linv_m L_{m,m+2} | Linv_{m+1} L_{m+1,m-1} |
+//                         Linv_{m+1} L_{m+1,m}
+__device__ __forceinline__ int twist_m(int K) { return (K - 2) / 2; }
+
+// (A B')[r][c], (A B)[r][c], (A' B')[r][c] of NB x NB row-major blocks.
+__device__ inline double mm_t(const double* A, const double* B, int NB, int r, int c) {
+  double s = 0.0;
+  for (int k = 0; k < NB; ++k) s += A[r * NB + k] * B[c * NB + k];
+  return s;
+}
+__device__ inline double mm_n(const double* A, const double* B, int NB, int r, int c) {
+  double s = 0.0;
+  for (int k = 0; k < NB; ++k) s += A[r * NB + k] * B[k * NB + c];
+  return s;
+}
+__device__ inline double mm_tt(const double* A, const double* B, int NB, int r, int c) {
+  double s = 0.0;
+  for (int k = 0; k < NB; ++k) s += A[k * NB + r] * B[c * NB + k];
+  return s;
+}
+
+// Cholesky factor of the SPD block Dm and its inverse (one thread).
+__device__ inline void chol_inv(const double* Dm, double* Lc, double* Li, int NB,
+                                int* bad) {
+  for (int e = 0; e < NB * NB; ++e) Lc[e] = Li[e] = 0.0;
+  for (int cc = 0; cc < NB; ++cc) {
+    double s = Dm[cc * NB + cc];
+    for (int k = 0; k < cc; ++k) s -= Lc[cc * NB + k] * Lc[cc * NB + k];
+    if (!(s > 0.0) || !isfinite(s)) {
+      *bad = 1;
+      s = 1.0;
+    }
+    const double dg = sqrt(s);
+    Lc[cc * NB + cc] = dg;
+    for (int rr = cc + 1; rr < NB; ++rr) {
+      double t = Dm[rr * NB + cc];
+      for (int k = 0; k < cc; ++k) t -= Lc[rr * NB + k] * Lc[cc * NB + k];
+      Lc[rr * NB + cc] = t / dg;
+    }
+  }
+  for (int cc = 0; cc < NB; ++cc) {
+    Li[cc * NB + cc] = 1.0 / Lc[cc * NB + cc];
+    for (int rr = cc + 1; rr < NB; ++rr) {
+      double t = 0.0;
+      for (int k = cc; k < rr; ++k) t += Lc[rr * NB + k] * Li[k * NB + cc];
+      Li[rr * NB + cc] = -t / Lc[rr * NB + rr];
+    }
+  }
+}
+
+// One 64-thread workgroup per (v, cls).
+__device__ inline void factor_twisted(const Dims& D, const Coef& C, Scalars* sc,
+                                      int v, int cls) {
+  const int NB = 2 * D.n, NB2 = NB * NB, K = D.K;
+  const int m = twist_m(K), nb = K - 2 - m;  // top and bottom chain lengths
+  const int tid = threadIdx.x;
+  const int r = tid / NB, c = tid - (tid / NB) * NB;
+  const bool act = tid < NB2;
+  __shared__ double S1[64], S2[64], Dm[64], L1[64], L2[64], T1[64];
+  __shared__ double Lp1[64], Lp2[64], L1p[64], Lc[64], Li[64];
+  __shared__ double A1[64], A2[64], A12[64], B1[64], B2[64], B12[64];
+  __shared__ double Lm1[64], Lmx[64], Lmi[64], LA[64], LM[64], SX[64];
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  const size_t cv = (size_t)cls * D.V + v;
+  const size_t fw0 = cv * fw_rows(K), bw0 = cv * K;
+  const size_t fwb = fw0 + m + 2, bwb = bw0 + m + 1;  // bottom chain tables
+  auto fwrow = [&](size_t row) { return C.Fw + (row * NB + r) * kFwRow; };
+  auto bwrow = [&](size_t row) { return C.Bw + (row * NB + r) * kBwRow; };
+  double* xw = C.Xw + (cv * NB + r) * kFwRow;
+  if (act) xw[24 + c] = 0.0;
+
+  // One chain: positions k = 0 .. len-1, block row i = top ? k : K-1-k,
+  // previous rows in the chain i - dir and i - 2 dir.  Leaves Lp1 = Linv of
+  // position len-1, Lp2 = Linv of position len-2, L1p = L_{len-1, len-2}.
+  auto chain = [&](bool top, int len, size_t ft, size_t bt) {
+    const int dir = top ? 1 : -1;
+    if (act) Lp1[tid] = Lp2[tid] = L1p[tid] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < len; ++k) {
+      const int i = top ? k : K - 1 - k;
+      if (act) {
+        Dm[tid] = phi_entry(D, C, cls, v, i, 0, r, c);
+        S1[tid] = k >= 1 ? phi_entry(D, C, cls, v, i, -dir, r, c) : 0.0;
+        S2[tid] = k >= 2 ? phi_entry(D, C, cls, v, i, -2 * dir, r, c) : 0.0;
+      }
+      __syncthreads();
+      if (act) L2[tid] = mm_t(S2, Lp2, NB, r, c);
+      __syncthreads();
+      if (act) T1[tid] = S1[tid] - mm_t(L2, L1p, NB, r, c);
+      __syncthreads();
+      if (act) L1[tid] = mm_t(T1, Lp1, NB, r, c);
+      __syncthreads();
+      if (act) Dm[tid] -= mm_t(L1, L1, NB, r, c) + mm_t(L2, L2, NB, r, c);
+      __syncthreads();
+      if (tid == 0) chol_inv(Dm, Lc, Li, NB, &bad);
+      __syncthreads();
+      if (act) {
+        double* fw = fwrow(ft + k);
+        fw[c] = mm_n(Li, L1, NB, r, c);
+        fw[8 + c] = mm_n(Li, L2, NB, r, c);
+        fw[16 + c] = Li[r * NB + c];
+        fwrow(ft + k + 1)[24 + c] = Li[c * NB + r];
+        if (k >= 1) bwrow(bt + k - 1)[c] = mm_tt(Lp1, L1, NB, r, c);
+        if (k >= 2) bwrow(bt + k - 2)[8 + c] = mm_tt(Lp2, L2, NB, r, c);
+      }
+      __syncthreads();
+      if (act) {
+        Lp2[tid] = Lp1[tid];
+        Lp1[tid] = Li[tid];
+        L1p[tid] = L1[tid];
+      }
+      __syncthreads();
+    }
+  };
+  chain(true, m, fw0, bw0);
+  if (act) {
+    A1[tid] = Lp1[tid];   // Linv_{m-1}
+    A2[tid] = Lp2[tid];   // Linv_{m-2}
+    A12[tid] = L1p[tid];  // L_{m-1,m-2}
+  }
+  chain(false, nb, fwb, bwb);
+  if (act) {
+    B1[tid] = Lp1[tid];   // Linv_{m+2}
+    B2[tid] = Lp2[tid];   // Linv_{m+3}
+    B12[tid] = L1p[tid];  // L_{m+2,m+3}
+  }
+  __syncthreads();
+
+  // ---- row m: top continuation plus L_{m,m+2}
+  if (act) {
+    Dm[tid] = phi_entry(D, C, cls, v, m, 0, r, c);
+    S1[tid] = phi_entry(D, C, cls, v, m, -1, r, c);
+    S2[tid] = phi_entry(D, C, cls, v, m, -2, r, c);
+    SX[tid] = phi_entry(D, C, cls, v, m, 2, r, c);
+  }
+  __syncthreads();
+  if (act) {
+    L2[tid] = mm_t(S2, A2, NB, r, c);   // L_{m,m-2}
+    Lmx[tid] = mm_t(SX, B1, NB, r, c);  // L_{m,m+2}
+  }
+  __syncthreads();
+  if (act) T1[tid] = S1[tid] - mm_t(L2, A12, NB, r, c);
+  __syncthreads();
+  if (act) Lm1[tid] = mm_t(T1, A1, NB, r, c);  // L_{m,m-1}
+  __syncthreads();
+  if (act)
+    Dm[tid] -= mm_t(Lm1, Lm1, NB, r, c) + mm_t(L2, L2, NB, r, c) + mm_t(Lmx, Lmx, NB, r, c);
+  __syncthreads();
+  if (tid == 0) chol_inv(Dm, Lc, Lmi, NB, &bad);  // Lmi = Linv_m
+  __syncthreads();
+  if (act) {
+    double* fw = fwrow(fw0 + m);
+    fw[c] = mm_n(Lmi, Lm1, NB, r, c);
+    fw[8 + c] = mm_n(Lmi, L2, NB, r, c);
+    fw[16 + c] = Lmi[r * NB + c];
+    double* fe = fwrow(fw0 + m + 1);
+    fe[c] = fe[8 + c] = fe[16 + c] = 0.0;
+    fe[24 + c] = Lmi[c * NB + r];                             // Linv_m'
+    xw[c] = mm_n(Lmi, Lmx, NB, r, c);                         // Linv_m L_{m,m+2}
+    bwrow(bw0 + m - 1)[c] = mm_tt(A1, Lm1, NB, r, c);         // N1_{m-1}
+    bwrow(bw0 + m - 2)[8 + c] = mm_tt(A2, L2, NB, r, c);      // N2_{m-2}
+    bwrow(bwb + nb - 1)[8 + c] = mm_tt(B1, Lmx, NB, r, c);    // N2 of row m+2
+  }
+  __syncthreads();
+
+  // ---- row m+1: bottom continuation plus L_{m+1,m-1}, L_{m+1,m}
+  if (act) {
+    Dm[tid] = phi_entry(D, C, cls, v, m + 1, 0, r, c);
+    S1[tid] = phi_entry(D, C, cls, v, m + 1, 1, r, c);    // Phi[m+1, m+2]
+    S2[tid] = phi_entry(D, C, cls, v, m + 1, 2, r, c);    // Phi[m+1, m+3]
+    SX[tid] = phi_entry(D, C, cls, v, m + 1, -2, r, c);   // Phi[m+1, m-1]
+    T1[tid] = phi_entry(D, C, cls, v, m + 1, -1, r, c);   // Phi[m+1, m]
+  }
+  __syncthreads();
+  if (act) {
+    L2[tid] = mm_t(S2, B2, NB, r, c);  // L_{m+1,m+3}
+    LA[tid] = mm_t(SX, A1, NB, r, c);  // L_{m+1,m-1}
+  }
+  __syncthreads();
+  if (act) S1[tid] -= mm_t(L2, B12, NB, r, c);
+  __syncthreads();
+  if (act) L1[tid] = mm_t(S1, B1, NB, r, c);  // L_{m+1,m+2}
+  __syncthreads();
+  if (act) T1[tid] -= mm_t(LA, Lm1, NB, r, c) + mm_t(L1, Lmx, NB, r, c);
+  __syncthreads();
+  if (act) LM[tid] = mm_t(T1, Lmi, NB, r, c);  // L_{m+1,m}
+  __syncthreads();
+  if (act)
+    Dm[tid] -= mm_t(L1, L1, NB, r, c) + mm_t(L2, L2, NB, r, c) + mm_t(LA, LA, NB, r, c) +
+               mm_t(LM, LM, NB, r, c);
+  __syncthreads();
+  if (tid == 0) chol_inv(Dm, Lc, Li, NB, &bad);  // Li = Linv_{m+1}
+  __syncthreads();
+  if (act) {
+    double* fw = fwrow(fwb + nb);
+    fw[c] = mm_n(Li, L1, NB, r, c);
+    fw[8 + c] = mm_n(Li, L2, NB, r, c);
+    fw[16 + c] = Li[r * NB + c];
+    double* fe = fwrow(fwb + nb + 1);
+    fe[c] = fe[8 + c] = fe[16 + c] = 0.0;
+    fe[24 + c] = Li[c * NB + r];                              // Linv_{m+1}'
+    xw[8 + c] = mm_n(Li, LA, NB, r, c);                       // Linv_{m+1} L_{m+1,m-1}
+    xw[16 + c] = mm_n(Li, LM, NB, r, c);                      // Linv_{m+1} L_{m+1,m}
+    bwrow(bwb + nb - 1)[c] = mm_tt(B1, L1, NB, r, c);         // N1 of row m+2
+    bwrow(bwb + nb - 2)[8 + c] = mm_tt(B2, L2, NB, r, c);     // N2 of row m+3
+    bwrow(bw0 + m - 1)[8 + c] = mm_tt(A1, LA, NB, r, c);      // N2_{m-1}
+    double* bm = bwrow(bw0 + m);
+    bm[c] = mm_tt(Lmi, LM, NB, r, c);                         // N1_m
+    bm[8 + c] = 0.0;
+    double* bl = bwrow(bwb + nb);                             // row m+1: zero
+    bl[c] = bl[8 + c] = 0.0;
+  }
+  __syncthreads();
+  if (tid == 0 && bad) atomicOr(&sc->flag_notspd, 1);
+  __syncthreads();
 }
 
 // r_delta = col(-gamma_hat, 0, ..., 0) in the internal layout, entry g =

@@ -70,14 +70,24 @@ struct Coef {
   double *G13, *Cdn, *Cup, *AT5;
   double *Qi, *QTi, *QTd, *Qm, *RiBT;
   double *Fw, *Bw;  // factors in the substitution layout
+  double* Xw;       // middle-row couplings of the twisted factorisation
 };
 
 // The operator blocks the hot kernels read, in the element type of the
 // vectors they act on (FP64 arrays above, or their FP32 copies).
 template <typename T>
 struct OpCoef {
-  const T *G13, *Cdn, *Cup, *Qi, *QTd, *Qm, *Fw, *Bw;
+  const T *G13, *Cdn, *Cup, *Qi, *QTd, *Qm, *Fw, *Bw, *Xw;
 };
+
+// Rows of the forward factor table per (class, super-column): the one-chain
+// factorisation uses K + 1 of them, the twisted one K + 2.
+__host__ __device__ inline int fw_rows(int K) { return K + 2; }
+
+// The single-problem path factors and solves Phi_bar in the twisted order
+// from this many block rows on (the batched form keeps the one-chain order).
+constexpr int kTwistMin = 8;
+__host__ __device__ inline bool twisted(const Dims& D) { return D.K >= kTwistMin; }
 
 // Device-resident PCG scalars.
 struct Scalars {

@@ -72,6 +72,18 @@ __global__ __launch_bounds__(2 * NS * kWave) void k_phi_solve(
   phi_tile<T, NS>(D, C, tau, out, qt_distinct, lb / nchunks, lb % nchunks, zb);
 }
 
+template <typename T, int NS>
+__global__ __launch_bounds__(4 * NS * kWave) void k_phi_solve_twisted(
+    Dims D, OpCoef<T> C, const T* __restrict__ tau, T* __restrict__ out,
+    const Scalars* sc, int check, int qt_distinct) {
+  if (is_done(sc, check)) return;
+  __shared__ T zb[2][2][2 * NS][kWave];
+  const int nchunks = time_chunks(D);
+  const int lb = xcd_block();
+  if (lb >= D.V * nchunks) return;
+  phi_tile_twisted<T, NS>(D, C, tau, out, qt_distinct, lb / nchunks, lb % nchunks, zb);
+}
+
 // x_t = Q_t^-1 (-dl_t + [t<T] A_hat' dl_{t+1}),  u_t = R^-1 B' dl_{t+1}
 // (Sec. II-B: x~ = Q~^-1 A~' delta~, u~ = R~^-1 B~' delta~), written in the
 // interface layout.
@@ -179,7 +191,15 @@ void phi_solve(const Dims& D, const OpCoef<T>& C, const T* tau, T* out,
 #define CALL(NS)                                                                   \
   hipLaunchKernelGGL((k_phi_solve<T, NS>), g, dim3(2 * NS * kWave), 0, s, D, C, \
                      tau, out, sc, check_done, qt_distinct)
-  LQG_DISPATCH_N(D.n, CALL)
+#define CALL_TW(NS)                                                            \
+  hipLaunchKernelGGL((k_phi_solve_twisted<T, NS>), g, dim3(4 * NS * kWave), 0, s, \
+                     D, C, tau, out, sc, check_done, qt_distinct)
+  if (twisted(D)) {
+    LQG_DISPATCH_N(D.n, CALL_TW)
+  } else {
+    LQG_DISPATCH_N(D.n, CALL)
+  }
+#undef CALL_TW
 #undef CALL
 }
 

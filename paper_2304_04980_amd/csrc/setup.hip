@@ -17,6 +17,9 @@ __global__ void k_stencil(Dims D, ProblemIn P, Coef C) {
 __global__ __launch_bounds__(64) void k_factor(Dims D, Coef C, Scalars* sc) {
   factor(D, C, sc, blockIdx.x, blockIdx.y);
 }
+__global__ __launch_bounds__(64) void k_factor_twisted(Dims D, Coef C, Scalars* sc) {
+  factor_twisted(D, C, sc, blockIdx.x, blockIdx.y);
+}
 __global__ void k_rhs_init(Dims D, const double* __restrict__ x0,
                            double* __restrict__ rd) {
   rhs_init(D, x0, rd, blockIdx.x * blockDim.x + threadIdx.x);
@@ -34,7 +37,10 @@ void launch_setup(const Dims& D, const ProblemIn& P, const Coef& C,
 }
 
 void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_factor, dim3(D.V, 2), dim3(64), 0, s, D, C, sc);
+  if (twisted(D))
+    hipLaunchKernelGGL(k_factor_twisted, dim3(D.V, 2), dim3(64), 0, s, D, C, sc);
+  else
+    hipLaunchKernelGGL(k_factor, dim3(D.V, 2), dim3(64), 0, s, D, C, sc);
 }
 
 void launch_rhs_init(const Dims& D, const double* x0, double* rd,
