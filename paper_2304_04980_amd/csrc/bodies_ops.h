@@ -266,20 +266,28 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off,
                                        float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
-// Coefficient j of a factor row whose dwords are spread one per lane.
+// The same with a wave-uniform byte offset in the instruction's scalar
+// offset field (no per-lane address arithmetic).
 template <typename T>
-__device__ __forceinline__ T coef(unsigned reg, int j);
+__device__ __forceinline__ T buf_lds(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
 template <>
-__device__ __forceinline__ double coef<double>(unsigned reg, int j) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)reg, 2 * j + 1);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+__device__ __forceinline__ double buf_lds<double>(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                  unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 template <>
-__device__ __forceinline__ float coef<float>(unsigned reg, int j) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane((int)reg, j));
+__device__ __forceinline__ float buf_lds<float>(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-
+__device__ __forceinline__ void buf_sts(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                        double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_sts(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                        float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
 // Compile-time loop: f(std::integral_constant<int, k>) for k = B .. E-1.
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
@@ -289,25 +297,32 @@ __device__ __forceinline__ void sfor(F&& f) {
   }
 }
 
-// One row of NW factor coefficients of a block row, as the sweeps read it.
-//   FP64: lane k holds dword k of the row (one coalesced load); coefficient j
-//         is moved to scalar registers with two v_readlane when used.
-//   FP32: lane l holds coefficient 16 g + (l mod 16) in register g, i.e. every
-//         16-lane row of the wavefront holds the same 16 coefficients; the
-//         product with coefficient j takes it from lane j mod 16 of the
-//         lane's own row by a DPP row broadcast (row_newbcast) that folds into
-//         the FMA, so no instruction is spent on moving coefficients.
+// One row of NW factor coefficients of a block row, as the sweeps read it:
+// lane l holds coefficient 16 g + (l mod 16) in register g, i.e. every 16-lane
+// row of the wavefront holds the same 16 coefficients.  The product with
+// coefficient j takes it from lane j mod 16 of the lane's own row by a DPP
+// row broadcast (row_newbcast) in the FMA itself (v_fmac_f32_dpp,
+// v_fmac_f64_dpp), so no instruction is spent on moving coefficients (the
+// compiler keeps a separate v_mov_b32_dpp, and has no 64-bit form).  The
+// coefficient registers are written only by vector-memory loads, so the DPP
+// read-after-VALU-write wait states do not apply; a check over the generated
+// code (check_dpp.py) guards this.
 template <typename T, int NW>
 struct CoefRow;
 template <int NW>
 struct CoefRow<double, NW> {
-  unsigned r;
+  double g[NW / 16];
   __device__ __forceinline__ void load(gptr<const unsigned> row, int lane) {
-    r = row[lane % (2 * NW)];
+    gptr<const double> rd = reinterpret_cast<gptr<const double>>(row);
+#pragma unroll
+    for (int k = 0; k < NW / 16; ++k) g[k] = rd[16 * k + (lane & 15)];
   }
   template <int J>
-  __device__ __forceinline__ double get() const {
-    return coef<double>(r, J);
+  __device__ __forceinline__ double fmac(double acc, double z) const {
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(g[J >> 4]), "v"(z), "n"(J & 15));
+    return acc;
   }
 };
 template <int NW>
@@ -323,6 +338,13 @@ struct CoefRow<float, NW> {
     return __builtin_bit_cast(
         float, __builtin_amdgcn_update_dpp(0, (int)g[J >> 4], kRowNewBcast + (J & 15),
                                            0xF, 0xF, true));
+  }
+  template <int J>
+  __device__ __forceinline__ float fmac(float acc, float z) const {
+    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(g[J >> 4]), "v"(z), "n"(J & 15));
+    return acc;
   }
 };
 
@@ -391,7 +413,7 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
   T pre = T(0);  // p_0 = Linv_0 tau_0
   sfor<0, R + 1>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
-    pre = fma(cring[0].template get<16 + c>(), tring[0][c], pre);
+    pre = cring[0].template fmac<16 + c>(pre, tring[0][c]);
   });
 #pragma unroll
   for (int c = 0; c < NT; ++c)
@@ -403,8 +425,8 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
       T e0 = T(0), e1 = T(0);
       sfor<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        if constexpr (c % 2 == 0) e0 = fma(cf.template get<c>(), z1[c], e0);
-        else e1 = fma(cf.template get<c>(), z1[c], e1);
+        if constexpr (c % 2 == 0) e0 = cf.template fmac<c>(e0, z1[c]);
+        else e1 = cf.template fmac<c>(e1, z1[c]);
       });
       zi = pre - (e0 + e1);
     }
@@ -413,7 +435,7 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
       T acc = T(0);
       sfor<R, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        acc = fma(cf.template get<24 + c>(), z1[c], acc);
+        acc = cf.template fmac<24 + c>(acc, z1[c]);
       });
       buf_st(rout, ro + (unsigned)(i - 1) * istride, acc);
     }
@@ -422,8 +444,8 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
       T a0 = T(0), a2 = T(0);
       sfor<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        if constexpr (c <= R) a0 = fma(cn.template get<16 + c>(), tring[sn][c], a0);
-        a2 = fma(cn.template get<8 + c>(), z1[c], a2);
+        if constexpr (c <= R) a0 = cn.template fmac<16 + c>(a0, tring[sn][c]);
+        a2 = cn.template fmac<8 + c>(a2, z1[c]);
       });
       pre = a0 - a2;
     }
@@ -450,7 +472,7 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
     T acc = T(0);
     sfor<R, NB>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
-      acc = fma(cf.template get<24 + c>(), z1[c], acc);
+      acc = cf.template fmac<24 + c>(acc, z1[c]);
     });
     buf_st(rout, ro + (unsigned)(K - 1) * istride, acc);
   }
@@ -481,8 +503,8 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
       T e0 = T(0), e1 = T(0);
       sfor<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        if constexpr (c % 2 == 0) e0 = fma(cb.template get<c>(), t1[c], e0);
-        else e1 = fma(cb.template get<c>(), t1[c], e1);
+        if constexpr (c % 2 == 0) e0 = cb.template fmac<c>(e0, t1[c]);
+        else e1 = cb.template fmac<c>(e1, t1[c]);
       });
       th = q - (e0 + e1);
     }
@@ -493,7 +515,7 @@ __device__ __forceinline__ void sweep_row(const Dims& D, const OpCoef<T>& C,
       T a2 = T(0);
       sfor<0, NB>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        a2 = fma(cn.template get<8 + c>(), t1[c], a2);
+        a2 = cn.template fmac<8 + c>(a2, t1[c]);
       });
       q = wring[sn] - a2;
     }
@@ -525,269 +547,6 @@ __device__ __forceinline__ void sweep_dispatch(int w, const Dims& D,
   if constexpr (R < 2 * NS) {
     if (w == R) sweep_row<T, NS, R>(D, C, cls, v, lane, t, act, rtau, rout, zb);
     else sweep_dispatch<T, NS, R + 1>(w, D, C, cls, v, lane, t, act, rtau, rout, zb);
-  }
-}
-
-// Forward/backward substitution with the twisted factor of Phi_bar_{v,cls}
-// (factor_twisted: block rows ordered [0 .. m-1 | K-1 .. m+2 | m, m+1],
-// m = (K-2)/2, |B| = K-2-m bottom rows).  4n wavefronts: the top chain on
-// wavefronts 0 .. 2n-1, the bottom chain on 2n .. 4n-1, one row R each, so
-// the two chains run side by side and each wavefront passes about K/2
-// exchange barriers per direction instead of K.  Each half exchanges its z
-// (theta) rows through its own LDS buffer `zo`; the two middle block rows
-// read the other half's buffer `zx`.  The work between barriers b-1 and b is
-// step b, and step b writes slot b & 1, so a slot is rewritten only after
-// every reader has passed the next barrier.  Steps (both halves pass the
-// same 2 |B| + 5 barriers):
-//   0 .. |B|-1     top positions 0 .. m-1 (after |B| - m idle steps),
-//                  bottom positions 0 .. |B|-1 (rows K-1 .. m+2)
-//   |B|            top: z_m = p_m - M1_m z_{m-1} - X_t z_{m+2};
-//                  bottom: p_{m+1} -= M1 z_{m+2} + X_b1 z_{m-1}
-//   |B|+1          top: w_m;  bottom: z_{m+1} = p_{m+1} - X_b2 z_m
-//   |B|+2          bottom: theta_{m+1} = Linv_{m+1}' z_{m+1}
-//   |B|+3 ..       top: theta_m, theta_{m-1}, .., theta_0;  bottom (one step
-//                  later, once theta_m is known): theta_{m+2} .. theta_{K-1}
-// Coefficients, tau and w are prefetched kPre positions ahead as in
-// sweep_row; the middle rows' coefficients sit in registers from the start.
-template <typename T, int NS, int R>
-__device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
-                                              int cls, int v, int lane, int t,
-                                              bool act, bool top,
-                                              __amdgpu_buffer_rsrc_t rtau,
-                                              __amdgpu_buffer_rsrc_t rout,
-                                              T (*zo)[2 * NS][kWave],
-                                              T (*zx)[2 * NS][kWave]) {
-  constexpr int NB = 2 * NS;
-  constexpr int NT = R + 1;
-  constexpr int ES = sizeof(T);
-  constexpr int FD = kFwRow * ES / 4, BD = kBwRow * ES / 4;
-  const int K = D.K;
-  const int m = (K - 2) / 2, nbot = K - 2 - m, pad = nbot - m;
-  const int len = top ? m + 1 : nbot + 1;  // chain positions, middle row last
-  const int rbase = top ? 0 : K - 1, rdir = top ? 1 : -1;
-  const unsigned istride = (unsigned)(NS * D.ldt * ES);
-  auto roff = [&](int k) { return (unsigned)(rbase + rdir * k) * istride; };
-  unsigned rb[NT];
-#pragma unroll
-  for (int c = 0; c < NT; ++c)
-    rb[c] = act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * ES)
-                : kOob;
-  const unsigned ro = act ? (unsigned)((((size_t)(2 * v + R / NS) * K * NS + (R % NS)) * D.ldt + t) * ES)
-                          : kOob;
-  const size_t cv = (size_t)cls * D.V + v;
-  gptr<const unsigned> fw = glob(reinterpret_cast<const unsigned*>(
-      C.Fw + ((cv * fw_rows(K) + (top ? 0 : m + 2)) * NB + R) * kFwRow));
-  gptr<const unsigned> bw = glob(reinterpret_cast<const unsigned*>(
-      C.Bw + ((cv * K + (top ? 0 : m + 1)) * NB + R) * kBwRow));
-  const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
-  CoefRow<T, kFwRow> cx, cmid, clast;
-  cx.load(glob(reinterpret_cast<const unsigned*>(C.Xw + (cv * NB + R) * kFwRow)), lane);
-  cmid.load(fw + (size_t)(len - 1) * fstep, lane);
-  clast.load(fw + (size_t)len * fstep, lane);
-
-  // ---------------------------------------------------------- forward
-  const int fso = top ? pad : 0;  // step of position 0
-  for (int u = 0; u < fso; ++u) lds_barrier();
-  T z1[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) z1[b] = T(0);
-  CoefRow<T, kFwRow> cring[kPre];
-  T tring[kPre][NT];
-#pragma unroll
-  for (int u = 0; u < kPre; ++u) {
-    cring[u].load(fw + (size_t)min(u, len) * fstep, lane);
-#pragma unroll
-    for (int c = 0; c < NT; ++c) tring[u][c] = buf_ld<T>(rtau, rb[c] + roff(min(u, len - 1)));
-  }
-  T pre = T(0);
-  sfor<0, R + 1>([&](auto cc) {
-    constexpr int c = decltype(cc)::value;
-    pre = fma(cring[0].template get<16 + c>(), tring[0][c], pre);
-  });
-#pragma unroll
-  for (int c = 0; c < NT; ++c) tring[0][c] = buf_ld<T>(rtau, rb[c] + roff(min(kPre, len - 1)));
-  auto w_of = [&](const CoefRow<T, kFwRow>& cf, const T* z) {  // row R of Linv' z
-    T acc = T(0);
-    sfor<R, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      acc = fma(cf.template get<24 + c>(), z[c], acc);
-    });
-    return acc;
-  };
-  auto fstep_body = [&](int i, int s, int sn, bool has_prev) {
-    const CoefRow<T, kFwRow> cf = cring[s];
-    T zi = pre;
-    if (has_prev) {
-      T e0 = T(0), e1 = T(0);
-      sfor<0, NB>([&](auto cc) {
-        constexpr int c = decltype(cc)::value;
-        if constexpr (c % 2 == 0) e0 = fma(cf.template get<c>(), z1[c], e0);
-        else e1 = fma(cf.template get<c>(), z1[c], e1);
-      });
-      zi = pre - (e0 + e1);
-    }
-    zo[(i + fso) & 1][R][lane] = zi;
-    if (has_prev) buf_st(rout, ro + roff(i - 1), w_of(cf, z1));
-    {
-      const CoefRow<T, kFwRow>& cn = cring[sn];
-      T a0 = T(0), a2 = T(0);
-      sfor<0, NB>([&](auto cc) {
-        constexpr int c = decltype(cc)::value;
-        if constexpr (c <= R) a0 = fma(cn.template get<16 + c>(), tring[sn][c], a0);
-        a2 = fma(cn.template get<8 + c>(), z1[c], a2);
-      });
-      pre = a0 - a2;
-    }
-    cring[s].load(fw + (size_t)min(i + kPre, len) * fstep, lane);
-    const int it = min(i + 1 + kPre, len - 1);
-#pragma unroll
-    for (int c = 0; c < NT; ++c) tring[sn][c] = buf_ld<T>(rtau, rb[c] + roff(it));
-    lds_barrier();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) z1[b] = zo[(i + fso) & 1][b][lane];
-  };
-  fstep_body(0, 0, 1, false);
-  int i = 1;
-  for (; i + kPre <= len - 1; i += kPre) {
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) fstep_body(i + u, (1 + u) % kPre, (2 + u) % kPre, true);
-  }
-#pragma unroll
-  for (int u = 0; u < kPre - 1; ++u)
-    if (i + u < len - 1) fstep_body(i + u, (1 + u) % kPre, (2 + u) % kPre, true);
-
-  // ---------------------------------------------------------- middle rows
-  const int sm = nbot;  // step of z_m
-  T zy[NB];
-  if (top) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) zy[b] = zx[(sm - 1) & 1][b][lane];  // z_{m+2}
-    T e0 = T(0), e1 = T(0);
-    sfor<0, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      e0 = fma(cmid.template get<c>(), z1[c], e0);
-      e1 = fma(cx.template get<c>(), zy[c], e1);
-    });
-    zo[sm & 1][R][lane] = pre - (e0 + e1);
-    buf_st(rout, ro + roff(len - 2), w_of(cmid, z1));  // w_{m-1}
-    lds_barrier();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) z1[b] = zo[sm & 1][b][lane];
-    buf_st(rout, ro + roff(len - 1), w_of(clast, z1));  // w_m
-    lds_barrier();
-  } else {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) zy[b] = zx[(sm - 1) & 1][b][lane];  // z_{m-1}
-    T e0 = T(0), e1 = T(0);
-    sfor<0, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      e0 = fma(cmid.template get<c>(), z1[c], e0);
-      e1 = fma(cx.template get<8 + c>(), zy[c], e1);
-    });
-    pre -= e0 + e1;
-    buf_st(rout, ro + roff(len - 2), w_of(cmid, z1));  // w_{m+2}
-    lds_barrier();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) zy[b] = zx[sm & 1][b][lane];  // z_m
-    T e2 = T(0), e3 = T(0);
-    sfor<0, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      if constexpr (c % 2 == 0) e2 = fma(cx.template get<16 + c>(), zy[c], e2);
-      else e3 = fma(cx.template get<16 + c>(), zy[c], e3);
-    });
-    zo[(sm + 1) & 1][R][lane] = pre - (e2 + e3);
-    lds_barrier();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) z1[b] = zo[(sm + 1) & 1][b][lane];  // z_{m+1}
-    const T th = w_of(clast, z1);  // theta_{m+1}
-    zo[(sm + 2) & 1][R][lane] = th;
-    buf_st(rout, ro + roff(len - 1), th);
-  }
-  lds_barrier();  // step sm + 2
-
-  // ---------------------------------------------------------- backward
-  // Backward step kk handles position bs - kk: theta = q - N1 theta_next,
-  // with q = w - N2 theta_next_next prepared one step earlier.
-  T t1[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) t1[b] = (top ? zx : zo)[(sm + 2) & 1][b][lane];  // theta_{m+1}
-  const int bs = top ? len - 1 : len - 2, cnt = bs + 1;
-  const int bso = top ? sm + 3 : sm + 4;  // step of backward step 0
-  CoefRow<T, kBwRow> bring[kPre];
-  T wring[kPre];
-#pragma unroll
-  for (int u = 0; u < kPre; ++u) {
-    const int iu = max(bs - u, 0);
-    bring[u].load(bw + (size_t)iu * bstep, lane);
-    wring[u] = buf_ld<T>(rout, ro + roff(iu));
-  }
-  T q = wring[0];
-  wring[0] = buf_ld<T>(rout, ro + roff(max(bs - kPre, 0)));
-  auto bstep_body = [&](int kk, int s, int sn) {
-    const int p = bs - kk;
-    const CoefRow<T, kBwRow> cb = bring[s];
-    T e0 = T(0), e1 = T(0);
-    sfor<0, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      if constexpr (c % 2 == 0) e0 = fma(cb.template get<c>(), t1[c], e0);
-      else e1 = fma(cb.template get<c>(), t1[c], e1);
-    });
-    const T th = q - (e0 + e1);
-    zo[(kk + bso) & 1][R][lane] = th;
-    buf_st(rout, ro + roff(p), th);
-    {
-      const CoefRow<T, kBwRow>& cn = bring[sn];
-      T a2 = T(0);
-      sfor<0, NB>([&](auto cc) {
-        constexpr int c = decltype(cc)::value;
-        a2 = fma(cn.template get<8 + c>(), t1[c], a2);
-      });
-      q = wring[sn] - a2;
-    }
-    bring[s].load(bw + (size_t)max(p - kPre, 0) * bstep, lane);
-    wring[sn] = buf_ld<T>(rout, ro + roff(max(p - 1 - kPre, 0)));
-    lds_barrier();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) t1[b] = zo[(kk + bso) & 1][b][lane];
-  };
-  if (!top) {  // step sm + 3: wait for theta_m, then fold N2 theta_m into q
-    lds_barrier();
-#pragma unroll
-    for (int b = 0; b < NB; ++b) zy[b] = zx[(sm + 3) & 1][b][lane];
-    T a2 = T(0);
-    sfor<0, NB>([&](auto cc) {
-      constexpr int c = decltype(cc)::value;
-      a2 = fma(bring[0].template get<8 + c>(), zy[c], a2);
-    });
-    q -= a2;
-  }
-  bstep_body(0, 0, 1);
-  int kk = 1;
-  for (; kk + kPre <= cnt; kk += kPre) {
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) bstep_body(kk + u, (1 + u) % kPre, (2 + u) % kPre);
-  }
-#pragma unroll
-  for (int u = 0; u < kPre - 1; ++u)
-    if (kk + u < cnt) bstep_body(kk + u, (1 + u) % kPre, (2 + u) % kPre);
-  for (int u = 0; u < (top ? pad : 0); ++u) lds_barrier();
-  lds_barrier();  // every wavefront is done reading the buffers
-}
-
-template <typename T, int NS, int R = 0>
-__device__ __forceinline__ void twisted_dispatch(int w, const Dims& D,
-                                                 const OpCoef<T>& C, int cls,
-                                                 int v, int lane, int t, bool act,
-                                                 bool top,
-                                                 __amdgpu_buffer_rsrc_t rtau,
-                                                 __amdgpu_buffer_rsrc_t rout,
-                                                 T (*zo)[2 * NS][kWave],
-                                                 T (*zx)[2 * NS][kWave]) {
-  if constexpr (R < 2 * NS) {
-    if (w == R)
-      sweep_twisted<T, NS, R>(D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
-    else
-      twisted_dispatch<T, NS, R + 1>(w, D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
   }
 }
 
@@ -833,19 +592,353 @@ __device__ __forceinline__ void phi_tile(const Dims& D, const OpCoef<T>& C,
   }
 }
 
-// phi_tile with the twisted factor: 4n wavefronts per workgroup, zb holds
-// the two halves' exchange buffers.
+// Rows of a block row that one wavefront of the twisted solve handles.
+template <int NS>
+constexpr int kRowsPerWave = 2;
+template <int NS>
+constexpr int kWavesPerHalf = 2 * NS / kRowsPerWave<NS>;
+
+// Forward/backward substitution with the twisted factor of Phi_bar_{v,cls}
+// (factor_twisted: block rows ordered [0 .. m-1 | K-1 .. m+2 | m, m+1],
+// m = (K-2)/2, |B| = K-2-m bottom rows).  The top chain runs on one half of
+// the workgroup's wavefronts, the bottom chain on the other, so the two
+// chains proceed side by side and each wavefront passes about K/2 exchange
+// barriers per direction instead of K.  A wavefront handles rows R0 ..
+// R0+NR-1 of every block row for 64 time steps (one per lane); NR = 4 (n =
+// 2, 4) keeps the all-to-all exchange of z through LDS small against the
+// arithmetic.  Each half exchanges its z (theta) rows through its own LDS
+// buffer `zo`; the two middle block rows read the other half's buffer `zx`.
+// The work between barriers b-1 and b is step b, and step b writes slot
+// b & 1, so a slot is rewritten only after every reader has passed the next
+// barrier.  Steps (both halves pass the same 2 |B| + 5 barriers):
+//   0 .. |B|-1     top positions 0 .. m-1 (after |B| - m idle steps),
+//                  bottom positions 0 .. |B|-1 (rows K-1 .. m+2)
+//   |B|            top: z_m = p_m - M1_m z_{m-1} - X_t z_{m+2};
+//                  bottom: p_{m+1} -= M1 z_{m+2} + X_b1 z_{m-1}
+//   |B|+1          top: w_m;  bottom: z_{m+1} = p_{m+1} - X_b2 z_m
+//   |B|+2          bottom: theta_{m+1} = Linv_{m+1}' z_{m+1}
+//   |B|+3 ..       top: theta_m, theta_{m-1}, .., theta_0;  bottom (one step
+//                  later, once theta_m is known): theta_{m+2} .. theta_{K-1}
+// Software pipelining across the barriers: a step first issues the LDS read
+// of the previous position's z (theta), then does the work that does not
+// need it -- M2_i z_{i-2}, Linv_{i+1} tau_{i+1}, w_{i-2} = Linv_{i-2}'
+// z_{i-2} (backward: w_p - N2_p theta_{p+2}) -- while the read is in flight,
+// and only then the product with M1 (N1) that the exchange feeds.
+// Coefficient rows and tau are prefetched into register rings (slot =
+// position mod ring depth), w into a ring in the backward sweep; the rows
+// around the middle sit in registers from the start.  Row offsets go into the
+// buffer instructions' scalar offset.
+template <typename T, int NS, int R0, int NR>
+__device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
+                                              int cls, int v, int lane, int t,
+                                              bool act, bool top,
+                                              __amdgpu_buffer_rsrc_t rtau,
+                                              __amdgpu_buffer_rsrc_t rout,
+                                              T (*zo)[2 * NS][kWave],
+                                              T (*zx)[2 * NS][kWave]) {
+  constexpr int NB = 2 * NS;
+  constexpr int NT = R0 + NR;  // tau rows that rows R0 .. R0+NR-1 of z need
+  // ring depth: coefficient rows are fetched kP - 2 steps before first use
+  constexpr int kP = sizeof(T) == 4 ? 6 : 4;
+  constexpr int ES = sizeof(T);
+  constexpr int FD = kFwRow * ES / 4, BD = kBwRow * ES / 4;
+  using Row = CoefRow<T, kFwRow>;
+  using BRow = CoefRow<T, kBwRow>;
+  using I0 = std::integral_constant<int, 0>;
+  using I8 = std::integral_constant<int, 8>;
+  const int K = D.K;
+  const int m = (K - 2) / 2, nbot = K - 2 - m, pad = nbot - m;
+  const int len = top ? m + 1 : nbot + 1;  // chain positions, middle row last
+  const int rbase = top ? 0 : K - 1, rdir = top ? 1 : -1;
+  const unsigned istride = (unsigned)(NS * D.ldt * ES);
+  auto roff = [&](int k) { return (unsigned)(rbase + rdir * k) * istride; };
+  auto row_off = [&](int c) {  // byte offset of row c of block row 0 at lane t
+    return act ? (unsigned)((((size_t)(2 * v + c / NS) * K * NS + (c % NS)) * D.ldt + t) * ES)
+               : kOob;
+  };
+  unsigned rb[NT], ro[NR];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) rb[c] = row_off(c);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) ro[j] = row_off(R0 + j);
+  const size_t cv = (size_t)cls * D.V + v;
+  gptr<const unsigned> fw = glob(reinterpret_cast<const unsigned*>(
+      C.Fw + ((cv * fw_rows(K) + (top ? 0 : m + 2)) * NB + R0) * kFwRow));
+  gptr<const unsigned> bw = glob(reinterpret_cast<const unsigned*>(
+      C.Bw + ((cv * K + (top ? 0 : m + 1)) * NB + R0) * kBwRow));
+  const size_t fstep = (size_t)NB * FD, bstep = (size_t)NB * BD;
+  auto load_f = [&](Row* dst, gptr<const unsigned> base) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) dst[j].load(base + (size_t)j * FD, lane);
+  };
+  auto load_b = [&](BRow* dst, gptr<const unsigned> base) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) dst[j].load(base + (size_t)j * BD, lane);
+  };
+  Row cx[NR], cpm[NR], cmid[NR], clast[NR];
+  load_f(cx, glob(reinterpret_cast<const unsigned*>(C.Xw + (cv * NB + R0) * kFwRow)));
+  load_f(cpm, fw + (size_t)(len - 2) * fstep);
+  load_f(cmid, fw + (size_t)(len - 1) * fstep);
+  load_f(clast, fw + (size_t)len * fstep);
+
+  auto dot8 = [&](const auto& cf, auto base, const T* z, T acc) {
+    constexpr int B0 = decltype(base)::value;
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      acc = cf.template fmac<B0 + c>(acc, z[c]);
+    });
+    return acc;
+  };
+  auto dot8x2 = [&](const auto& cf, auto base, const T* z) {  // two chains
+    constexpr int B0 = decltype(base)::value;
+    T e0 = T(0), e1 = T(0);
+    sfor<0, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      if constexpr (c % 2 == 0) e0 = cf.template fmac<B0 + c>(e0, z[c]);
+      else e1 = cf.template fmac<B0 + c>(e1, z[c]);
+    });
+    return e0 + e1;
+  };
+  // row R0+J of Linv' z (upper triangle) and of Linv tau (lower triangle)
+  auto w_of = [&](auto jc, const Row& cf, const T* z) {
+    constexpr int J = decltype(jc)::value;
+    T acc = T(0);
+    sfor<R0 + J, NB>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      acc = cf.template fmac<24 + c>(acc, z[c]);
+    });
+    return acc;
+  };
+  auto linv_tau = [&](auto jc, const Row& cf, const T* tv) {
+    constexpr int J = decltype(jc)::value;
+    T acc = T(0);
+    sfor<0, R0 + J + 1>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      acc = cf.template fmac<16 + c>(acc, tv[c]);
+    });
+    return acc;
+  };
+  auto read_all = [&](T* dst, T (*buf)[kWave]) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dst[b] = buf[b][lane];
+  };
+
+  // ---------------------------------------------------------- forward
+  const int fso = top ? pad : 0;  // step of position 0
+  for (int u = 0; u < fso; ++u) lds_barrier();
+  T z2[NB], zn[NB], a[NR];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) z2[b] = T(0);
+  Row cring[kP][NR];
+  T tring[kP][NT];
+#pragma unroll
+  for (int u = 0; u < kP; ++u) {
+    load_f(cring[u], fw + (size_t)min(u, len) * fstep);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) tring[u][c] = buf_lds<T>(rtau, rb[c], roff(min(u, len - 1)));
+  }
+  // position 0: z_0 = Linv_0 tau_0; then a = Linv_1 tau_1
+  sfor<0, NR>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    zo[fso & 1][R0 + j][lane] = linv_tau(jc, cring[0][j], tring[0]);
+    a[j] = linv_tau(jc, cring[1][j], tring[1]);
+  });
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    tring[0][c] = buf_lds<T>(rtau, rb[c], roff(min(kP, len - 1)));
+    tring[1][c] = buf_lds<T>(rtau, rb[c], roff(min(kP + 1, len - 1)));
+  }
+  lds_barrier();
+  // Standard position i >= 1 (sp, s, sn: ring slots of rows i-1, i, i+1).
+  auto fstep_body = [&](int i, int sp, int s, int sn) {
+    read_all(zn, zo[(i - 1 + fso) & 1]);  // z_{i-1}
+    T pre[NR], an[NR];
+    sfor<0, NR>([&](auto jc) {  // independent of z_{i-1}
+      constexpr int j = decltype(jc)::value;
+      pre[j] = a[j] - dot8(cring[s][j], I8{}, z2, T(0));
+      if (i >= 2) buf_sts(rout, ro[j], roff(i - 2), w_of(jc, cring[sp][j], z2));
+      an[j] = linv_tau(jc, cring[sn][j], tring[sn]);
+    });
+    sfor<0, NR>([&](auto jc) {  // z_i = Linv_i tau_i - M2_i z_{i-2} - M1_i z_{i-1}
+      constexpr int j = decltype(jc)::value;
+      zo[(i + fso) & 1][R0 + j][lane] = pre[j] - dot8x2(cring[s][j], I0{}, zn);
+      a[j] = an[j];
+    });
+#pragma unroll
+    for (int b = 0; b < NB; ++b) z2[b] = zn[b];
+    load_f(cring[sp], fw + (size_t)min(i - 1 + kP, len) * fstep);
+    const int it = min(i + 1 + kP, len - 1);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) tring[sn][c] = buf_lds<T>(rtau, rb[c], roff(it));
+    lds_barrier();
+  };
+  int i = 1;
+  for (; i + kP <= len - 1; i += kP) {
+#pragma unroll
+    for (int u = 0; u < kP; ++u) fstep_body(i + u, u % kP, (1 + u) % kP, (2 + u) % kP);
+  }
+#pragma unroll
+  for (int u = 0; u < kP - 1; ++u)
+    if (i + u < len - 1) fstep_body(i + u, u % kP, (1 + u) % kP, (2 + u) % kP);
+
+  // the backward sweep's first coefficient rows, fetched a few steps early
+  const int bs = top ? len - 1 : len - 2, cnt = bs + 1;
+  BRow bring[kP][NR];
+#pragma unroll
+  for (int u = 0; u < kP; ++u) load_b(bring[u], bw + (size_t)max(bs - u, 0) * bstep);
+
+  // ---------------------------------------------------------- middle rows
+  // Here: z2 = z of position len-3, a = Linv tau of position len-1, and
+  // z of position len-2 in zo.
+  const int sm = nbot;  // step of z_m
+  T zy[NB], pre[NR];
+  read_all(zn, zo[(sm - 1) & 1]);  // top: z_{m-1}; bottom: z_{m+2}
+  read_all(zy, zx[(sm - 1) & 1]);  // top: z_{m+2}; bottom: z_{m-1}
+  sfor<0, NR>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    pre[j] = a[j] - dot8(cmid[j], I8{}, z2, T(0));
+    buf_sts(rout, ro[j], roff(len - 3), w_of(jc, cpm[j], z2));
+    buf_sts(rout, ro[j], roff(len - 2), w_of(jc, cmid[j], zn));
+  });
+  if (top) {
+    sfor<0, NR>([&](auto jc) {  // z_m
+      constexpr int j = decltype(jc)::value;
+      zo[sm & 1][R0 + j][lane] = pre[j] - (dot8x2(cmid[j], I0{}, zn) + dot8x2(cx[j], I0{}, zy));
+    });
+    lds_barrier();
+    read_all(zn, zo[sm & 1]);
+    sfor<0, NR>([&](auto jc) {  // w_m
+      constexpr int j = decltype(jc)::value;
+      buf_sts(rout, ro[j], roff(len - 1), w_of(jc, clast[j], zn));
+    });
+    lds_barrier();
+  } else {
+    sfor<0, NR>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      pre[j] -= dot8x2(cmid[j], I0{}, zn) + dot8x2(cx[j], I8{}, zy);
+    });
+    lds_barrier();
+    read_all(zy, zx[sm & 1]);  // z_m
+    sfor<0, NR>([&](auto jc) {  // z_{m+1}
+      constexpr int j = decltype(jc)::value;
+      zo[(sm + 1) & 1][R0 + j][lane] =
+          pre[j] - dot8x2(cx[j], std::integral_constant<int, 16>{}, zy);
+    });
+    lds_barrier();
+    read_all(zn, zo[(sm + 1) & 1]);
+    sfor<0, NR>([&](auto jc) {  // theta_{m+1}
+      constexpr int j = decltype(jc)::value;
+      const T th = w_of(jc, clast[j], zn);
+      zo[(sm + 2) & 1][R0 + j][lane] = th;
+      buf_sts(rout, ro[j], roff(len - 1), th);
+    });
+  }
+  lds_barrier();  // step sm + 2
+
+  // ---------------------------------------------------------- backward
+  // Backward step kk handles position p = bs - kk:
+  //   theta_p = (w_p - N2_p theta_{p+2}) - N1_p theta_{p+1}
+  // with theta_{p+1} from the exchange and theta_{p+2} in registers (t2).
+  T t2[NB], tn[NB];
+  const int bso = top ? sm + 3 : sm + 4;  // step of backward step 0
+  T wring[kP][NR];
+#pragma unroll
+  for (int u = 0; u < kP; ++u)
+#pragma unroll
+    for (int j = 0; j < NR; ++j) wring[u][j] = buf_lds<T>(rout, ro[j], roff(max(bs - u, 0)));
+  // theta_p = q - N1_p theta_{p+1} for the rows of this wavefront; refill
+  auto bfinish = [&](int kk, int p, int s, const T* q) {
+    sfor<0, NR>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const T th = q[j] - dot8x2(bring[s][j], I0{}, tn);
+      zo[(kk + bso) & 1][R0 + j][lane] = th;
+      buf_sts(rout, ro[j], roff(p), th);
+    });
+    load_b(bring[s], bw + (size_t)max(p - kP, 0) * bstep);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) wring[s][j] = buf_lds<T>(rout, ro[j], roff(max(p - kP, 0)));
+    lds_barrier();
+  };
+  if (top) {  // step sm + 3: theta_m = w_m - N1_m theta_{m+1}
+    read_all(tn, zx[(sm + 2) & 1]);
+    T q[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) q[j] = wring[0][j];
+    bfinish(0, bs, 0, q);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) t2[b] = tn[b];
+  } else {  // step sm + 3 idle; step sm + 4: theta_{m+2}, once theta_m is known
+    read_all(t2, zo[(sm + 2) & 1]);  // theta_{m+1}
+    lds_barrier();
+    read_all(tn, zx[(sm + 3) & 1]);  // theta_m
+    // roles swapped for this row: N1 pairs with theta_{m+1}, N2 with theta_m
+    T q[NR];
+    sfor<0, NR>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      q[j] = wring[0][j] - dot8x2(bring[0][j], I0{}, t2);
+      const T th = q[j] - dot8x2(bring[0][j], I8{}, tn);
+      zo[bso & 1][R0 + j][lane] = th;
+      buf_sts(rout, ro[j], roff(bs), th);
+    });
+    load_b(bring[0], bw + (size_t)max(bs - kP, 0) * bstep);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) wring[0][j] = buf_lds<T>(rout, ro[j], roff(max(bs - kP, 0)));
+    lds_barrier();
+  }
+  auto bstep_body = [&](int kk, int s) {
+    read_all(tn, zo[(kk - 1 + bso) & 1]);  // theta_{p+1}
+    T q[NR];
+    sfor<0, NR>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      q[j] = wring[s][j] - dot8(bring[s][j], I8{}, t2, T(0));
+    });
+    bfinish(kk, bs - kk, s, q);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) t2[b] = tn[b];
+  };
+  int kk = 1;
+  for (; kk + kP <= cnt; kk += kP) {
+#pragma unroll
+    for (int u = 0; u < kP; ++u) bstep_body(kk + u, (1 + u) % kP);
+  }
+#pragma unroll
+  for (int u = 0; u < kP - 1; ++u)
+    if (kk + u < cnt) bstep_body(kk + u, (1 + u) % kP);
+  for (int u = 0; u < (top ? pad : 0); ++u) lds_barrier();
+  lds_barrier();  // every wavefront is done reading the buffers
+}
+
+template <typename T, int NS, int W = 0>
+__device__ __forceinline__ void twisted_dispatch(int w, const Dims& D,
+                                                 const OpCoef<T>& C, int cls,
+                                                 int v, int lane, int t, bool act,
+                                                 bool top,
+                                                 __amdgpu_buffer_rsrc_t rtau,
+                                                 __amdgpu_buffer_rsrc_t rout,
+                                                 T (*zo)[2 * NS][kWave],
+                                                 T (*zx)[2 * NS][kWave]) {
+  constexpr int NR = kRowsPerWave<NS>;
+  if constexpr (W < kWavesPerHalf<NS>) {
+    if (w == W)
+      sweep_twisted<T, NS, W * NR, NR>(D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
+    else
+      twisted_dispatch<T, NS, W + 1>(w, D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
+  }
+}
+
+// phi_tile with the twisted factor: 2 kWavesPerHalf wavefronts per
+// workgroup, zb holds the two halves' exchange buffers.
 template <typename T, int NS>
 __device__ __forceinline__ void phi_tile_twisted(const Dims& D, const OpCoef<T>& C,
                                                  const T* __restrict__ tau,
                                                  T* __restrict__ out, int qt_distinct,
                                                  int v, int chunk,
                                                  T (*zb)[2][2 * NS][kWave]) {
-  constexpr int NB = 2 * NS;
+  constexpr int NB = 2 * NS, WH = kWavesPerHalf<NS>;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x >> 6);
-  const bool top = w < NB;
-  const int R = top ? w : w - NB;
+  const bool top = w < WH;
+  const int wi = top ? w : w - WH;
   const int t0 = chunk * kWave;
   const int t = t0 + lane;
   const int T_ = D.T;
@@ -855,18 +948,19 @@ __device__ __forceinline__ void phi_tile_twisted(const Dims& D, const OpCoef<T>&
   const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, bytes);
   T(*zo)[NB][kWave] = zb[top ? 0 : 1];
   T(*zx)[NB][kWave] = zb[top ? 1 : 0];
-  twisted_dispatch<T, NS>(R, D, C, 0, v, lane, t,
+  twisted_dispatch<T, NS>(wi, D, C, 0, v, lane, t,
                           valid && t >= 1 && !(qt_distinct && t == T_), top, rtau, rout,
                           zo, zx);
   if (qt_distinct && t0 <= T_ && T_ < t0 + kWave)
-    twisted_dispatch<T, NS>(R, D, C, 1, v, lane, t, valid && t == T_, top, rtau, rout, zo,
+    twisted_dispatch<T, NS>(wi, D, C, 1, v, lane, t, valid && t == T_, top, rtau, rout, zo,
                             zx);
-  if (chunk == 0) {  // t = 0: theta = Q tau per node, block rows split over the halves
+  if (chunk == 0) {  // t = 0: theta = Q tau per node; item = (block row i, row R)
     const size_t nn = (size_t)NS * NS;
-    const int h = R / NS, a = R % NS;
     gptr<const T> tg = glob(tau);
     gptr<T> og = glob(out);
-    for (int i = lane + (top ? 0 : kWave); i < D.K; i += 2 * kWave) {
+    for (int item = threadIdx.x; item < D.K * NB; item += 2 * WH * kWave) {
+      const int i = item / NB, R = item - (item / NB) * NB;
+      const int h = R / NS, a = R % NS;
       const int p = (2 * v + h) * D.K + i;
       gptr<const T> Qp = glob(C.Qm) + p * nn + a * NS;
       T acc = T(0);

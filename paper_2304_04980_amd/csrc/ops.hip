@@ -73,7 +73,7 @@ __global__ __launch_bounds__(2 * NS * kWave) void k_phi_solve(
 }
 
 template <typename T, int NS>
-__global__ __launch_bounds__(4 * NS * kWave) void k_phi_solve_twisted(
+__global__ __launch_bounds__(2 * kWavesPerHalf<NS> * kWave) void k_phi_solve_twisted(
     Dims D, OpCoef<T> C, const T* __restrict__ tau, T* __restrict__ out,
     const Scalars* sc, int check, int qt_distinct) {
   if (is_done(sc, check)) return;
@@ -192,7 +192,7 @@ void phi_solve(const Dims& D, const OpCoef<T>& C, const T* tau, T* out,
   hipLaunchKernelGGL((k_phi_solve<T, NS>), g, dim3(2 * NS * kWave), 0, s, D, C, \
                      tau, out, sc, check_done, qt_distinct)
 #define CALL_TW(NS)                                                            \
-  hipLaunchKernelGGL((k_phi_solve_twisted<T, NS>), g, dim3(4 * NS * kWave), 0, s, \
+  hipLaunchKernelGGL((k_phi_solve_twisted<T, NS>), g, dim3(2 * kWavesPerHalf<NS> * kWave), 0, s, \
                      D, C, tau, out, sc, check_done, qt_distinct)
   if (twisted(D)) {
     LQG_DISPATCH_N(D.n, CALL_TW)
