@@ -597,6 +597,19 @@ template <int NS>
 constexpr int kRowsPerWave = 2;
 template <int NS>
 constexpr int kWavesPerHalf = 2 * NS / kRowsPerWave<NS>;
+// LDS of the twisted solve: the two halves' exchange buffers, and, for FP64,
+// in the rest of the 160 KiB of a CU, the last kWKeep<T, NS> positions of
+// each chain's parked w (so only the earlier ones make the round trip to
+// HBM).  For FP32 the solve is not bound by that traffic and measured faster
+// without it (the full-size allocation also limits a CU to one workgroup).
+constexpr int kLdsBytes = 160 * 1024;
+template <typename T, int NS>
+constexpr int kWKeep = sizeof(T) == 4 ? 0
+                                      : (kLdsBytes - 2 * 2 * 2 * NS * kWave * (int)sizeof(T)) /
+                                                (2 * 2 * NS * kWave * (int)sizeof(T)) -
+                                            1;
+template <typename T, int NS>
+constexpr int kWKeepAlloc = kWKeep<T, NS> + 1;  // + a spare slot
 
 // Forward/backward substitution with the twisted factor of Phi_bar_{v,cls}
 // (factor_twisted: block rows ordered [0 .. m-1 | K-1 .. m+2 | m, m+1],
@@ -635,7 +648,8 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
                                               __amdgpu_buffer_rsrc_t rtau,
                                               __amdgpu_buffer_rsrc_t rout,
                                               T (*zo)[2 * NS][kWave],
-                                              T (*zx)[2 * NS][kWave]) {
+                                              T (*zx)[2 * NS][kWave],
+                                              T (*wl)[2 * NS][kWave]) {
   constexpr int NB = 2 * NS;
   constexpr int NT = R0 + NR;  // tau rows that rows R0 .. R0+NR-1 of z need
   // ring depth: coefficient rows are fetched kP - 2 steps before first use
@@ -722,6 +736,32 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
 #pragma unroll
     for (int b = 0; b < NB; ++b) dst[b] = buf[b][lane];
   };
+  // Parked w of position k, row R0+j: LDS for the last kWKeep positions,
+  // else HBM.  Without branches, which would split the pipelined steps: both
+  // accesses are issued, the HBM one with an out-of-range offset when the
+  // value lives in LDS (store dropped, load returns 0), the LDS one at the
+  // spare slot kWKeep when it lives in HBM, and a select picks the result.
+  constexpr int kKeep = kWKeep<T, NS>;
+  const int kl = max(0, len - kKeep);
+  auto put_w = [&](int k, int j, T val) {
+    if constexpr (kKeep == 0) {
+      buf_sts(rout, ro[j], roff(k), val);
+    } else {
+      const bool in_lds = k >= kl;
+      wl[in_lds ? k - kl : kKeep][R0 + j][lane] = val;
+      buf_sts(rout, in_lds ? kOob : ro[j], roff(k), val);
+    }
+  };
+  auto get_w = [&](int k, int j) {
+    if constexpr (kKeep == 0) {
+      return buf_lds<T>(rout, ro[j], roff(k));
+    } else {
+      const bool in_lds = k >= kl;
+      const T a = wl[in_lds ? k - kl : kKeep][R0 + j][lane];
+      const T b = buf_lds<T>(rout, in_lds ? kOob : ro[j], roff(k));
+      return in_lds ? a : b;
+    }
+  };
 
   // ---------------------------------------------------------- forward
   const int fso = top ? pad : 0;  // step of position 0
@@ -756,7 +796,7 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     sfor<0, NR>([&](auto jc) {  // independent of z_{i-1}
       constexpr int j = decltype(jc)::value;
       pre[j] = a[j] - dot8(cring[s][j], I8{}, z2, T(0));
-      if (i >= 2) buf_sts(rout, ro[j], roff(i - 2), w_of(jc, cring[sp][j], z2));
+      if (i >= 2) put_w(i - 2, j, w_of(jc, cring[sp][j], z2));
       an[j] = linv_tau(jc, cring[sn][j], tring[sn]);
     });
     sfor<0, NR>([&](auto jc) {  // z_i = Linv_i tau_i - M2_i z_{i-2} - M1_i z_{i-1}
@@ -797,8 +837,8 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
   sfor<0, NR>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     pre[j] = a[j] - dot8(cmid[j], I8{}, z2, T(0));
-    buf_sts(rout, ro[j], roff(len - 3), w_of(jc, cpm[j], z2));
-    buf_sts(rout, ro[j], roff(len - 2), w_of(jc, cmid[j], zn));
+    put_w(len - 3, j, w_of(jc, cpm[j], z2));
+    put_w(len - 2, j, w_of(jc, cmid[j], zn));
   });
   if (top) {
     sfor<0, NR>([&](auto jc) {  // z_m
@@ -809,7 +849,7 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     read_all(zn, zo[sm & 1]);
     sfor<0, NR>([&](auto jc) {  // w_m
       constexpr int j = decltype(jc)::value;
-      buf_sts(rout, ro[j], roff(len - 1), w_of(jc, clast[j], zn));
+      put_w(len - 1, j, w_of(jc, clast[j], zn));
     });
     lds_barrier();
   } else {
@@ -845,7 +885,7 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
 #pragma unroll
   for (int u = 0; u < kP; ++u)
 #pragma unroll
-    for (int j = 0; j < NR; ++j) wring[u][j] = buf_lds<T>(rout, ro[j], roff(max(bs - u, 0)));
+    for (int j = 0; j < NR; ++j) wring[u][j] = get_w(max(bs - u, 0), j);
   // theta_p = q - N1_p theta_{p+1} for the rows of this wavefront; refill
   auto bfinish = [&](int kk, int p, int s, const T* q) {
     sfor<0, NR>([&](auto jc) {
@@ -856,7 +896,7 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     });
     load_b(bring[s], bw + (size_t)max(p - kP, 0) * bstep);
 #pragma unroll
-    for (int j = 0; j < NR; ++j) wring[s][j] = buf_lds<T>(rout, ro[j], roff(max(p - kP, 0)));
+    for (int j = 0; j < NR; ++j) wring[s][j] = get_w(max(p - kP, 0), j);
     lds_barrier();
   };
   if (top) {  // step sm + 3: theta_m = w_m - N1_m theta_{m+1}
@@ -882,7 +922,7 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     });
     load_b(bring[0], bw + (size_t)max(bs - kP, 0) * bstep);
 #pragma unroll
-    for (int j = 0; j < NR; ++j) wring[0][j] = buf_lds<T>(rout, ro[j], roff(max(bs - kP, 0)));
+    for (int j = 0; j < NR; ++j) wring[0][j] = get_w(max(bs - kP, 0), j);
     lds_barrier();
   }
   auto bstep_body = [&](int kk, int s) {
@@ -916,24 +956,28 @@ __device__ __forceinline__ void twisted_dispatch(int w, const Dims& D,
                                                  __amdgpu_buffer_rsrc_t rtau,
                                                  __amdgpu_buffer_rsrc_t rout,
                                                  T (*zo)[2 * NS][kWave],
-                                                 T (*zx)[2 * NS][kWave]) {
+                                                 T (*zx)[2 * NS][kWave],
+                                                 T (*wl)[2 * NS][kWave]) {
   constexpr int NR = kRowsPerWave<NS>;
   if constexpr (W < kWavesPerHalf<NS>) {
     if (w == W)
-      sweep_twisted<T, NS, W * NR, NR>(D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
+      sweep_twisted<T, NS, W * NR, NR>(D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx,
+                                       wl);
     else
-      twisted_dispatch<T, NS, W + 1>(w, D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx);
+      twisted_dispatch<T, NS, W + 1>(w, D, C, cls, v, lane, t, act, top, rtau, rout, zo, zx,
+                                     wl);
   }
 }
 
 // phi_tile with the twisted factor: 2 kWavesPerHalf wavefronts per
-// workgroup, zb holds the two halves' exchange buffers.
+// workgroup, zb holds the two halves' exchange buffers, wb their parked w.
 template <typename T, int NS>
 __device__ __forceinline__ void phi_tile_twisted(const Dims& D, const OpCoef<T>& C,
                                                  const T* __restrict__ tau,
                                                  T* __restrict__ out, int qt_distinct,
                                                  int v, int chunk,
-                                                 T (*zb)[2][2 * NS][kWave]) {
+                                                 T (*zb)[2][2 * NS][kWave],
+                                                 T (*wb)[kWKeepAlloc<T, NS>][2 * NS][kWave]) {
   constexpr int NB = 2 * NS, WH = kWavesPerHalf<NS>;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x >> 6);
@@ -948,12 +992,13 @@ __device__ __forceinline__ void phi_tile_twisted(const Dims& D, const OpCoef<T>&
   const __amdgpu_buffer_rsrc_t rout = make_rsrc(out, bytes);
   T(*zo)[NB][kWave] = zb[top ? 0 : 1];
   T(*zx)[NB][kWave] = zb[top ? 1 : 0];
+  T(*wl)[NB][kWave] = wb[top ? 0 : 1];
   twisted_dispatch<T, NS>(wi, D, C, 0, v, lane, t,
                           valid && t >= 1 && !(qt_distinct && t == T_), top, rtau, rout,
-                          zo, zx);
+                          zo, zx, wl);
   if (qt_distinct && t0 <= T_ && T_ < t0 + kWave)
     twisted_dispatch<T, NS>(wi, D, C, 1, v, lane, t, valid && t == T_, top, rtau, rout, zo,
-                            zx);
+                            zx, wl);
   if (chunk == 0) {  // t = 0: theta = Q tau per node; item = (block row i, row R)
     const size_t nn = (size_t)NS * NS;
     gptr<const T> tg = glob(tau);

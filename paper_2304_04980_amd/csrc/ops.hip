@@ -78,10 +78,11 @@ __global__ __launch_bounds__(2 * kWavesPerHalf<NS> * kWave) void k_phi_solve_twi
     const Scalars* sc, int check, int qt_distinct) {
   if (is_done(sc, check)) return;
   __shared__ T zb[2][2][2 * NS][kWave];
+  __shared__ T wb[2][kWKeepAlloc<T, NS>][2 * NS][kWave];
   const int nchunks = time_chunks(D);
   const int lb = xcd_block();
   if (lb >= D.V * nchunks) return;
-  phi_tile_twisted<T, NS>(D, C, tau, out, qt_distinct, lb / nchunks, lb % nchunks, zb);
+  phi_tile_twisted<T, NS>(D, C, tau, out, qt_distinct, lb / nchunks, lb % nchunks, zb, wb);
 }
 
 // x_t = Q_t^-1 (-dl_t + [t<T] A_hat' dl_{t+1}),  u_t = R^-1 B' dl_{t+1}
