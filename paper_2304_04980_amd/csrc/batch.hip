@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void kb_omega(LQG_BATCH_ARGS, int rho, int th,
     const BatchProb& P = probs[w.prob];
     if (gated_out(scs[w.prob], check)) continue;
     omega_tile<double, NS>(P.D, op64(P.C), rho >= 0 ? P.v[rho] : nullptr,
-                           P.v[th], P.v[tau], w.a, w.b);
+                           P.v[th], P.v[tau], w.a, w.b, w.b + 1);
   }
 }
 
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void kb_xi(LQG_BATCH_ARGS, int r, int dl,
     const BatchProb& P = probs[w.prob];
     if (gated_out(scs[w.prob], check)) continue;
     xi_tile<double, NS>(P.D, op64(P.C), r >= 0 ? P.v[r] : nullptr, P.v[dl],
-                        P.v[rho], w.a, w.b);
+                        P.v[rho], w.a, w.b, w.b + 1);
   }
 }
 

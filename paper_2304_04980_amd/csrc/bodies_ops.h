@@ -84,153 +84,6 @@ __device__ __forceinline__ bool is_done(const Scalars* sc, int check) {
   return check && __builtin_nontemporal_load(&sc->done) != 0;
 }
 
-// Node tiles: 4 nodes (one per wavefront of a 256-thread workgroup) x 64
-// consecutive time steps (one per lane).  Tile (group, chunk) covers nodes
-// 4 group .. 4 group + 3 and t = 64 chunk .. 64 chunk + 63.
-__host__ __device__ inline int node_groups(const Dims& D) {
-  return (D.real_nodes + 3) / 4;
-}
-__host__ __device__ inline int time_chunks(const Dims& D) {
-  return (D.Tt + kWave - 1) / kWave;
-}
-__device__ __forceinline__ void node_coords(int group, int chunk, int* p, int* t) {
-  *p = uniform(group * 4 + (threadIdx.x >> 6));
-  *t = chunk * kWave + (threadIdx.x & (kWave - 1));
-}
-
-// ---------------------------------------------------------------------------
-// y = Delta d on one node tile; the tile's FP64 partial sum of y'd is written
-// to *partial (when non-null) by thread 0.  Every thread of the workgroup
-// must call this (it contains a workgroup reduction).
-//   y_t(p) = Q_t^-1 d_t(p)
-//          + [t>=1] ( sum_13 G[p][k] d_t(p+o_k) - sum_5 Cdn[p][k] d_{t-1}(p+o_k) )
-//          - [t<T]  sum_5 Cup[p][k] d_{t+1}(p+o_k)
-template <typename T, int NS>
-__device__ __forceinline__ void delta_tile(const Dims& D, const OpCoef<T>& C,
-                                           const T* __restrict__ d,
-                                           T* __restrict__ y,
-                                           double* __restrict__ partial,
-                                           int group, int chunk) {
-  int p, t;
-  node_coords(group, chunk, &p, &t);
-  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
-  const size_t nn = (size_t)NS * NS;
-  double dot = 0.0;
-  if (p < D.real_nodes && t < D.Tt) {
-    const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-    T self[NS], acc[NS], nb[NS];
-#pragma unroll
-    for (int a = 0; a < NS; ++a) acc[a] = T(0);
-    load_node<NS>(d, p, t, ldt, self);
-    mv_add<NS>(C.Qi + p * nn, self, acc);
-    if (t == T_) mv_add<NS>(C.QTd + p * nn, self, acc);
-    if (t >= 1) {
-#pragma unroll
-      for (int k = 0; k < 13; ++k) {
-        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_node<NS>(d, jq * K + iq, t, ldt, nb);
-        mv_add<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
-      }
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_node<NS>(d, jq * K + iq, t - 1, ldt, nb);
-        mv_sub<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
-      }
-    }
-    if (t < T_) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_node<NS>(d, jq * K + iq, t + 1, ldt, nb);
-        mv_sub<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
-      }
-    }
-    store_node<NS>(y, p, t, ldt, acc);
-#pragma unroll
-    for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
-  }
-  dot = block_sum<256>(dot);
-  if (partial && threadIdx.x == 0) *partial = dot;
-}
-
-// tau = rho + Omega~ theta on one node tile, Omega~ = Phi~ - Psi~: minus the
-// blocks of Psi_hat_t (t >= 1) that couple different super-columns;
-// Omega_hat_0 = 0.  rho may be null (zero).
-template <typename T, int NS>
-__device__ __forceinline__ void omega_tile(const Dims& D, const OpCoef<T>& C,
-                                           const T* __restrict__ rho,
-                                           const T* __restrict__ th,
-                                           T* __restrict__ tau, int group,
-                                           int chunk) {
-  int p, t;
-  node_coords(group, chunk, &p, &t);
-  const int ldt = D.ldt, K = D.K, N = D.N;
-  const size_t nn = (size_t)NS * NS;
-  if (p >= D.real_nodes || t >= D.Tt) return;
-  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-  T acc[NS], nb[NS];
-  if (rho) load_node<NS>(rho, p, t, ldt, acc);
-  else
-#pragma unroll
-    for (int a = 0; a < NS; ++a) acc[a] = T(0);
-  if (t >= 1) {
-#pragma unroll
-    for (int k = 0; k < 13; ++k) {
-      const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-      if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-      if ((jq >> 1) == (j >> 1)) continue;  // same super-column: inside Phi~
-      load_node<NS>(th, jq * K + iq, t, ldt, nb);
-      mv_sub<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
-    }
-  }
-  store_node<NS>(tau, p, t, ldt, acc);
-}
-
-// rho = r + Xi~ dl on one node tile, Xi~ = Psi~ - Delta:
-//   (Xi~ dl)_t(p) = [t>=1] sum_5 Cdn[p][k] dl_{t-1}(q) + [t<T] sum_5 Cup[p][k] dl_{t+1}(q)
-// r may be null (zero).
-template <typename T, int NS>
-__device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
-                                        const T* __restrict__ r,
-                                        const T* __restrict__ dl,
-                                        T* __restrict__ rho, int group,
-                                        int chunk) {
-  int p, t;
-  node_coords(group, chunk, &p, &t);
-  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
-  const size_t nn = (size_t)NS * NS;
-  if (p >= D.real_nodes || t >= D.Tt) return;
-  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-  T acc[NS], nb[NS];
-  if (r) load_node<NS>(r, p, t, ldt, acc);
-  else
-#pragma unroll
-    for (int a = 0; a < NS; ++a) acc[a] = T(0);
-  if (t >= 1) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-      if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-      load_node<NS>(dl, jq * K + iq, t - 1, ldt, nb);
-      mv_add<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
-    }
-  }
-  if (t < T_) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-      if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-      load_node<NS>(dl, jq * K + iq, t + 1, ldt, nb);
-      mv_add<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
-    }
-  }
-  store_node<NS>(rho, p, t, ldt, acc);
-}
-
 // ---------------------------------------------------------------------------
 // Buffer-resource access for the block solve: a lane outside the current
 // factor class uses an out-of-range offset, whose loads return 0 and whose
@@ -294,6 +147,190 @@ __device__ __forceinline__ void sfor(F&& f) {
   if constexpr (B < E) {
     f(std::integral_constant<int, B>{});
     sfor<B + 1, E>(f);
+  }
+}
+
+// Node tiles: 4 nodes (one per wavefront of a 256-thread workgroup) x time
+// chunks c0 .. c1-1 of 64 consecutive steps (one per lane).  Group g covers
+// nodes 4 g .. 4 g + 3 and t = 64 c .. 64 c + 63 for each chunk c.  A
+// wavefront that runs several chunks of its node reloads the node's operator
+// blocks from the scalar cache rather than from L2.
+__host__ __device__ inline int node_groups(const Dims& D) {
+  return (D.real_nodes + 3) / 4;
+}
+__host__ __device__ inline int time_chunks(const Dims& D) {
+  return (D.Tt + kWave - 1) / kWave;
+}
+__device__ __forceinline__ int tile_node(int group) {
+  return uniform(group * 4 + (threadIdx.x >> 6));
+}
+
+// The NS components of node q at the lane's time offset toff (bytes), by
+// buffer loads whose node offset is wave-uniform (scalar offset field).
+template <int NS, typename T>
+__device__ __forceinline__ void load_nb(__amdgpu_buffer_rsrc_t r, unsigned toff, int q,
+                                        int ldt, T (&x)[NS]) {
+  const unsigned base = (unsigned)q * (unsigned)(NS * ldt * sizeof(T));
+#pragma unroll
+  for (int c = 0; c < NS; ++c)
+    x[c] = buf_lds<T>(r, toff, base + (unsigned)(c * ldt * sizeof(T)));
+}
+template <int NS, typename T>
+__device__ __forceinline__ void store_nb(__amdgpu_buffer_rsrc_t r, unsigned toff, int q,
+                                         int ldt, const T (&x)[NS]) {
+  const unsigned base = (unsigned)q * (unsigned)(NS * ldt * sizeof(T));
+#pragma unroll
+  for (int c = 0; c < NS; ++c) buf_sts(r, toff, base + (unsigned)(c * ldt * sizeof(T)), x[c]);
+}
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const Dims& D, const T* v) {
+  return make_rsrc(v, D.vlen * (long long)sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// y = Delta d on one node tile (one time chunk); the tile's FP64 partial sum
+// of y'd is written to *partial (when non-null) by thread 0.  Every thread of the workgroup
+// must call this (it contains a workgroup reduction).
+//   y_t(p) = Q_t^-1 d_t(p)
+//          + [t>=1] ( sum_13 G[p][k] d_t(p+o_k) - sum_5 Cdn[p][k] d_{t-1}(p+o_k) )
+//          - [t<T]  sum_5 Cup[p][k] d_{t+1}(p+o_k)
+template <typename T, int NS>
+__device__ __forceinline__ void delta_tile(const Dims& D, const OpCoef<T>& C,
+                                           const T* __restrict__ d,
+                                           T* __restrict__ y,
+                                           double* __restrict__ partial,
+                                           int group, int chunk) {
+  const int p = tile_node(group);
+  const int t = chunk * kWave + (threadIdx.x & (kWave - 1));
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const size_t nn = (size_t)NS * NS;
+  double dot = 0.0;
+  if (p < D.real_nodes && t < D.Tt) {
+    const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+    T self[NS], acc[NS], nb[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = T(0);
+    load_node<NS>(d, p, t, ldt, self);
+    mv_add<NS>(C.Qi + p * nn, self, acc);
+    if (t == T_) mv_add<NS>(C.QTd + p * nn, self, acc);
+    if (t >= 1) {
+#pragma unroll
+      for (int k = 0; k < 13; ++k) {
+        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_node<NS>(d, jq * K + iq, t, ldt, nb);
+        mv_add<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_node<NS>(d, jq * K + iq, t - 1, ldt, nb);
+        mv_sub<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
+      }
+    }
+    if (t < T_) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_node<NS>(d, jq * K + iq, t + 1, ldt, nb);
+        mv_sub<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
+      }
+    }
+    store_node<NS>(y, p, t, ldt, acc);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
+  }
+  dot = block_sum<256>(dot);
+  if (partial && threadIdx.x == 0) *partial = dot;
+}
+
+// tau = rho + Omega~ theta on one node tile, Omega~ = Phi~ - Psi~: minus the
+// blocks of Psi_hat_t (t >= 1) that couple different super-columns;
+// Omega_hat_0 = 0.  rho may be null (zero).
+template <typename T, int NS>
+__device__ __forceinline__ void omega_tile(const Dims& D, const OpCoef<T>& C,
+                                           const T* __restrict__ rho,
+                                           const T* __restrict__ th,
+                                           T* __restrict__ tau, int group, int c0,
+                                           int c1) {
+  const int p = tile_node(group);
+  const int ldt = D.ldt, K = D.K, N = D.N;
+  const size_t nn = (size_t)NS * NS;
+  constexpr unsigned ES = sizeof(T);
+  if (p >= D.real_nodes) return;
+  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  const __amdgpu_buffer_rsrc_t rth = vec_rsrc(D, th), rtau = vec_rsrc(D, tau);
+  const __amdgpu_buffer_rsrc_t rrho = vec_rsrc(D, rho ? rho : th);
+  for (int chunk = c0; chunk < c1; ++chunk) {
+    const int t = chunk * kWave + (threadIdx.x & (kWave - 1));
+    if (t >= D.Tt) continue;
+    const unsigned toff = (unsigned)t * ES;
+    T acc[NS], nb[NS];
+    if (rho) load_nb<NS>(rrho, toff, p, ldt, acc);
+    else
+#pragma unroll
+      for (int a = 0; a < NS; ++a) acc[a] = T(0);
+    if (t >= 1) {
+#pragma unroll
+      for (int k = 0; k < 13; ++k) {
+        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        if ((jq >> 1) == (j >> 1)) continue;  // same super-column: inside Phi~
+        load_nb<NS>(rth, toff, jq * K + iq, ldt, nb);
+        mv_sub<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
+      }
+    }
+    store_nb<NS>(rtau, toff, p, ldt, acc);
+  }
+}
+
+// rho = r + Xi~ dl on one node tile, Xi~ = Psi~ - Delta:
+//   (Xi~ dl)_t(p) = [t>=1] sum_5 Cdn[p][k] dl_{t-1}(q) + [t<T] sum_5 Cup[p][k] dl_{t+1}(q)
+// r may be null (zero).
+template <typename T, int NS>
+__device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
+                                        const T* __restrict__ r,
+                                        const T* __restrict__ dl,
+                                        T* __restrict__ rho, int group, int c0,
+                                        int c1) {
+  const int p = tile_node(group);
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const size_t nn = (size_t)NS * NS;
+  constexpr unsigned ES = sizeof(T);
+  if (p >= D.real_nodes) return;
+  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  const __amdgpu_buffer_rsrc_t rdl = vec_rsrc(D, dl), rrho = vec_rsrc(D, rho);
+  const __amdgpu_buffer_rsrc_t rr = vec_rsrc(D, r ? r : dl);
+  for (int chunk = c0; chunk < c1; ++chunk) {
+    const int t = chunk * kWave + (threadIdx.x & (kWave - 1));
+    if (t >= D.Tt) continue;
+    const unsigned toff = (unsigned)t * ES;
+    T acc[NS], nb[NS];
+    if (r) load_nb<NS>(rr, toff, p, ldt, acc);
+    else
+#pragma unroll
+      for (int a = 0; a < NS; ++a) acc[a] = T(0);
+    if (t >= 1) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_nb<NS>(rdl, toff - ES, jq * K + iq, ldt, nb);
+        mv_add<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
+      }
+    }
+    if (t < T_) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
+        load_nb<NS>(rdl, toff + ES, jq * K + iq, ldt, nb);
+        mv_add<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
+      }
+    }
+    store_nb<NS>(rrho, toff, p, ldt, acc);
   }
 }
 

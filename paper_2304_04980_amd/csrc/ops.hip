@@ -8,15 +8,24 @@ namespace lqg {
 namespace {
 using namespace dev;
 
-// Logical block of the node-tile kernels: chunk-major, node group fastest,
-// remapped per XCD.  Returns false for padding blocks.
+// Logical block of the one-chunk node tiles (k_recover): chunk-major, node
+// group fastest, remapped per XCD.  Returns false for padding blocks.
 __device__ __forceinline__ bool node_tile(const Dims& D, int* lb, int* p, int* t) {
   const int ngroups = node_groups(D);
   *lb = xcd_block();
   if (*lb >= ngroups * time_chunks(D)) return false;
-  node_coords(*lb % ngroups, *lb / ngroups, p, t);
+  *p = tile_node(*lb % ngroups);
+  *t = (*lb / ngroups) * kWave + (threadIdx.x & (kWave - 1));
   return true;
 }
+
+// The stencil kernels of the iteration.  Delta apply: one workgroup per
+// node tile (group of 4 nodes x one time chunk, chunk-major); its 24
+// neighbour loads per node dominate, so more and shorter wavefronts keep more
+// of them in flight.  Omega~ / Xi~ right-hand sides: one workgroup per group
+// of 4 nodes running all time chunks, so the nodes' operator blocks come from
+// the scalar cache after the first chunk.  Blocks are XCD-remapped, so an XCD
+// holds neighbouring nodes.
 
 template <typename T, int NS>
 __global__ __launch_bounds__(256) void k_delta(Dims D, OpCoef<T> C,
@@ -39,10 +48,9 @@ __global__ __launch_bounds__(256) void k_omega(Dims D, OpCoef<T> C,
                                                T* __restrict__ tau,
                                                const Scalars* sc, int check) {
   if (is_done(sc, check)) return;
-  const int ngroups = node_groups(D);
   const int lb = xcd_block();
-  if (lb >= ngroups * time_chunks(D)) return;
-  omega_tile<T, NS>(D, C, rho, th, tau, lb % ngroups, lb / ngroups);
+  if (lb >= node_groups(D)) return;
+  omega_tile<T, NS>(D, C, rho, th, tau, lb, 0, time_chunks(D));
 }
 
 template <typename T, int NS>
@@ -52,10 +60,9 @@ __global__ __launch_bounds__(256) void k_xi(Dims D, OpCoef<T> C,
                                             T* __restrict__ rho,
                                             const Scalars* sc, int check) {
   if (is_done(sc, check)) return;
-  const int ngroups = node_groups(D);
   const int lb = xcd_block();
-  if (lb >= ngroups * time_chunks(D)) return;
-  xi_tile<T, NS>(D, C, r, dl, rho, lb % ngroups, lb / ngroups);
+  if (lb >= node_groups(D)) return;
+  xi_tile<T, NS>(D, C, r, dl, rho, lb, 0, time_chunks(D));
 }
 
 // One workgroup of 2n wavefronts per (super-column v, 64 time steps),
@@ -137,6 +144,7 @@ inline int node_blocks(const Dims& D) {
   return ((D.real_nodes + 3) / 4) * ((D.Tt + kWave - 1) / kWave);
 }
 inline dim3 node_grid(const Dims& D) { return dim3(padded_grid(node_blocks(D))); }
+inline dim3 group_grid(const Dims& D) { return dim3(padded_grid(node_groups(D))); }
 
 }  // namespace
 
@@ -165,7 +173,7 @@ int delta_apply(const Dims& D, const OpCoef<T>& C, const T* d, T* y,
 template <typename T>
 void omega_rhs(const Dims& D, const OpCoef<T>& C, const T* rho, const T* th,
                T* tau, const Scalars* sc, int check_done, hipStream_t s) {
-  const dim3 g = node_grid(D);
+  const dim3 g = group_grid(D);
 #define CALL(NS)                                                               \
   hipLaunchKernelGGL((k_omega<T, NS>), g, dim3(256), 0, s, D, C, rho, th, tau, \
                      sc, check_done)
@@ -176,7 +184,7 @@ void omega_rhs(const Dims& D, const OpCoef<T>& C, const T* rho, const T* th,
 template <typename T>
 void xi_rhs(const Dims& D, const OpCoef<T>& C, const T* r, const T* dl, T* rho,
             const Scalars* sc, int check_done, hipStream_t s) {
-  const dim3 g = node_grid(D);
+  const dim3 g = group_grid(D);
 #define CALL(NS)                                                                 \
   hipLaunchKernelGGL((k_xi<T, NS>), g, dim3(256), 0, s, D, C, r, dl, rho, sc, \
                      check_done)
