@@ -236,6 +236,64 @@ __device__ inline double phi_entry(const Dims& D, const Coef& C, int cls, int v,
   return val;
 }
 
+// Cholesky factor L of the SPD NB x NB block Dm (shared memory, row-major)
+// and Li = L^-1, written to Li (shared), by one thread with the block in
+// registers.  A non-positive or non-finite pivot sets *bad and is replaced
+// by 1 so that the factorisation runs to the end.
+template <int NB>
+__device__ inline void chol_inv_reg(const double* Dm, double* Li, int* bad) {
+  double a[NB][NB], li[NB][NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      a[r][c] = Dm[r * NB + c];
+      li[r][c] = 0.0;
+    }
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    double s = a[cc][cc];
+#pragma unroll
+    for (int k = 0; k < cc; ++k) s -= a[cc][k] * a[cc][k];
+    if (!(s > 0.0) || !isfinite(s)) {
+      *bad = 1;
+      s = 1.0;
+    }
+    const double dg = sqrt(s);
+    a[cc][cc] = dg;
+#pragma unroll
+    for (int rr = cc + 1; rr < NB; ++rr) {
+      double t = a[rr][cc];
+#pragma unroll
+      for (int k = 0; k < cc; ++k) t -= a[rr][k] * a[cc][k];
+      a[rr][cc] = t / dg;
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < NB; ++cc) {
+    li[cc][cc] = 1.0 / a[cc][cc];
+#pragma unroll
+    for (int rr = cc + 1; rr < NB; ++rr) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = cc; k < rr; ++k) t += a[rr][k] * li[k][cc];
+      li[rr][cc] = -t / a[rr][rr];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Li[r * NB + c] = li[r][c];
+}
+__device__ inline void chol_inv(const double* Dm, double* Li, int NB, int* bad) {
+  switch (NB) {
+    case 2: chol_inv_reg<2>(Dm, Li, bad); break;
+    case 4: chol_inv_reg<4>(Dm, Li, bad); break;
+    case 6: chol_inv_reg<6>(Dm, Li, bad); break;
+    default: chol_inv_reg<8>(Dm, Li, bad); break;
+  }
+}
+
 // Banded block Cholesky of Phi_bar_{v,cls} by one 64-thread workgroup.  Block rows of size NB = 2n; block bandwidth 2 (Psi_hat couples
 // nodes at Manhattan distance <= 2, so rows i and i-2 meet only in the same
 // column).  For each block row i:
@@ -249,7 +307,7 @@ __device__ inline void factor(const Dims& D, const Coef& C, Scalars* sc, int v,
   const int r = tid / NB, c = tid - (tid / NB) * NB;
   const bool act = tid < NB2;
   __shared__ double S1[64], S2[64], Dm[64], L1[64], L2[64], T1[64];
-  __shared__ double Lp1[64], Lp2[64], L1p[64], Lc[64], Li[64];
+  __shared__ double Lp1[64], Lp2[64], L1p[64], Li[64];
   __shared__ int bad;
   if (tid == 0) bad = 0;
   if (act) Lp1[tid] = Lp2[tid] = L1p[tid] = 0.0;
@@ -286,32 +344,7 @@ __device__ inline void factor(const Dims& D, const Coef& C, Scalars* sc, int v,
       Dm[tid] = s;
     }
     __syncthreads();
-    if (tid == 0) {  // Cholesky of Dm and inverse of the factor
-      for (int e = 0; e < NB2; ++e) Lc[e] = Li[e] = 0.0;
-      for (int cc = 0; cc < NB; ++cc) {
-        double s = Dm[cc * NB + cc];
-        for (int k = 0; k < cc; ++k) s -= Lc[cc * NB + k] * Lc[cc * NB + k];
-        if (!(s > 0.0) || !isfinite(s)) {
-          bad = 1;
-          s = 1.0;
-        }
-        const double dg = sqrt(s);
-        Lc[cc * NB + cc] = dg;
-        for (int rr = cc + 1; rr < NB; ++rr) {
-          double t = Dm[rr * NB + cc];
-          for (int k = 0; k < cc; ++k) t -= Lc[rr * NB + k] * Lc[cc * NB + k];
-          Lc[rr * NB + cc] = t / dg;
-        }
-      }
-      for (int cc = 0; cc < NB; ++cc) {
-        Li[cc * NB + cc] = 1.0 / Lc[cc * NB + cc];
-        for (int rr = cc + 1; rr < NB; ++rr) {
-          double t = 0.0;
-          for (int k = cc; k < rr; ++k) t += Lc[rr * NB + k] * Li[k * NB + cc];
-          Li[rr * NB + cc] = -t / Lc[rr * NB + rr];
-        }
-      }
-    }
+    if (tid == 0) chol_inv(Dm, Li, NB, &bad);  // Cholesky of Dm, inverse
     __syncthreads();
     if (act) {
       double m1 = 0.0, m2 = 0.0, n1 = 0.0, n2 = 0.0;
@@ -391,191 +424,164 @@ __device__ inline double mm_tt(const double* A, const double* B, int NB, int r, 
   return s;
 }
 
-// Cholesky factor of the SPD block Dm and its inverse (one thread).
-__device__ inline void chol_inv(const double* Dm, double* Lc, double* Li, int NB,
-                                int* bad) {
-  for (int e = 0; e < NB * NB; ++e) Lc[e] = Li[e] = 0.0;
-  for (int cc = 0; cc < NB; ++cc) {
-    double s = Dm[cc * NB + cc];
-    for (int k = 0; k < cc; ++k) s -= Lc[cc * NB + k] * Lc[cc * NB + k];
-    if (!(s > 0.0) || !isfinite(s)) {
-      *bad = 1;
-      s = 1.0;
-    }
-    const double dg = sqrt(s);
-    Lc[cc * NB + cc] = dg;
-    for (int rr = cc + 1; rr < NB; ++rr) {
-      double t = Dm[rr * NB + cc];
-      for (int k = 0; k < cc; ++k) t -= Lc[rr * NB + k] * Lc[cc * NB + k];
-      Lc[rr * NB + cc] = t / dg;
-    }
-  }
-  for (int cc = 0; cc < NB; ++cc) {
-    Li[cc * NB + cc] = 1.0 / Lc[cc * NB + cc];
-    for (int rr = cc + 1; rr < NB; ++rr) {
-      double t = 0.0;
-      for (int k = cc; k < rr; ++k) t += Lc[rr * NB + k] * Li[k * NB + cc];
-      Li[rr * NB + cc] = -t / Lc[rr * NB + rr];
-    }
-  }
-}
-
-// One 64-thread workgroup per (v, cls).
+// One 128-thread workgroup per (v, cls): threads 0-63 factor the top chain,
+// threads 64-127 the bottom chain (independent in this order, so side by
+// side, with the same barriers; the shorter top chain idles), then threads
+// 0-63 the two middle rows.
 __device__ inline void factor_twisted(const Dims& D, const Coef& C, Scalars* sc,
                                       int v, int cls) {
   const int NB = 2 * D.n, NB2 = NB * NB, K = D.K;
   const int m = twist_m(K), nb = K - 2 - m;  // top and bottom chain lengths
-  const int tid = threadIdx.x;
+  const int h = threadIdx.x >> 6, tid = threadIdx.x & 63;  // half, thread in half
   const int r = tid / NB, c = tid - (tid / NB) * NB;
   const bool act = tid < NB2;
-  __shared__ double S1[64], S2[64], Dm[64], L1[64], L2[64], T1[64];
-  __shared__ double Lp1[64], Lp2[64], L1p[64], Lc[64], Li[64];
-  __shared__ double A1[64], A2[64], A12[64], B1[64], B2[64], B12[64];
+  const bool top = h == 0;
+  __shared__ double S1[2][64], S2[2][64], Dm[2][64], L1[2][64], L2[2][64], T1[2][64];
+  __shared__ double Lp1[2][64], Lp2[2][64], L1p[2][64], Li[2][64];
   __shared__ double Lm1[64], Lmx[64], Lmi[64], LA[64], LM[64], SX[64];
   __shared__ int bad;
-  if (tid == 0) bad = 0;
+  if (threadIdx.x == 0) bad = 0;
   const size_t cv = (size_t)cls * D.V + v;
   const size_t fw0 = cv * fw_rows(K), bw0 = cv * K;
   const size_t fwb = fw0 + m + 2, bwb = bw0 + m + 1;  // bottom chain tables
   auto fwrow = [&](size_t row) { return C.Fw + (row * NB + r) * kFwRow; };
   auto bwrow = [&](size_t row) { return C.Bw + (row * NB + r) * kBwRow; };
   double* xw = C.Xw + (cv * NB + r) * kFwRow;
-  if (act) xw[24 + c] = 0.0;
+  if (act && top) xw[24 + c] = 0.0;
 
-  // One chain: positions k = 0 .. len-1, block row i = top ? k : K-1-k,
-  // previous rows in the chain i - dir and i - 2 dir.  Leaves Lp1 = Linv of
-  // position len-1, Lp2 = Linv of position len-2, L1p = L_{len-1, len-2}.
-  auto chain = [&](bool top, int len, size_t ft, size_t bt) {
-    const int dir = top ? 1 : -1;
-    if (act) Lp1[tid] = Lp2[tid] = L1p[tid] = 0.0;
+  // The two chains: position k, block row i = top ? k : K-1-k, previous rows
+  // in the chain i - dir and i - 2 dir.  Afterwards Lp1 / Lp2 hold Linv of
+  // the last / second-last position of each chain, L1p the coupling between
+  // them.
+  {
+    const int dir = top ? 1 : -1, len = top ? m : nb;
+    const size_t ft = top ? fw0 : fwb, bt = top ? bw0 : bwb;
+    double *S1h = S1[h], *S2h = S2[h], *Dmh = Dm[h], *L1h = L1[h], *L2h = L2[h];
+    double *T1h = T1[h], *Lp1h = Lp1[h], *Lp2h = Lp2[h], *L1ph = L1p[h], *Lih = Li[h];
+    if (act) Lp1h[tid] = Lp2h[tid] = L1ph[tid] = 0.0;
     __syncthreads();
-    for (int k = 0; k < len; ++k) {
+    for (int k = 0; k < nb; ++k) {
+      const bool work = act && k < len;
       const int i = top ? k : K - 1 - k;
-      if (act) {
-        Dm[tid] = phi_entry(D, C, cls, v, i, 0, r, c);
-        S1[tid] = k >= 1 ? phi_entry(D, C, cls, v, i, -dir, r, c) : 0.0;
-        S2[tid] = k >= 2 ? phi_entry(D, C, cls, v, i, -2 * dir, r, c) : 0.0;
+      if (work) {
+        Dmh[tid] = phi_entry(D, C, cls, v, i, 0, r, c);
+        S1h[tid] = k >= 1 ? phi_entry(D, C, cls, v, i, -dir, r, c) : 0.0;
+        S2h[tid] = k >= 2 ? phi_entry(D, C, cls, v, i, -2 * dir, r, c) : 0.0;
       }
       __syncthreads();
-      if (act) L2[tid] = mm_t(S2, Lp2, NB, r, c);
+      if (work) L2h[tid] = mm_t(S2h, Lp2h, NB, r, c);
       __syncthreads();
-      if (act) T1[tid] = S1[tid] - mm_t(L2, L1p, NB, r, c);
+      if (work) T1h[tid] = S1h[tid] - mm_t(L2h, L1ph, NB, r, c);
       __syncthreads();
-      if (act) L1[tid] = mm_t(T1, Lp1, NB, r, c);
+      if (work) L1h[tid] = mm_t(T1h, Lp1h, NB, r, c);
       __syncthreads();
-      if (act) Dm[tid] -= mm_t(L1, L1, NB, r, c) + mm_t(L2, L2, NB, r, c);
+      if (work) Dmh[tid] -= mm_t(L1h, L1h, NB, r, c) + mm_t(L2h, L2h, NB, r, c);
       __syncthreads();
-      if (tid == 0) chol_inv(Dm, Lc, Li, NB, &bad);
+      if (tid == 0 && k < len) chol_inv(Dmh, Lih, NB, &bad);
       __syncthreads();
-      if (act) {
+      if (work) {
         double* fw = fwrow(ft + k);
-        fw[c] = mm_n(Li, L1, NB, r, c);
-        fw[8 + c] = mm_n(Li, L2, NB, r, c);
-        fw[16 + c] = Li[r * NB + c];
-        fwrow(ft + k + 1)[24 + c] = Li[c * NB + r];
-        if (k >= 1) bwrow(bt + k - 1)[c] = mm_tt(Lp1, L1, NB, r, c);
-        if (k >= 2) bwrow(bt + k - 2)[8 + c] = mm_tt(Lp2, L2, NB, r, c);
+        fw[c] = mm_n(Lih, L1h, NB, r, c);
+        fw[8 + c] = mm_n(Lih, L2h, NB, r, c);
+        fw[16 + c] = Lih[r * NB + c];
+        fwrow(ft + k + 1)[24 + c] = Lih[c * NB + r];
+        if (k >= 1) bwrow(bt + k - 1)[c] = mm_tt(Lp1h, L1h, NB, r, c);
+        if (k >= 2) bwrow(bt + k - 2)[8 + c] = mm_tt(Lp2h, L2h, NB, r, c);
       }
       __syncthreads();
-      if (act) {
-        Lp2[tid] = Lp1[tid];
-        Lp1[tid] = Li[tid];
-        L1p[tid] = L1[tid];
+      if (work) {
+        Lp2h[tid] = Lp1h[tid];
+        Lp1h[tid] = Lih[tid];
+        L1ph[tid] = L1h[tid];
       }
       __syncthreads();
     }
-  };
-  chain(true, m, fw0, bw0);
-  if (act) {
-    A1[tid] = Lp1[tid];   // Linv_{m-1}
-    A2[tid] = Lp2[tid];   // Linv_{m-2}
-    A12[tid] = L1p[tid];  // L_{m-1,m-2}
   }
-  chain(false, nb, fwb, bwb);
-  if (act) {
-    B1[tid] = Lp1[tid];   // Linv_{m+2}
-    B2[tid] = Lp2[tid];   // Linv_{m+3}
-    B12[tid] = L1p[tid];  // L_{m+2,m+3}
-  }
-  __syncthreads();
+  // top chain's end: A1 = Linv_{m-1}, A2 = Linv_{m-2}, A12 = L_{m-1,m-2};
+  // bottom chain's end: B1 = Linv_{m+2}, B2 = Linv_{m+3}, B12 = L_{m+2,m+3}
+  const double *A1 = Lp1[0], *A2 = Lp2[0], *A12 = L1p[0];
+  const double *B1 = Lp1[1], *B2 = Lp2[1], *B12 = L1p[1];
+  double *S1m = S1[0], *S2m = S2[0], *Dmm = Dm[0], *L1m = L1[0], *L2m = L2[0];
+  double *T1m = T1[0], *Lim = Li[0];
+  const bool mact = act && top;  // the middle rows run on threads 0-63
 
   // ---- row m: top continuation plus L_{m,m+2}
-  if (act) {
-    Dm[tid] = phi_entry(D, C, cls, v, m, 0, r, c);
-    S1[tid] = phi_entry(D, C, cls, v, m, -1, r, c);
-    S2[tid] = phi_entry(D, C, cls, v, m, -2, r, c);
+  if (mact) {
+    Dmm[tid] = phi_entry(D, C, cls, v, m, 0, r, c);
+    S1m[tid] = phi_entry(D, C, cls, v, m, -1, r, c);
+    S2m[tid] = phi_entry(D, C, cls, v, m, -2, r, c);
     SX[tid] = phi_entry(D, C, cls, v, m, 2, r, c);
   }
   __syncthreads();
-  if (act) {
-    L2[tid] = mm_t(S2, A2, NB, r, c);   // L_{m,m-2}
-    Lmx[tid] = mm_t(SX, B1, NB, r, c);  // L_{m,m+2}
+  if (mact) {
+    L2m[tid] = mm_t(S2m, A2, NB, r, c);  // L_{m,m-2}
+    Lmx[tid] = mm_t(SX, B1, NB, r, c);   // L_{m,m+2}
   }
   __syncthreads();
-  if (act) T1[tid] = S1[tid] - mm_t(L2, A12, NB, r, c);
+  if (mact) T1m[tid] = S1m[tid] - mm_t(L2m, A12, NB, r, c);
   __syncthreads();
-  if (act) Lm1[tid] = mm_t(T1, A1, NB, r, c);  // L_{m,m-1}
+  if (mact) Lm1[tid] = mm_t(T1m, A1, NB, r, c);  // L_{m,m-1}
   __syncthreads();
-  if (act)
-    Dm[tid] -= mm_t(Lm1, Lm1, NB, r, c) + mm_t(L2, L2, NB, r, c) + mm_t(Lmx, Lmx, NB, r, c);
+  if (mact)
+    Dmm[tid] -= mm_t(Lm1, Lm1, NB, r, c) + mm_t(L2m, L2m, NB, r, c) + mm_t(Lmx, Lmx, NB, r, c);
   __syncthreads();
-  if (tid == 0) chol_inv(Dm, Lc, Lmi, NB, &bad);  // Lmi = Linv_m
+  if (threadIdx.x == 0) chol_inv(Dmm, Lmi, NB, &bad);  // Lmi = Linv_m
   __syncthreads();
-  if (act) {
+  if (mact) {
     double* fw = fwrow(fw0 + m);
     fw[c] = mm_n(Lmi, Lm1, NB, r, c);
-    fw[8 + c] = mm_n(Lmi, L2, NB, r, c);
+    fw[8 + c] = mm_n(Lmi, L2m, NB, r, c);
     fw[16 + c] = Lmi[r * NB + c];
     double* fe = fwrow(fw0 + m + 1);
     fe[c] = fe[8 + c] = fe[16 + c] = 0.0;
     fe[24 + c] = Lmi[c * NB + r];                             // Linv_m'
     xw[c] = mm_n(Lmi, Lmx, NB, r, c);                         // Linv_m L_{m,m+2}
     bwrow(bw0 + m - 1)[c] = mm_tt(A1, Lm1, NB, r, c);         // N1_{m-1}
-    bwrow(bw0 + m - 2)[8 + c] = mm_tt(A2, L2, NB, r, c);      // N2_{m-2}
+    bwrow(bw0 + m - 2)[8 + c] = mm_tt(A2, L2m, NB, r, c);     // N2_{m-2}
     bwrow(bwb + nb - 1)[8 + c] = mm_tt(B1, Lmx, NB, r, c);    // N2 of row m+2
   }
   __syncthreads();
 
   // ---- row m+1: bottom continuation plus L_{m+1,m-1}, L_{m+1,m}
-  if (act) {
-    Dm[tid] = phi_entry(D, C, cls, v, m + 1, 0, r, c);
-    S1[tid] = phi_entry(D, C, cls, v, m + 1, 1, r, c);    // Phi[m+1, m+2]
-    S2[tid] = phi_entry(D, C, cls, v, m + 1, 2, r, c);    // Phi[m+1, m+3]
-    SX[tid] = phi_entry(D, C, cls, v, m + 1, -2, r, c);   // Phi[m+1, m-1]
-    T1[tid] = phi_entry(D, C, cls, v, m + 1, -1, r, c);   // Phi[m+1, m]
+  if (mact) {
+    Dmm[tid] = phi_entry(D, C, cls, v, m + 1, 0, r, c);
+    S1m[tid] = phi_entry(D, C, cls, v, m + 1, 1, r, c);    // Phi[m+1, m+2]
+    S2m[tid] = phi_entry(D, C, cls, v, m + 1, 2, r, c);    // Phi[m+1, m+3]
+    SX[tid] = phi_entry(D, C, cls, v, m + 1, -2, r, c);    // Phi[m+1, m-1]
+    T1m[tid] = phi_entry(D, C, cls, v, m + 1, -1, r, c);   // Phi[m+1, m]
   }
   __syncthreads();
-  if (act) {
-    L2[tid] = mm_t(S2, B2, NB, r, c);  // L_{m+1,m+3}
-    LA[tid] = mm_t(SX, A1, NB, r, c);  // L_{m+1,m-1}
+  if (mact) {
+    L2m[tid] = mm_t(S2m, B2, NB, r, c);  // L_{m+1,m+3}
+    LA[tid] = mm_t(SX, A1, NB, r, c);    // L_{m+1,m-1}
   }
   __syncthreads();
-  if (act) S1[tid] -= mm_t(L2, B12, NB, r, c);
+  if (mact) S1m[tid] -= mm_t(L2m, B12, NB, r, c);
   __syncthreads();
-  if (act) L1[tid] = mm_t(S1, B1, NB, r, c);  // L_{m+1,m+2}
+  if (mact) L1m[tid] = mm_t(S1m, B1, NB, r, c);  // L_{m+1,m+2}
   __syncthreads();
-  if (act) T1[tid] -= mm_t(LA, Lm1, NB, r, c) + mm_t(L1, Lmx, NB, r, c);
+  if (mact) T1m[tid] -= mm_t(LA, Lm1, NB, r, c) + mm_t(L1m, Lmx, NB, r, c);
   __syncthreads();
-  if (act) LM[tid] = mm_t(T1, Lmi, NB, r, c);  // L_{m+1,m}
+  if (mact) LM[tid] = mm_t(T1m, Lmi, NB, r, c);  // L_{m+1,m}
   __syncthreads();
-  if (act)
-    Dm[tid] -= mm_t(L1, L1, NB, r, c) + mm_t(L2, L2, NB, r, c) + mm_t(LA, LA, NB, r, c) +
-               mm_t(LM, LM, NB, r, c);
+  if (mact)
+    Dmm[tid] -= mm_t(L1m, L1m, NB, r, c) + mm_t(L2m, L2m, NB, r, c) + mm_t(LA, LA, NB, r, c) +
+                mm_t(LM, LM, NB, r, c);
   __syncthreads();
-  if (tid == 0) chol_inv(Dm, Lc, Li, NB, &bad);  // Li = Linv_{m+1}
+  if (threadIdx.x == 0) chol_inv(Dmm, Lim, NB, &bad);  // Lim = Linv_{m+1}
   __syncthreads();
-  if (act) {
+  if (mact) {
     double* fw = fwrow(fwb + nb);
-    fw[c] = mm_n(Li, L1, NB, r, c);
-    fw[8 + c] = mm_n(Li, L2, NB, r, c);
-    fw[16 + c] = Li[r * NB + c];
+    fw[c] = mm_n(Lim, L1m, NB, r, c);
+    fw[8 + c] = mm_n(Lim, L2m, NB, r, c);
+    fw[16 + c] = Lim[r * NB + c];
     double* fe = fwrow(fwb + nb + 1);
     fe[c] = fe[8 + c] = fe[16 + c] = 0.0;
-    fe[24 + c] = Li[c * NB + r];                              // Linv_{m+1}'
-    xw[8 + c] = mm_n(Li, LA, NB, r, c);                       // Linv_{m+1} L_{m+1,m-1}
-    xw[16 + c] = mm_n(Li, LM, NB, r, c);                      // Linv_{m+1} L_{m+1,m}
-    bwrow(bwb + nb - 1)[c] = mm_tt(B1, L1, NB, r, c);         // N1 of row m+2
-    bwrow(bwb + nb - 2)[8 + c] = mm_tt(B2, L2, NB, r, c);     // N2 of row m+3
+    fe[24 + c] = Lim[c * NB + r];                             // Linv_{m+1}'
+    xw[8 + c] = mm_n(Lim, LA, NB, r, c);                      // Linv_{m+1} L_{m+1,m-1}
+    xw[16 + c] = mm_n(Lim, LM, NB, r, c);                     // Linv_{m+1} L_{m+1,m}
+    bwrow(bwb + nb - 1)[c] = mm_tt(B1, L1m, NB, r, c);        // N1 of row m+2
+    bwrow(bwb + nb - 2)[8 + c] = mm_tt(B2, L2m, NB, r, c);    // N2 of row m+3
     bwrow(bw0 + m - 1)[8 + c] = mm_tt(A1, LA, NB, r, c);      // N2_{m-1}
     double* bm = bwrow(bw0 + m);
     bm[c] = mm_tt(Lmi, LM, NB, r, c);                         // N1_m
@@ -584,7 +590,7 @@ __device__ inline void factor_twisted(const Dims& D, const Coef& C, Scalars* sc,
     bl[c] = bl[8 + c] = 0.0;
   }
   __syncthreads();
-  if (tid == 0 && bad) atomicOr(&sc->flag_notspd, 1);
+  if (threadIdx.x == 0 && bad) atomicOr(&sc->flag_notspd, 1);
   __syncthreads();
 }
 

@@ -17,7 +17,7 @@ __global__ void k_stencil(Dims D, ProblemIn P, Coef C) {
 __global__ __launch_bounds__(64) void k_factor(Dims D, Coef C, Scalars* sc) {
   factor(D, C, sc, blockIdx.x, blockIdx.y);
 }
-__global__ __launch_bounds__(64) void k_factor_twisted(Dims D, Coef C, Scalars* sc) {
+__global__ __launch_bounds__(128) void k_factor_twisted(Dims D, Coef C, Scalars* sc) {
   factor_twisted(D, C, sc, blockIdx.x, blockIdx.y);
 }
 __global__ void k_rhs_init(Dims D, const double* __restrict__ x0,
@@ -38,7 +38,7 @@ void launch_setup(const Dims& D, const ProblemIn& P, const Coef& C,
 
 void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s) {
   if (twisted(D))
-    hipLaunchKernelGGL(k_factor_twisted, dim3(D.V, 2), dim3(64), 0, s, D, C, sc);
+    hipLaunchKernelGGL(k_factor_twisted, dim3(D.V, 2), dim3(128), 0, s, D, C, sc);
   else
     hipLaunchKernelGGL(k_factor, dim3(D.V, 2), dim3(64), 0, s, D, C, sc);
 }

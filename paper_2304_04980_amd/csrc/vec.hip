@@ -123,19 +123,31 @@ __global__ __launch_bounds__(256) void k_to_float(long long n,
 }
 
 // Deterministic fixed-order reduction of np partials, then the scalar update
-// of Algorithm 1 selected by mode.
-__global__ __launch_bounds__(256) void k_scalar(int mode,
-                                                const double* __restrict__ psum,
-                                                const double* __restrict__ pmax,
-                                                int np, Scalars* sc, double tol) {
+// of Algorithm 1 selected by mode.  Four independent accumulators per thread
+// keep several loads in flight.
+constexpr int kScalarThreads = 1024;
+__global__ __launch_bounds__(kScalarThreads) void k_scalar(int mode,
+                                                           const double* __restrict__ psum,
+                                                           const double* __restrict__ pmax,
+                                                           int np, Scalars* sc, double tol) {
   if (scalar_mode_gated(mode) && sc->done) return;
-  double s = 0.0, m = 0.0;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    s += psum[k];
+  constexpr int B = kScalarThreads;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, m = 0.0;
+  int k = threadIdx.x;
+  for (; k + 3 * B < np; k += 4 * B) {
+    s0 += psum[k];
+    s1 += psum[k + B];
+    s2 += psum[k + 2 * B];
+    s3 += psum[k + 3 * B];
+    if (pmax)
+      m = fmax(fmax(m, fmax(pmax[k], pmax[k + B])), fmax(pmax[k + 2 * B], pmax[k + 3 * B]));
+  }
+  for (; k < np; k += B) {
+    s0 += psum[k];
     if (pmax) m = fmax(m, pmax[k]);
   }
-  s = block_sum<256>(s);
-  if (pmax) m = block_max<256>(m);
+  double s = block_sum<B>((s0 + s1) + (s2 + s3));
+  if (pmax) m = block_max<B>(m);
   if (threadIdx.x != 0) return;
   scalar_apply(mode, s, m, sc, nullptr, tol);
 }
@@ -232,7 +244,7 @@ void copy_to_float(const double* a, float* b, long long n, hipStream_t s) {
 }
 void scalar_step(int mode, const double* psum, const double* pmax, int np,
                  Scalars* sc, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(256), 0, s, mode, psum, pmax, np,
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kScalarThreads), 0, s, mode, psum, pmax, np,
                      sc, tol);
 }
 void to_internal(const Dims& D, const double* abi, double* internal,
