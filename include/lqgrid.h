@@ -181,12 +181,17 @@ typedef enum {
 LQGRID_API int lqgrid_apply_operator(lqgrid_ctx *ctx, int op, int outer_S, int inner_L,
                           const double *in, double *out);
 
-/* Per-kernel device timing over the calls that follow (HIP events on the
- * context's stream around every launch of the hot kernels).  enable = 0
- * stops recording.  Used by the benchmark to time the dominant kernel. */
+/* Per-kernel device timing over the calls that follow: HIP events on the
+ * context's stream around every enable-th launch of each hot kernel
+ * (enable = 1: every launch; enable <= 0 stops recording).  An event pair
+ * between two launches serialises their dispatch, so a stride above 1 keeps
+ * the timed calls close to untimed ones.  Used by the benchmark to time the
+ * dominant kernel.  Returns LQGRID_EINVAL for a null ctx, LQGRID_EHIP if
+ * resolving pending events fails. */
 LQGRID_API int lqgrid_profile_enable(lqgrid_ctx *ctx, int enable);
 /* kernel: 0 = Delta apply, 1 = Phi solve, 2 = Omega/Xi right-hand side,
- * 3 = vector update.  Returns launches and summed milliseconds since enable. */
+ * 3 = vector update.  Returns the timed launches and their summed
+ * milliseconds since enable. */
 LQGRID_API int lqgrid_profile_read(lqgrid_ctx *ctx, int kernel, long long *launches,
                         double *total_ms);
 

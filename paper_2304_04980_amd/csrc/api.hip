@@ -115,6 +115,8 @@ struct lqgrid_ctx {
   int host_iter[2];   // staging for resetting the device iteration counters
   // profiling
   bool prof = false;
+  int prof_stride = 1;                  // time every prof_stride-th launch
+  long long prof_seen[4] = {0, 0, 0, 0};  // launches per kind since enable
   long long prof_launches[4] = {0, 0, 0, 0};
   double prof_ms[4] = {0, 0, 0, 0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -167,6 +169,7 @@ struct ProfScope {
   int slot = -1;
   ProfScope(lqgrid_ctx* c_, int k) : c(c_) {
     if (!c->prof) return;
+    if (c->prof_seen[k]++ % c->prof_stride != 0) return;
     if (c->prof_used >= (int)c->prof_ev.size()) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -628,8 +631,10 @@ int lqgrid_profile_enable(lqgrid_ctx* c, int enable) {
     if (hipStreamSynchronize(c->stream) != hipSuccess) return LQGRID_EHIP;
     prof_resolve(c);
   }
-  c->prof = enable != 0;
+  c->prof = enable > 0;
+  c->prof_stride = enable > 0 ? enable : 1;
   for (int k = 0; k < 4; ++k) {
+    c->prof_seen[k] = 0;
     c->prof_launches[k] = 0;
     c->prof_ms[k] = 0.0;
   }

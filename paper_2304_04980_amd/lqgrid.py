@@ -267,8 +267,9 @@ class Context:
         torch.cuda.current_stream().synchronize()
         return out
 
-    def profile_enable(self, on=True):
-        self.L.lqgrid_profile_enable(self.ctx, 1 if on else 0)
+    def profile_enable(self, on=True, stride=1):
+        """Time every stride-th launch of each hot kernel with HIP events."""
+        self.L.lqgrid_profile_enable(self.ctx, max(1, int(stride)) if on else 0)
 
     def profile_read(self, kernel):
         n = c_longlong()
