@@ -3,7 +3,8 @@
 Operators: element-wise comparison on the same seeded inputs at sizes that
 span several 64-wide time tiles with a ragged tail, odd and even N (the odd
 case exercises the single-column last super-column), K = 1, N = 1, T = 1 and
-n = 1..4.
+n = 1..4; K < 8 runs the one-chain Phi_bar factorisation, K >= 8 (even and
+odd, up to the headline K = 128) the twisted one.
 
 Tolerances (FP64, derived from the arithmetic): each operator output is a sum
 of at most 23 n-by-n block products, evaluated in a different order than the
@@ -47,7 +48,15 @@ CASES = [
     (1, 5, 9, 2, 1, 1.0),       # K = 1
     (6, 1, 9, 2, 2, 1.0),       # N = 1 (single dummy-padded super-column)
     (4, 3, 1, 1, 1, 1.0),       # T = 1, n = 1
-    (7, 8, 40, 4, 3, 1.0),
+    (7, 8, 40, 4, 3, 1.0),      # K = 7: the last one-chain Phi_bar factor
+    # K >= 8: the twisted factorisation and two-chain sweep
+    (8, 4, 70, 4, 2, 1.0),      # K = 8: chains of 3 + 3 rows, two time tiles
+    (9, 6, 40, 3, 2, 2.5),      # odd K: bottom chain one row longer, QT != Q
+    (12, 3, 9, 2, 2, 1.3),      # odd N, QT != Q
+    (16, 5, 130, 2, 1, 0.7),    # three time tiles with a ragged tail, QT != Q
+    (33, 2, 20, 4, 3, 1.0),     # odd K
+    (64, 2, 64, 1, 1, 1.0),     # T+1 = 65, n = 1
+    (128, 2, 20, 4, 2, 1.0),    # K of the headline workload
 ]
 
 
@@ -208,7 +217,8 @@ def test_error_paths(lib, torch):
 
 # ------------------------------------------------------------ precision form
 F32_CASES = [(4, 4, 20, 2, 1, 1.0), (5, 7, 150, 3, 2, 1.0), (3, 5, 64, 4, 2, 0.7),
-             (6, 1, 9, 2, 2, 1.0)]
+             (6, 1, 9, 2, 2, 1.0), (8, 4, 70, 4, 2, 1.0), (9, 6, 40, 3, 2, 2.5),
+             (33, 2, 20, 4, 3, 1.0), (128, 2, 20, 4, 2, 1.3)]
 
 
 @pytest.mark.parametrize("case", F32_CASES, ids=[str(c) for c in F32_CASES])
