@@ -150,6 +150,97 @@ __device__ __forceinline__ void sfor(F&& f) {
   }
 }
 
+// acc + (or -) c * z where c is lane L of the lane's own 16-lane row of
+// register c (DPP row_newbcast folded into the FMA).  The compiler emits a
+// separate v_mov_b32_dpp for the broadcast and has no 64-bit form, so these
+// are inline assembly; the registers read through DPP are only ever written
+// by vector-memory loads (no VALU write within the DPP wait states), which a
+// check over the generated code (check_dpp.py) confirms.
+template <int L, bool NEG>
+__device__ __forceinline__ float dpp_fmac(float acc, float c, float z) {
+  if constexpr (NEG)
+    asm("v_fmac_f32_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(c), "v"(z), "n"(L));
+  else
+    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(c), "v"(z), "n"(L));
+  return acc;
+}
+template <int L, bool NEG>
+__device__ __forceinline__ double dpp_fmac(double acc, double c, double z) {
+  if constexpr (NEG)
+    asm("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(c), "v"(z), "n"(L));
+  else
+    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc) : "v"(c), "v"(z), "n"(L));
+  return acc;
+}
+
+// NW wave-uniform coefficients (a node's operator blocks), held 16 per
+// register: lane l of register k holds coefficient 16 k + l mod 16.  Loaded
+// by one vector load per 16 coefficients, all issued together (the scalar
+// loads they replace are L2 misses that a wavefront otherwise waits for one
+// block at a time).  Coefficients past NW read whatever follows (or zero out
+// of range) and are never used.
+template <typename T, int NW>
+struct NodeBlocks {
+  static constexpr int kRegs = (NW + 15) / 16;
+  T g[kRegs];
+  __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, unsigned base, int lane) {
+#pragma unroll
+    for (int k = 0; k < kRegs; ++k)
+      g[k] = buf_lds<T>(rs, (unsigned)((16 * k + (lane & 15)) * sizeof(T)), base);
+  }
+  // acc +=/-= M x, M the NS x NS row-major block starting at coefficient J0
+  template <int J0, bool NEG, int NS>
+  __device__ __forceinline__ void mv(const T (&x)[NS], T (&acc)[NS]) const {
+    sfor<0, NS>([&](auto ac) {
+      constexpr int a = decltype(ac)::value;
+      sfor<0, NS>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int J = J0 + a * NS + b;
+        acc[a] = dpp_fmac<J & 15, NEG>(acc[a], g[J >> 4], x[b]);
+      });
+    });
+  }
+};
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const T* base, long long count) {
+  return make_rsrc(base, count * (long long)sizeof(T));
+}
+
+// A node's operator blocks as the stencil tiles apply them: in registers
+// through DPP-broadcast FMAs for FP32 (NodeBlocks), through the scalar cache
+// for FP64 (whose register copy costs more occupancy than it saves latency).
+// count: number of T in the whole array; base: first coefficient of node p.
+template <typename T, int NW>
+struct TileBlocks;
+template <int NW>
+struct TileBlocks<float, NW> {
+  NodeBlocks<float, NW> b;
+  __device__ __forceinline__ void load(const float* arr, long long count, long long first,
+                                       int lane) {
+    b.load(block_rsrc(arr, count), (unsigned)(first * sizeof(float)), lane);
+  }
+  template <int J0, bool NEG, int NS>
+  __device__ __forceinline__ void mv(const float (&x)[NS], float (&acc)[NS]) const {
+    b.template mv<J0, NEG>(x, acc);
+  }
+};
+template <int NW>
+struct TileBlocks<double, NW> {
+  const double* m;
+  __device__ __forceinline__ void load(const double* arr, long long, long long first, int) {
+    m = arr + first;
+  }
+  template <int J0, bool NEG, int NS>
+  __device__ __forceinline__ void mv(const double (&x)[NS], double (&acc)[NS]) const {
+    if constexpr (NEG) mv_sub<NS>(m + J0, x, acc);
+    else mv_add<NS>(m + J0, x, acc);
+  }
+};
+
 // Node tiles: 4 nodes (one per wavefront of a 256-thread workgroup) x time
 // chunks c0 .. c1-1 of 64 consecutive steps (one per lane).  Group g covers
 // nodes 4 g .. 4 g + 3 and t = 64 c .. 64 c + 63 for each chunk c.  A
@@ -187,60 +278,97 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const Dims& D, const 
   return make_rsrc(v, D.vlen * (long long)sizeof(T));
 }
 
+// Per-lane time offsets of a tile row: every lane (also those past the last
+// step) stays active so that the DPP-broadcast FMAs read valid source lanes;
+// loads use time indices clamped into [0, Tt), so every access lies inside
+// its row, and results of lanes past Tt are discarded by the stores.
+struct TileTime {
+  int t;               // this lane's time step
+  bool valid;          // t < Tt
+  unsigned off, prev, next;  // byte offsets of min(t, Tt-1) and its clamped neighbours
+};
+template <typename T>
+__device__ __forceinline__ TileTime tile_time(const Dims& D, int chunk) {
+  TileTime r;
+  r.t = chunk * kWave + (threadIdx.x & (kWave - 1));
+  r.valid = r.t < D.Tt;
+  const int tl = min(r.t, D.Tt - 1);
+  r.off = (unsigned)tl * sizeof(T);
+  r.prev = (unsigned)max(tl - 1, 0) * sizeof(T);
+  r.next = (unsigned)min(tl + 1, D.Tt - 1) * sizeof(T);
+  return r;
+}
+template <int NS, typename T>
+__device__ __forceinline__ void zero_unless(bool keep, T (&x)[NS]) {
+#pragma unroll
+  for (int c = 0; c < NS; ++c) x[c] = keep ? x[c] : T(0);
+}
+
 // ---------------------------------------------------------------------------
 // y = Delta d on one node tile (one time chunk); the tile's FP64 partial sum
-// of y'd is written to *partial (when non-null) by thread 0.  Every thread of the workgroup
-// must call this (it contains a workgroup reduction).
+// of y'd is written to *partial (when non-null) by thread 0.  Every thread of
+// the workgroup must call this (it contains a workgroup reduction).
 //   y_t(p) = Q_t^-1 d_t(p)
 //          + [t>=1] ( sum_13 G[p][k] d_t(p+o_k) - sum_5 Cdn[p][k] d_{t-1}(p+o_k) )
 //          - [t<T]  sum_5 Cup[p][k] d_{t+1}(p+o_k)
+// The node's 25 operator blocks are applied through TileBlocks.
 template <typename T, int NS>
 __device__ __forceinline__ void delta_tile(const Dims& D, const OpCoef<T>& C,
                                            const T* __restrict__ d,
                                            T* __restrict__ y,
                                            double* __restrict__ partial,
                                            int group, int chunk) {
+  constexpr int nn = NS * NS;
   const int p = tile_node(group);
-  const int t = chunk * kWave + (threadIdx.x & (kWave - 1));
   const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
-  const size_t nn = (size_t)NS * NS;
+  const int lane = threadIdx.x & (kWave - 1);
   double dot = 0.0;
-  if (p < D.real_nodes && t < D.Tt) {
+  if (p < D.real_nodes) {  // wave-uniform
     const int j = uniform(p / K), i = uniform(p - (p / K) * K);
-    T self[NS], acc[NS], nb[NS];
+    const long long nodes = D.nodes;
+    TileBlocks<T, 13 * nn> G;
+    TileBlocks<T, 5 * nn> Cd, Cu;
+    TileBlocks<T, nn> Qi, Qd;
+    G.load(C.G13, nodes * 13 * nn, (long long)p * 13 * nn, lane);
+    Cd.load(C.Cdn, nodes * 5 * nn, (long long)p * 5 * nn, lane);
+    Cu.load(C.Cup, nodes * 5 * nn, (long long)p * 5 * nn, lane);
+    Qi.load(C.Qi, nodes * nn, (long long)p * nn, lane);
+    Qd.load(C.QTd, nodes * nn, (long long)p * nn, lane);
+    const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), ry = vec_rsrc(D, y);
+    const TileTime tt = tile_time<T>(D, chunk);
+    T self[NS], acc[NS], nb[NS], sq[NS];
 #pragma unroll
     for (int a = 0; a < NS; ++a) acc[a] = T(0);
-    load_node<NS>(d, p, t, ldt, self);
-    mv_add<NS>(C.Qi + p * nn, self, acc);
-    if (t == T_) mv_add<NS>(C.QTd + p * nn, self, acc);
-    if (t >= 1) {
+    load_nb<NS>(rd, tt.off, p, ldt, self);
+    Qi.template mv<0, false>(self, acc);
 #pragma unroll
-      for (int k = 0; k < 13; ++k) {
-        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_node<NS>(d, jq * K + iq, t, ldt, nb);
-        mv_add<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
-      }
+    for (int c = 0; c < NS; ++c) sq[c] = self[c];
+    zero_unless<NS>(tt.t == T_, sq);
+    Qd.template mv<0, false>(sq, acc);
+    sfor<0, 13>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+      load_nb<NS>(rd, tt.off, jq * K + iq, ldt, nb);
+      zero_unless<NS>(tt.t >= 1, nb);
+      G.template mv<k * nn, false>(nb, acc);
+    });
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+      load_nb<NS>(rd, tt.prev, jq * K + iq, ldt, nb);
+      zero_unless<NS>(tt.t >= 1, nb);
+      Cd.template mv<k * nn, true>(nb, acc);
+      load_nb<NS>(rd, tt.next, jq * K + iq, ldt, nb);
+      zero_unless<NS>(tt.t < T_, nb);
+      Cu.template mv<k * nn, true>(nb, acc);
+    });
+    store_nb<NS>(ry, tt.valid ? tt.off : kOob, p, ldt, acc);
+    if (tt.valid) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_node<NS>(d, jq * K + iq, t - 1, ldt, nb);
-        mv_sub<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
-      }
+      for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
     }
-    if (t < T_) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_node<NS>(d, jq * K + iq, t + 1, ldt, nb);
-        mv_sub<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
-      }
-    }
-    store_node<NS>(y, p, t, ldt, acc);
-#pragma unroll
-    for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
   }
   dot = block_sum<256>(dot);
   if (partial && threadIdx.x == 0) *partial = dot;
@@ -255,34 +383,33 @@ __device__ __forceinline__ void omega_tile(const Dims& D, const OpCoef<T>& C,
                                            const T* __restrict__ th,
                                            T* __restrict__ tau, int group, int c0,
                                            int c1) {
+  constexpr int nn = NS * NS;
   const int p = tile_node(group);
   const int ldt = D.ldt, K = D.K, N = D.N;
-  const size_t nn = (size_t)NS * NS;
-  constexpr unsigned ES = sizeof(T);
-  if (p >= D.real_nodes) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (p >= D.real_nodes) return;  // wave-uniform
   const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  TileBlocks<T, 13 * nn> G;
+  G.load(C.G13, (long long)D.nodes * 13 * nn, (long long)p * 13 * nn, lane);
   const __amdgpu_buffer_rsrc_t rth = vec_rsrc(D, th), rtau = vec_rsrc(D, tau);
   const __amdgpu_buffer_rsrc_t rrho = vec_rsrc(D, rho ? rho : th);
   for (int chunk = c0; chunk < c1; ++chunk) {
-    const int t = chunk * kWave + (threadIdx.x & (kWave - 1));
-    if (t >= D.Tt) continue;
-    const unsigned toff = (unsigned)t * ES;
+    const TileTime tt = tile_time<T>(D, chunk);
     T acc[NS], nb[NS];
-    if (rho) load_nb<NS>(rrho, toff, p, ldt, acc);
+    if (rho) load_nb<NS>(rrho, tt.off, p, ldt, acc);
     else
 #pragma unroll
       for (int a = 0; a < NS; ++a) acc[a] = T(0);
-    if (t >= 1) {
-#pragma unroll
-      for (int k = 0; k < 13; ++k) {
-        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        if ((jq >> 1) == (j >> 1)) continue;  // same super-column: inside Phi~
-        load_nb<NS>(rth, toff, jq * K + iq, ldt, nb);
-        mv_sub<NS>(C.G13 + ((size_t)p * 13 + k) * nn, nb, acc);
-      }
-    }
-    store_nb<NS>(rtau, toff, p, ldt, acc);
+    sfor<0, 13>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+      if ((jq >> 1) == (j >> 1)) return;  // same super-column: inside Phi~
+      load_nb<NS>(rth, tt.off, jq * K + iq, ldt, nb);
+      zero_unless<NS>(tt.t >= 1, nb);
+      G.template mv<k * nn, true>(nb, acc);
+    });
+    store_nb<NS>(rtau, tt.valid ? tt.off : kOob, p, ldt, acc);
   }
 }
 
@@ -295,42 +422,36 @@ __device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
                                         const T* __restrict__ dl,
                                         T* __restrict__ rho, int group, int c0,
                                         int c1) {
+  constexpr int nn = NS * NS;
   const int p = tile_node(group);
   const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
-  const size_t nn = (size_t)NS * NS;
-  constexpr unsigned ES = sizeof(T);
-  if (p >= D.real_nodes) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (p >= D.real_nodes) return;  // wave-uniform
   const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  TileBlocks<T, 5 * nn> Cd, Cu;
+  Cd.load(C.Cdn, (long long)D.nodes * 5 * nn, (long long)p * 5 * nn, lane);
+  Cu.load(C.Cup, (long long)D.nodes * 5 * nn, (long long)p * 5 * nn, lane);
   const __amdgpu_buffer_rsrc_t rdl = vec_rsrc(D, dl), rrho = vec_rsrc(D, rho);
   const __amdgpu_buffer_rsrc_t rr = vec_rsrc(D, r ? r : dl);
   for (int chunk = c0; chunk < c1; ++chunk) {
-    const int t = chunk * kWave + (threadIdx.x & (kWave - 1));
-    if (t >= D.Tt) continue;
-    const unsigned toff = (unsigned)t * ES;
+    const TileTime tt = tile_time<T>(D, chunk);
     T acc[NS], nb[NS];
-    if (r) load_nb<NS>(rr, toff, p, ldt, acc);
+    if (r) load_nb<NS>(rr, tt.off, p, ldt, acc);
     else
 #pragma unroll
       for (int a = 0; a < NS; ++a) acc[a] = T(0);
-    if (t >= 1) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_nb<NS>(rdl, toff - ES, jq * K + iq, ldt, nb);
-        mv_add<NS>(C.Cdn + ((size_t)p * 5 + k) * nn, nb, acc);
-      }
-    }
-    if (t < T_) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) continue;
-        load_nb<NS>(rdl, toff + ES, jq * K + iq, ldt, nb);
-        mv_add<NS>(C.Cup + ((size_t)p * 5 + k) * nn, nb, acc);
-      }
-    }
-    store_nb<NS>(rrho, toff, p, ldt, acc);
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+      load_nb<NS>(rdl, tt.prev, jq * K + iq, ldt, nb);
+      zero_unless<NS>(tt.t >= 1, nb);
+      Cd.template mv<k * nn, false>(nb, acc);
+      load_nb<NS>(rdl, tt.next, jq * K + iq, ldt, nb);
+      zero_unless<NS>(tt.t < T_, nb);
+      Cu.template mv<k * nn, false>(nb, acc);
+    });
+    store_nb<NS>(rrho, tt.valid ? tt.off : kOob, p, ldt, acc);
   }
 }
 
@@ -339,11 +460,8 @@ __device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
 // row of the wavefront holds the same 16 coefficients.  The product with
 // coefficient j takes it from lane j mod 16 of the lane's own row by a DPP
 // row broadcast (row_newbcast) in the FMA itself (v_fmac_f32_dpp,
-// v_fmac_f64_dpp), so no instruction is spent on moving coefficients (the
-// compiler keeps a separate v_mov_b32_dpp, and has no 64-bit form).  The
-// coefficient registers are written only by vector-memory loads, so the DPP
-// read-after-VALU-write wait states do not apply; a check over the generated
-// code (check_dpp.py) guards this.
+// v_fmac_f64_dpp through dpp_fmac), so no instruction is spent on moving
+// coefficients.
 template <typename T, int NW>
 struct CoefRow;
 template <int NW>
@@ -356,10 +474,7 @@ struct CoefRow<double, NW> {
   }
   template <int J>
   __device__ __forceinline__ double fmac(double acc, double z) const {
-    asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(g[J >> 4]), "v"(z), "n"(J & 15));
-    return acc;
+    return dpp_fmac<J & 15, false>(acc, g[J >> 4], z);
   }
 };
 template <int NW>
@@ -378,10 +493,7 @@ struct CoefRow<float, NW> {
   }
   template <int J>
   __device__ __forceinline__ float fmac(float acc, float z) const {
-    asm("v_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(g[J >> 4]), "v"(z), "n"(J & 15));
-    return acc;
+    return dpp_fmac<J & 15, false>(acc, __builtin_bit_cast(float, g[J >> 4]), z);
   }
 };
 
