@@ -86,19 +86,29 @@ __global__ __launch_bounds__(256) void kb_xi(LQG_BATCH_ARGS, int r, int dl,
 }
 
 // Block-solve items are dealt out round-robin (item = lb + k G) so that the
-// long sweeps of large-K problems spread over all workgroups.
+// long sweeps of large-K problems spread over all workgroups.  A problem with
+// K >= kTwistMin is solved in the twisted order (the same 2n wavefronts: two
+// rows each, half per chain), smaller ones in the one-chain order; both use
+// the one LDS buffer.
 template <int NS>
 __global__ __launch_bounds__(2 * NS * kWave) void kb_solve(LQG_BATCH_ARGS,
                                                            int tau, int out,
                                                            int check) {
-  __shared__ double zb[2][2 * NS][kWave];
+  static_assert(2 * kWavesPerHalf<NS> == 2 * NS, "twisted and one-chain solves share the grid");
+  constexpr int NB = 2 * NS, WK = kWKeepAlloc<double, NS>;
+  __shared__ double zb2[2][2][NB][kWave];
+  __shared__ double wb[2][WK][NB][kWave];
+  auto* zb1 = zb2[0];  // the one-chain exchange buffer
   const int n = *nlive;
   for (int it = xcd_block(); it < n; it += gridDim.x) {
     const Item w = live[it];
     const BatchProb& P = probs[w.prob];
     if (gated_out(scs[w.prob], check)) continue;
-    phi_tile<double, NS>(P.D, op64(P.C), P.v[tau], P.v[out],
-                         scs[w.prob].qt_differs != 0, w.a, w.b, zb);
+    const int qt = scs[w.prob].qt_differs != 0;
+    if (twisted(P.D))
+      phi_tile_twisted<double, NS>(P.D, op64(P.C), P.v[tau], P.v[out], qt, w.a, w.b, zb2, wb);
+    else
+      phi_tile<double, NS>(P.D, op64(P.C), P.v[tau], P.v[out], qt, w.a, w.b, zb1);
   }
 }
 
@@ -298,12 +308,23 @@ __global__ void kb_stencil(BatchDev B) {
     if (q < w.b) stencil(P.D, P.in, P.C, q);
   }
 }
+// Factor units of the problems factored in the twisted order (128 threads,
+// one chain per half) or in the one-chain order (64 threads); each kernel
+// skips the other kind.
+__global__ __launch_bounds__(128) void kb_factor_twisted(BatchDev B) {
+  const Item* u = B.units[kUnitFactor];
+  for (int it = blockIdx.x; it < B.nunits[kUnitFactor]; it += gridDim.x) {
+    const Item w = u[it];
+    const BatchProb& P = B.probs[w.prob];
+    if (twisted(P.D)) factor_twisted(P.D, P.C, P.sc, w.a, w.b);
+  }
+}
 __global__ __launch_bounds__(64) void kb_factor(BatchDev B) {
   const Item* u = B.units[kUnitFactor];
   for (int it = blockIdx.x; it < B.nunits[kUnitFactor]; it += gridDim.x) {
     const Item w = u[it];
     const BatchProb& P = B.probs[w.prob];
-    factor(P.D, P.C, P.sc, w.a, w.b);
+    if (!twisted(P.D)) factor(P.D, P.C, P.sc, w.a, w.b);
   }
 }
 __global__ void kb_rhs_init(BatchDev B) {
@@ -402,8 +423,9 @@ void batch_setup(const BatchDev& B, hipStream_t s) {
   hipLaunchKernelGGL(kb_stencil, dim3(2048), dim3(128), 0, s, B);
 }
 void batch_factor(const BatchDev& B, hipStream_t s) {
-  hipLaunchKernelGGL(kb_factor, dim3(std::max(1, std::min(B.nunits[kUnitFactor], 16384))),
-                     dim3(64), 0, s, B);
+  const dim3 g(std::max(1, std::min(B.nunits[kUnitFactor], 16384)));
+  hipLaunchKernelGGL(kb_factor, g, dim3(64), 0, s, B);
+  hipLaunchKernelGGL(kb_factor_twisted, g, dim3(128), 0, s, B);
 }
 void batch_rhs_init(const BatchDev& B, hipStream_t s) {
   hipLaunchKernelGGL(kb_rhs_init, dim3(1024), dim3(256), 0, s, B);

@@ -68,6 +68,7 @@ size_t coef_bytes(const Dims& D) {
   b += align_up(nodes * (size_t)D.m * D.n * 8); // RiBT
   b += align_up((size_t)2 * D.V * fw_rows(D.K) * NB * kFwRow * 8);
   b += align_up((size_t)2 * D.V * D.K * NB * kBwRow * 8);
+  b += align_up((size_t)2 * D.V * NB * kFwRow * 8);  // Xw
   return b;
 }
 
@@ -91,7 +92,7 @@ Coef coef_at(char* base, const Dims& D) {
   C.RiBT = take(nodes * (size_t)D.m * D.n * 8);
   C.Fw = take((size_t)2 * D.V * fw_rows(D.K) * NB * kFwRow * 8);
   C.Bw = take((size_t)2 * D.V * D.K * NB * kBwRow * 8);
-  C.Xw = nullptr;  // the batched form uses the one-chain factorisation
+  C.Xw = take((size_t)2 * D.V * NB * kFwRow * 8);
   return C;
 }
 

@@ -5,7 +5,8 @@ by the oracle in FP64 on the returned delta~), take the oracle's Algorithm 1
 iteration count within 2, and agree with the oracle's PCG solution within
 kappa * tol (the bound used is 1e-6 relative, as for the single-problem
 path).  The batches mix odd and even N, K = 1 and N = 1, one to four 64-wide
-time tiles with ragged tails, and a distinct terminal weight.
+time tiles with ragged tails, a distinct terminal weight, and K below and
+above 8 (one-chain and twisted Phi_bar factorisations in one batch).
 """
 import sys
 
@@ -30,8 +31,10 @@ UNEVEN = [
     (3, 5, 64, 4, 2, 0.7),      # T+1 = 65
     (1, 5, 9, 4, 2, 1.0),       # K = 1
     (6, 1, 9, 4, 3, 1.0),       # N = 1
-    (9, 8, 200, 4, 2, 1.0),     # four time tiles
+    (9, 8, 200, 4, 2, 1.0),     # four time tiles; K >= 8: twisted Phi_bar order
     (2, 3, 1, 4, 2, 1.0),       # T = 1
+    (12, 5, 70, 4, 2, 2.0),     # twisted, odd N, QT != Q
+    (17, 4, 30, 4, 3, 1.0),     # twisted, odd K
 ]
 
 
@@ -78,7 +81,8 @@ def test_batch_equals_single_problem_path(lib, torch):
     """Each problem of a batch takes the same iterations as the
     single-problem solve and lands within kappa * tol of it."""
     from paper_2304_04980_amd import lqgrid
-    probs = uneven_problems()[:4]
+    allp = uneven_problems()
+    probs = [allp[k] for k in (0, 1, 6, 8)]  # one-chain and twisted Phi_bar orders
     opts = lqgrid.default_opts(tol=1e-10)
     outs, infos, st = lqgrid.batch_solve(probs, opts=opts)
     assert st == lqgrid.OK
