@@ -1148,11 +1148,14 @@ __device__ __forceinline__ void phi_tile_twisted(const Dims& D, const OpCoef<T>&
   if (qt_distinct && t0 <= T_ && T_ < t0 + kWave)
     twisted_dispatch<T, NS>(wi, D, C, 1, v, lane, t, valid && t == T_, top, rtau, rout, zo,
                             zx, wl);
-  if (chunk == 0) {  // t = 0: theta = Q tau per node; item = (block row i, row R)
+  {  // t = 0: theta = Q tau per node, item = (block row i, row R), spread over
+     // the time-chunk workgroups of this super-column so none runs long
     const size_t nn = (size_t)NS * NS;
     gptr<const T> tg = glob(tau);
     gptr<T> og = glob(out);
-    for (int item = threadIdx.x; item < D.K * NB; item += 2 * WH * kWave) {
+    const int nthr = 2 * WH * kWave;
+    for (int item = chunk * nthr + threadIdx.x; item < D.K * NB;
+         item += time_chunks(D) * nthr) {
       const int i = item / NB, R = item - (item / NB) * NB;
       const int h = R / NS, a = R % NS;
       const int p = (2 * v + h) * D.K + i;
