@@ -281,7 +281,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const Dims& D, const 
 // Per-lane time offsets of a tile row: every lane (also those past the last
 // step) stays active so that the DPP-broadcast FMAs read valid source lanes;
 // loads use time indices clamped into [0, Tt), so every access lies inside
-// its row, and results of lanes past Tt are discarded by the stores.
+// its row (finite data), terms outside their time range are masked by
+// selects, and results of lanes past Tt are discarded by the stores.
 struct TileTime {
   int t;               // this lane's time step
   bool valid;          // t < Tt
@@ -395,20 +396,24 @@ __device__ __forceinline__ void omega_tile(const Dims& D, const OpCoef<T>& C,
   const __amdgpu_buffer_rsrc_t rrho = vec_rsrc(D, rho ? rho : th);
   for (int chunk = c0; chunk < c1; ++chunk) {
     const TileTime tt = tile_time<T>(D, chunk);
-    T acc[NS], nb[NS];
+    T acc[NS], a1[NS], nb[NS];
     if (rho) load_nb<NS>(rrho, tt.off, p, ldt, acc);
     else
 #pragma unroll
       for (int a = 0; a < NS; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) a1[a] = T(0);
     sfor<0, 13>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
       if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
       if ((jq >> 1) == (j >> 1)) return;  // same super-column: inside Phi~
       load_nb<NS>(rth, tt.off, jq * K + iq, ldt, nb);
-      zero_unless<NS>(tt.t >= 1, nb);
-      G.template mv<k * nn, true>(nb, acc);
+      G.template mv<k * nn, true>(nb, a1);
     });
+    zero_unless<NS>(tt.t >= 1, a1);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] += a1[a];
     store_nb<NS>(rtau, tt.valid ? tt.off : kOob, p, ldt, acc);
   }
 }
@@ -435,22 +440,26 @@ __device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
   const __amdgpu_buffer_rsrc_t rr = vec_rsrc(D, r ? r : dl);
   for (int chunk = c0; chunk < c1; ++chunk) {
     const TileTime tt = tile_time<T>(D, chunk);
-    T acc[NS], nb[NS];
+    T acc[NS], a1[NS], a2[NS], nb[NS];
     if (r) load_nb<NS>(rr, tt.off, p, ldt, acc);
     else
 #pragma unroll
       for (int a = 0; a < NS; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) a1[a] = a2[a] = T(0);
     sfor<0, 5>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
       if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
       load_nb<NS>(rdl, tt.prev, jq * K + iq, ldt, nb);
-      zero_unless<NS>(tt.t >= 1, nb);
-      Cd.template mv<k * nn, false>(nb, acc);
+      Cd.template mv<k * nn, false>(nb, a1);
       load_nb<NS>(rdl, tt.next, jq * K + iq, ldt, nb);
-      zero_unless<NS>(tt.t < T_, nb);
-      Cu.template mv<k * nn, false>(nb, acc);
+      Cu.template mv<k * nn, false>(nb, a2);
     });
+    zero_unless<NS>(tt.t >= 1, a1);
+    zero_unless<NS>(tt.t < T_, a2);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] += a1[a] + a2[a];
     store_nb<NS>(rrho, tt.valid ? tt.off : kOob, p, ldt, acc);
   }
 }
