@@ -36,6 +36,18 @@ __global__ __launch_bounds__(256) void k_delta(Dims D, OpCoef<T> C,
   if (is_done(sc, check)) return;
   const int ngroups = node_groups(D);
   const int lb = xcd_block();
+  if constexpr (sizeof(T) == 4) {
+    if (tail_packed<NS>(D)) {  // regular chunks, then the packed last chunk
+      const int nreg = ngroups * (time_chunks(D) - 1);
+      if (lb >= nreg + tail_groups(D)) return;
+      if (lb >= nreg)
+        delta_tail<NS>(D, C, d, y, partial ? partial + lb : nullptr, lb - nreg);
+      else
+        delta_tile<T, NS>(D, C, d, y, partial ? partial + lb : nullptr, lb % ngroups,
+                          lb / ngroups);
+      return;
+    }
+  }
   if (lb >= ngroups * time_chunks(D)) return;
   delta_tile<T, NS>(D, C, d, y, partial ? partial + lb : nullptr, lb % ngroups,
                     lb / ngroups);
@@ -143,6 +155,14 @@ __global__ __launch_bounds__(256) void k_recover(Dims D, Coef C,
 inline int node_blocks(const Dims& D) {
   return ((D.real_nodes + 3) / 4) * ((D.Tt + kWave - 1) / kWave);
 }
+// blocks of the FP32 Delta apply: regular chunks plus packed tail groups when
+// the last chunk holds at most 16 steps
+inline int delta_blocks_f32(const Dims& D) {
+  const int nc = (D.Tt + kWave - 1) / kWave;
+  if (nc >= 2 && D.Tt - (nc - 1) * kWave <= 16)
+    return ((D.real_nodes + 3) / 4) * (nc - 1) + (D.real_nodes + 15) / 16;
+  return node_blocks(D);
+}
 inline dim3 node_grid(const Dims& D) { return dim3(padded_grid(node_blocks(D))); }
 inline dim3 group_grid(const Dims& D) { return dim3(padded_grid(node_groups(D))); }
 
@@ -161,13 +181,14 @@ template <typename T>
 int delta_apply(const Dims& D, const OpCoef<T>& C, const T* d, T* y,
                 double* partial, const Scalars* sc, int check_done,
                 hipStream_t s) {
-  const dim3 g = node_grid(D);
+  const int nb = sizeof(T) == 4 ? delta_blocks_f32(D) : node_blocks(D);
+  const dim3 g(padded_grid(nb));
 #define CALL(NS)                                                              \
   hipLaunchKernelGGL((k_delta<T, NS>), g, dim3(256), 0, s, D, C, d, y, partial, \
                      sc, check_done)
   LQG_DISPATCH_N(D.n, CALL)
 #undef CALL
-  return node_blocks(D);
+  return nb;
 }
 
 template <typename T>
