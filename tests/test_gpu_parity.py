@@ -218,7 +218,10 @@ def test_error_paths(lib, torch):
 # ------------------------------------------------------------ precision form
 F32_CASES = [(4, 4, 20, 2, 1, 1.0), (5, 7, 150, 3, 2, 1.0), (3, 5, 64, 4, 2, 0.7),
              (6, 1, 9, 2, 2, 1.0), (8, 4, 70, 4, 2, 1.0), (9, 6, 40, 3, 2, 2.5),
-             (33, 2, 20, 4, 3, 1.0), (128, 2, 20, 4, 2, 1.3)]
+             (33, 2, 20, 4, 3, 1.0), (128, 2, 20, 4, 2, 1.3),
+             # last 64-step tile of at most 16 steps: packed 4-node tails, node
+             # count not a multiple of 4 (or of 16), n = 3 and n = 2
+             (7, 3, 129, 3, 2, 1.0), (5, 3, 66, 2, 1, 1.0)]
 
 
 @pytest.mark.parametrize("case", F32_CASES, ids=[str(c) for c in F32_CASES])
