@@ -561,6 +561,109 @@ __device__ __forceinline__ void xi_tile(const Dims& D, const OpCoef<T>& C,
   }
 }
 
+// Whole-wavefront lane moves (DPP wave_shr / wave_shl / wave_ror /
+// wave_rol by one lane); a 64-bit value moves as two 32-bit halves.  A lane
+// whose source lies outside the wavefront keeps `old`.
+constexpr int kWaveShl1 = 0x130, kWaveRol1 = 0x134, kWaveShr1 = 0x138, kWaveRor1 = 0x13C;
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float old, float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double old, double x) {
+  const long long o = __double_as_longlong(old), v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi =
+      __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// lane l <- x[l-1]; lane 0 <- prev[63]
+template <typename T>
+__device__ __forceinline__ T from_prev_lane(T x, T prev) {
+  return dpp_mov<kWaveShr1>(dpp_mov<kWaveRor1>(prev, prev), x);
+}
+// lane l <- x[l+1]; lane 63 <- next[0]
+template <typename T>
+__device__ __forceinline__ T from_next_lane(T x, T next) {
+  return dpp_mov<kWaveShl1>(dpp_mov<kWaveRol1>(next, next), x);
+}
+
+// rho = r + Xi~ dl for one node over all its time chunks.  The 5-point
+// blocks do not depend on t, so with W_t = sum_5 Cdn[p][k] dl_t(q) and
+// V_t = sum_5 Cup[p][k] dl_t(q) the right-hand side is
+// [t>=1] W_{t-1} + [t<T] V_{t+1}: one aligned read of each neighbour per
+// chunk forms W and V, which reach the lanes of t+1 and t-1 by lane moves; the
+// chunk boundaries take lane 63 of the previous chunk's W and lane 0 of the
+// next chunk's V, computed one chunk ahead.  Same terms and order as
+// xi_tile, so the same sums.
+template <typename T, int NS>
+__device__ __forceinline__ void xi_rows(const Dims& D, const OpCoef<T>& C,
+                                        const T* __restrict__ r,
+                                        const T* __restrict__ dl,
+                                        T* __restrict__ rho, int group) {
+  constexpr int nn = NS * NS;
+  const int p = tile_node(group);
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (p >= D.real_nodes) return;  // wave-uniform
+  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  TileBlocks<T, 5 * nn> Cd, Cu;
+  Cd.load(C.Cdn, (long long)D.nodes * 5 * nn, (long long)p * 5 * nn, lane);
+  Cu.load(C.Cup, (long long)D.nodes * 5 * nn, (long long)p * 5 * nn, lane);
+  const __amdgpu_buffer_rsrc_t rdl = vec_rsrc(D, dl), rrho = vec_rsrc(D, rho);
+  const __amdgpu_buffer_rsrc_t rr = vec_rsrc(D, r ? r : dl);
+  const int nc = time_chunks(D);
+  auto prod = [&](int c, T(&W)[NS], T(&V)[NS]) {
+    const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) W[a] = V[a] = T(0);
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+      T nb[NS];
+      load_nb<NS>(rdl, off, jq * K + iq, ldt, nb);
+      Cd.template mv<k * nn, false>(nb, W);
+      Cu.template mv<k * nn, false>(nb, V);
+    });
+  };
+  T Wp[NS], W[NS], V[NS], Wn[NS], Vn[NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) Wp[a] = T(0);
+  prod(0, W, V);
+  for (int c = 0; c < nc; ++c) {
+    if (c + 1 < nc) {
+      prod(c + 1, Wn, Vn);
+    } else {
+#pragma unroll
+      for (int a = 0; a < NS; ++a) Wn[a] = Vn[a] = T(0);
+    }
+    const TileTime tt = tile_time<T>(D, c);
+    T acc[NS], a1[NS], a2[NS];
+    if (r) load_nb<NS>(rr, tt.off, p, ldt, acc);
+    else
+#pragma unroll
+      for (int a = 0; a < NS; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      a1[a] = from_prev_lane(W[a], Wp[a]);
+      a2[a] = from_next_lane(V[a], Vn[a]);
+    }
+    zero_unless<NS>(tt.t >= 1, a1);
+    zero_unless<NS>(tt.t < T_, a2);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] += a1[a] + a2[a];
+    store_nb<NS>(rrho, tt.valid ? tt.off : kOob, p, ldt, acc);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      Wp[a] = W[a];
+      W[a] = Wn[a];
+      V[a] = Vn[a];
+    }
+  }
+}
+
 // One row of NW factor coefficients of a block row, as the sweeps read it:
 // lane l holds coefficient 16 g + (l mod 16) in register g, i.e. every 16-lane
 // row of the wavefront holds the same 16 coefficients.  The product with

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_xi(Dims D, OpCoef<T> C,
   if (is_done(sc, check)) return;
   const int lb = xcd_block();
   if (lb >= node_groups(D)) return;
-  xi_tile<T, NS>(D, C, r, dl, rho, lb, 0, time_chunks(D));
+  xi_rows<T, NS>(D, C, r, dl, rho, lb);
 }
 
 // One workgroup of 2n wavefronts per (super-column v, 64 time steps),
