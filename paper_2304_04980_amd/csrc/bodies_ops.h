@@ -192,14 +192,6 @@ struct NodeBlocks {
     for (int k = 0; k < kRegs; ++k)
       g[k] = buf_lds<T>(rs, (unsigned)((16 * k + (lane & 15)) * sizeof(T)), base);
   }
-  // the same with a per-lane first coefficient (each 16-lane row may hold a
-  // different node's blocks)
-  __device__ __forceinline__ void load_lane(__amdgpu_buffer_rsrc_t rs, unsigned first,
-                                            int lane) {
-#pragma unroll
-    for (int k = 0; k < kRegs; ++k)
-      g[k] = buf_lds<T>(rs, (unsigned)((first + 16 * k + (lane & 15)) * sizeof(T)), 0u);
-  }
   // acc +=/-= M x, M the NS x NS row-major block starting at coefficient J0
   template <int J0, bool NEG, int NS>
   __device__ __forceinline__ void mv(const T (&x)[NS], T (&acc)[NS]) const {
@@ -378,95 +370,6 @@ __device__ __forceinline__ void delta_tile(const Dims& D, const OpCoef<T>& C,
 #pragma unroll
       for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
     }
-  }
-  dot = block_sum<256>(dot);
-  if (partial && threadIdx.x == 0) *partial = dot;
-}
-
-// The last time chunk of the FP32 Delta apply when it holds at most 16 steps
-// (and is not the only chunk): one wavefront covers 4 nodes x 16 steps, each
-// 16-lane row one node whose blocks that row's DPP broadcasts read, so the
-// chunk costs a quarter of the wavefronts it would otherwise.  Addresses are
-// per lane; a neighbour outside the grid is read at the node itself (finite
-// data) and meets the zero block the assembly stores for it.  A workgroup
-// covers 16 nodes (group tg); its FP64 partial of y'd goes to *partial.
-template <int NS>
-__device__ __forceinline__ bool tail_packed(const Dims& D) {
-  return time_chunks(D) >= 2 && D.Tt - (time_chunks(D) - 1) * kWave <= 16;
-}
-__host__ __device__ inline int tail_groups(const Dims& D) { return (D.real_nodes + 15) / 16; }
-
-template <int NS>
-__device__ __forceinline__ void delta_tail(const Dims& D, const OpCoef<float>& C,
-                                           const float* __restrict__ d,
-                                           float* __restrict__ y,
-                                           double* __restrict__ partial, int tg) {
-  using T = float;
-  constexpr int nn = NS * NS;
-  constexpr unsigned ES = sizeof(T);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int p = tg * 16 + (threadIdx.x >> 6) * 4 + (lane >> 4);
-  const int K = D.K, N = D.N, ldt = D.ldt, T_ = D.T;
-  const bool pvalid = p < D.real_nodes;
-  const int pc = pvalid ? p : 0;
-  const int j = pc / K, i = pc - j * K;
-  const int t = (time_chunks(D) - 1) * kWave + (lane & 15);
-  const bool valid = pvalid && t < D.Tt;
-  const unsigned toff = (unsigned)min(t, D.Tt - 1) * ES;
-  const long long nodes = D.nodes;
-  NodeBlocks<T, 13 * nn> G;
-  NodeBlocks<T, 5 * nn> Cd, Cu;
-  NodeBlocks<T, nn> Qi, Qd;
-  G.load_lane(block_rsrc(C.G13, nodes * 13 * nn), (unsigned)(pc * 13 * nn), lane);
-  Cd.load_lane(block_rsrc(C.Cdn, nodes * 5 * nn), (unsigned)(pc * 5 * nn), lane);
-  Cu.load_lane(block_rsrc(C.Cup, nodes * 5 * nn), (unsigned)(pc * 5 * nn), lane);
-  Qi.load_lane(block_rsrc(C.Qi, nodes * nn), (unsigned)(pc * nn), lane);
-  Qd.load_lane(block_rsrc(C.QTd, nodes * nn), (unsigned)(pc * nn), lane);
-  const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), ry = vec_rsrc(D, y);
-  const unsigned node_bytes = (unsigned)(NS * ldt) * ES;
-  // components of node q at the lane's time offset (+ dt steps, in range)
-  auto ld = [&](int q, int dt, T(&x)[NS]) {
-    const unsigned v = (unsigned)q * node_bytes + toff + (unsigned)(dt * (int)ES);
-#pragma unroll
-    for (int c = 0; c < NS; ++c) x[c] = buf_lds<T>(rd, v, (unsigned)(c * ldt) * ES);
-  };
-  auto nbq = [&](int di, int dj) {  // neighbour index, or the node itself outside
-    const int iq = i + di, jq = j + dj;
-    return (iq >= 0 && iq < K && jq >= 0 && jq < N) ? jq * K + iq : pc;
-  };
-  T self[NS], acc[NS], nb[NS], sq[NS];
-#pragma unroll
-  for (int a = 0; a < NS; ++a) acc[a] = T(0);
-  ld(pc, 0, self);
-  Qi.template mv<0, false>(self, acc);
-#pragma unroll
-  for (int c = 0; c < NS; ++c) sq[c] = self[c];
-  zero_unless<NS>(t == T_, sq);
-  Qd.template mv<0, false>(sq, acc);
-  // t >= 64 here, so every t >= 1 term applies; t + 1 stays below Tt except
-  // at t = T, where the Cup terms are masked
-  const int dn = t < T_ ? 1 : 0;
-  sfor<0, 13>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    ld(nbq(kOff13[k][0], kOff13[k][1]), 0, nb);
-    G.template mv<k * nn, false>(nb, acc);
-  });
-  sfor<0, 5>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    const int q = nbq(kOff5[k][0], kOff5[k][1]);
-    ld(q, -1, nb);
-    Cd.template mv<k * nn, true>(nb, acc);
-    ld(q, dn, nb);
-    zero_unless<NS>(t < T_, nb);
-    Cu.template mv<k * nn, true>(nb, acc);
-  });
-  const unsigned so = valid ? (unsigned)p * node_bytes + (unsigned)t * ES : kOob;
-#pragma unroll
-  for (int c = 0; c < NS; ++c) buf_sts(ry, so, (unsigned)(c * ldt) * ES, acc[c]);
-  double dot = 0.0;
-  if (valid) {
-#pragma unroll
-    for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
   }
   dot = block_sum<256>(dot);
   if (partial && threadIdx.x == 0) *partial = dot;
@@ -662,6 +565,120 @@ __device__ __forceinline__ void xi_rows(const Dims& D, const OpCoef<T>& C,
       V[a] = Vn[a];
     }
   }
+}
+
+constexpr bool five_point_leads_thirteen() {
+  for (int k = 0; k < 5; ++k)
+    if (kOff5[k][0] != kOff13[k][0] || kOff5[k][1] != kOff13[k][1]) return false;
+  return true;
+}
+static_assert(five_point_leads_thirteen(), "the 5-point offsets lead the 13-point list");
+
+// y = Delta d for one node over all its time chunks (the sum as in
+// delta_tile), with the Cdn / Cup terms formed as in xi_rows: the 13 aligned
+// neighbour reads of a chunk give sum_13 G d_t(q), W_t = sum_5 Cdn d_t(q) and
+// V_t = sum_5 Cup d_t(q), and W_{t-1}, V_{t+1} reach their lanes by lane
+// moves, the chunk boundaries from the neighbouring chunks (one chunk ahead).
+// The workgroup's FP64 partial of y'd goes to *partial.  Every thread of the
+// workgroup must call this.
+template <typename T, int NS>
+__device__ __forceinline__ void delta_rows(const Dims& D, const OpCoef<T>& C,
+                                           const T* __restrict__ d,
+                                           T* __restrict__ y,
+                                           double* __restrict__ partial, int group) {
+  constexpr int nn = NS * NS;
+  const int p = tile_node(group);
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const int lane = threadIdx.x & (kWave - 1);
+  double dot = 0.0;
+  if (p < D.real_nodes) {  // wave-uniform
+    const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+    const long long nodes = D.nodes;
+    TileBlocks<T, 13 * nn> G;
+    TileBlocks<T, 5 * nn> Cd, Cu;
+    TileBlocks<T, nn> Qi, Qd;
+    G.load(C.G13, nodes * 13 * nn, (long long)p * 13 * nn, lane);
+    Cd.load(C.Cdn, nodes * 5 * nn, (long long)p * 5 * nn, lane);
+    Cu.load(C.Cup, nodes * 5 * nn, (long long)p * 5 * nn, lane);
+    Qi.load(C.Qi, nodes * nn, (long long)p * nn, lane);
+    Qd.load(C.QTd, nodes * nn, (long long)p * nn, lane);
+    const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), ry = vec_rsrc(D, y);
+    const int nc = time_chunks(D);
+    struct Prod {
+      T self[NS], g[NS], w[NS], v[NS];
+    };
+    auto prod = [&](int c, Prod& P) {
+      const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
+#pragma unroll
+      for (int a = 0; a < NS; ++a) P.g[a] = P.w[a] = P.v[a] = T(0);
+      load_nb<NS>(rd, off, p, ldt, P.self);
+      sfor<0, 13>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+        T nb[NS];
+        if constexpr (k == 0) {
+#pragma unroll
+          for (int a = 0; a < NS; ++a) nb[a] = P.self[a];
+        } else {
+          load_nb<NS>(rd, off, jq * K + iq, ldt, nb);
+        }
+        G.template mv<k * nn, false>(nb, P.g);
+        if constexpr (k < 5) {  // the 5-point offsets lead the 13-point list
+          Cd.template mv<k * nn, false>(nb, P.w);
+          Cu.template mv<k * nn, false>(nb, P.v);
+        }
+      });
+    };
+    Prod cur, nxt;
+    T wp[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) wp[a] = T(0);
+    prod(0, cur);
+    for (int c = 0; c < nc; ++c) {
+      if (c + 1 < nc) {
+        prod(c + 1, nxt);
+      } else {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) nxt.v[a] = T(0);
+      }
+      const TileTime tt = tile_time<T>(D, c);
+      T acc[NS], sq[NS], a1[NS], a2[NS];
+#pragma unroll
+      for (int a = 0; a < NS; ++a) acc[a] = T(0);
+      Qi.template mv<0, false>(cur.self, acc);
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        sq[a] = cur.self[a];
+        a1[a] = from_prev_lane(cur.w[a], wp[a]);
+        a2[a] = from_next_lane(cur.v[a], nxt.v[a]);
+      }
+      zero_unless<NS>(tt.t == T_, sq);
+      Qd.template mv<0, false>(sq, acc);
+      T g[NS];
+#pragma unroll
+      for (int a = 0; a < NS; ++a) g[a] = cur.g[a] - a1[a];
+      zero_unless<NS>(tt.t >= 1, g);
+      zero_unless<NS>(tt.t < T_, a2);
+#pragma unroll
+      for (int a = 0; a < NS; ++a) acc[a] += g[a] - a2[a];
+      store_nb<NS>(ry, tt.valid ? tt.off : kOob, p, ldt, acc);
+      if (tt.valid) {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)cur.self[a], dot);
+      }
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        wp[a] = cur.w[a];
+        cur.self[a] = nxt.self[a];
+        cur.g[a] = nxt.g[a];
+        cur.w[a] = nxt.w[a];
+        cur.v[a] = nxt.v[a];
+      }
+    }
+  }
+  dot = block_sum<256>(dot);
+  if (partial && threadIdx.x == 0) *partial = dot;
 }
 
 // One row of NW factor coefficients of a block row, as the sweeps read it:

@@ -19,12 +19,10 @@ __device__ __forceinline__ bool node_tile(const Dims& D, int* lb, int* p, int* t
   return true;
 }
 
-// The stencil kernels of the iteration.  Delta apply: one workgroup per
-// node tile (group of 4 nodes x one time chunk, chunk-major); its 24
-// neighbour loads per node dominate, so more and shorter wavefronts keep more
-// of them in flight.  Omega~ / Xi~ right-hand sides: one workgroup per group
-// of 4 nodes running all time chunks, so the nodes' operator blocks come from
-// the scalar cache after the first chunk.  Blocks are XCD-remapped, so an XCD
+// The stencil kernels of the iteration: one workgroup per group of 4 nodes,
+// each wavefront one node over all its time chunks, so that the node's
+// operator blocks are read once and a chunk's t-1 / t+1 terms come from the
+// neighbouring chunks by lane moves.  Blocks are XCD-remapped, so an XCD
 // holds neighbouring nodes.
 
 template <typename T, int NS>
@@ -34,23 +32,9 @@ __global__ __launch_bounds__(256) void k_delta(Dims D, OpCoef<T> C,
                                                double* __restrict__ partial,
                                                const Scalars* sc, int check) {
   if (is_done(sc, check)) return;
-  const int ngroups = node_groups(D);
   const int lb = xcd_block();
-  if constexpr (sizeof(T) == 4) {
-    if (tail_packed<NS>(D)) {  // regular chunks, then the packed last chunk
-      const int nreg = ngroups * (time_chunks(D) - 1);
-      if (lb >= nreg + tail_groups(D)) return;
-      if (lb >= nreg)
-        delta_tail<NS>(D, C, d, y, partial ? partial + lb : nullptr, lb - nreg);
-      else
-        delta_tile<T, NS>(D, C, d, y, partial ? partial + lb : nullptr, lb % ngroups,
-                          lb / ngroups);
-      return;
-    }
-  }
-  if (lb >= ngroups * time_chunks(D)) return;
-  delta_tile<T, NS>(D, C, d, y, partial ? partial + lb : nullptr, lb % ngroups,
-                    lb / ngroups);
+  if (lb >= node_groups(D)) return;
+  delta_rows<T, NS>(D, C, d, y, partial ? partial + lb : nullptr, lb);
 }
 
 template <typename T, int NS>
@@ -155,14 +139,6 @@ __global__ __launch_bounds__(256) void k_recover(Dims D, Coef C,
 inline int node_blocks(const Dims& D) {
   return ((D.real_nodes + 3) / 4) * ((D.Tt + kWave - 1) / kWave);
 }
-// blocks of the FP32 Delta apply: regular chunks plus packed tail groups when
-// the last chunk holds at most 16 steps
-inline int delta_blocks_f32(const Dims& D) {
-  const int nc = (D.Tt + kWave - 1) / kWave;
-  if (nc >= 2 && D.Tt - (nc - 1) * kWave <= 16)
-    return ((D.real_nodes + 3) / 4) * (nc - 1) + (D.real_nodes + 15) / 16;
-  return node_blocks(D);
-}
 inline dim3 node_grid(const Dims& D) { return dim3(padded_grid(node_blocks(D))); }
 inline dim3 group_grid(const Dims& D) { return dim3(padded_grid(node_groups(D))); }
 
@@ -181,7 +157,7 @@ template <typename T>
 int delta_apply(const Dims& D, const OpCoef<T>& C, const T* d, T* y,
                 double* partial, const Scalars* sc, int check_done,
                 hipStream_t s) {
-  const int nb = sizeof(T) == 4 ? delta_blocks_f32(D) : node_blocks(D);
+  const int nb = node_groups(D);  // one partial of y'd per workgroup
   const dim3 g(padded_grid(nb));
 #define CALL(NS)                                                              \
   hipLaunchKernelGGL((k_delta<T, NS>), g, dim3(256), 0, s, D, C, d, y, partial, \
