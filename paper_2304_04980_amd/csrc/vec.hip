@@ -14,13 +14,50 @@ namespace {
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; \
        g += (long long)gridDim.x * blockDim.x)
 
+// k_dir and k_dot stream 16-byte units (4 floats / 2 doubles), two per
+// thread and loop pass, so that each wavefront keeps more bytes in flight; a
+// vector length that is not a multiple of the unit ends in a scalar tail
+// (D.vlen always is one).  k_update, with four streams, keeps the plain loop,
+// which measured faster.
+template <typename T>
+struct alignas(16) Unit16 {
+  static constexpr int kLanes = 16 / sizeof(T);
+  T e[kLanes];
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_dir(long long n, const T* __restrict__ q,
                                              T* __restrict__ d,
                                              const Scalars* sc) {
   if (sc->done) return;
+  using V = Unit16<T>;
+  constexpr int W = V::kLanes;
   const T beta = (T)sc->beta;
-  GRID_STRIDE(g, n) d[g] = fma(beta, d[g], q[g]);
+  const long long nu = n / W, stride = (long long)gridDim.x * blockDim.x;
+  const V* __restrict__ qv = reinterpret_cast<const V*>(q);
+  V* __restrict__ dv = reinterpret_cast<V*>(d);
+  long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; g + stride < nu; g += 2 * stride) {
+    V a = dv[g], b = dv[g + stride];
+    const V qa = qv[g], qb = qv[g + stride];
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      a.e[e] = fma(beta, a.e[e], qa.e[e]);
+      b.e[e] = fma(beta, b.e[e], qb.e[e]);
+    }
+    dv[g] = a;
+    dv[g + stride] = b;
+  }
+  if (g < nu) {
+    V a = dv[g];
+    const V qa = qv[g];
+#pragma unroll
+    for (int e = 0; e < W; ++e) a.e[e] = fma(beta, a.e[e], qa.e[e]);
+    dv[g] = a;
+  }
+  for (long long t = nu * W + (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += stride)
+    d[t] = fma(beta, d[t], q[t]);
 }
 
 template <typename T>
@@ -50,8 +87,28 @@ __global__ __launch_bounds__(256) void k_dot(long long n, const T* __restrict__ 
                                              double* __restrict__ partial,
                                              const Scalars* sc, int check) {
   if (check && sc->done) return;
+  using V = Unit16<T>;
+  constexpr int W = V::kLanes;
+  const long long nu = n / W, stride = (long long)gridDim.x * blockDim.x;
+  const V* __restrict__ av = reinterpret_cast<const V*>(a);
+  const V* __restrict__ bv = reinterpret_cast<const V*>(b);
   double acc = 0.0;
-  GRID_STRIDE(g, n) acc = fma((double)a[g], (double)b[g], acc);
+  long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; g + stride < nu; g += 2 * stride) {
+    const V a0 = av[g], b0 = bv[g], a1 = av[g + stride], b1 = bv[g + stride];
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc = fma((double)a0.e[e], (double)b0.e[e], acc);
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc = fma((double)a1.e[e], (double)b1.e[e], acc);
+  }
+  if (g < nu) {
+    const V a0 = av[g], b0 = bv[g];
+#pragma unroll
+    for (int e = 0; e < W; ++e) acc = fma((double)a0.e[e], (double)b0.e[e], acc);
+  }
+  for (long long t = nu * W + (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += stride)
+    acc = fma((double)a[t], (double)b[t], acc);
   acc = block_sum<256>(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
