@@ -14,11 +14,11 @@ namespace {
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < n; \
        g += (long long)gridDim.x * blockDim.x)
 
-// k_dir and k_dot stream 16-byte units (4 floats / 2 doubles), two per
-// thread and loop pass, so that each wavefront keeps more bytes in flight; a
-// vector length that is not a multiple of the unit ends in a scalar tail
-// (D.vlen always is one).  k_update, with four streams, keeps the plain loop,
-// which measured faster.
+// In FP32, k_dir and k_dot stream 16-byte units (4 floats), two per thread
+// and loop pass, so that each wavefront keeps more bytes in flight; a vector
+// length that is not a multiple of the unit ends in a scalar tail (D.vlen
+// always is one).  FP64 and k_update (four streams) keep the plain loop,
+// which measured faster there.
 template <typename T>
 struct alignas(16) Unit16 {
   static constexpr int kLanes = 16 / sizeof(T);
@@ -30,9 +30,13 @@ __global__ __launch_bounds__(256) void k_dir(long long n, const T* __restrict__ 
                                              T* __restrict__ d,
                                              const Scalars* sc) {
   if (sc->done) return;
+  const T beta = (T)sc->beta;
+  if constexpr (sizeof(T) == 8) {
+    GRID_STRIDE(g, n) d[g] = fma(beta, d[g], q[g]);
+    return;
+  }
   using V = Unit16<T>;
   constexpr int W = V::kLanes;
-  const T beta = (T)sc->beta;
   const long long nu = n / W, stride = (long long)gridDim.x * blockDim.x;
   const V* __restrict__ qv = reinterpret_cast<const V*>(q);
   V* __restrict__ dv = reinterpret_cast<V*>(d);
@@ -87,12 +91,18 @@ __global__ __launch_bounds__(256) void k_dot(long long n, const T* __restrict__ 
                                              double* __restrict__ partial,
                                              const Scalars* sc, int check) {
   if (check && sc->done) return;
+  double acc = 0.0;
+  if constexpr (sizeof(T) == 8) {
+    GRID_STRIDE(g, n) acc = fma((double)a[g], (double)b[g], acc);
+    acc = block_sum<256>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    return;
+  }
   using V = Unit16<T>;
   constexpr int W = V::kLanes;
   const long long nu = n / W, stride = (long long)gridDim.x * blockDim.x;
   const V* __restrict__ av = reinterpret_cast<const V*>(a);
   const V* __restrict__ bv = reinterpret_cast<const V*>(b);
-  double acc = 0.0;
   long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (; g + stride < nu; g += 2 * stride) {
     const V a0 = av[g], b0 = bv[g], a1 = av[g + stride], b1 = bv[g + stride];
