@@ -416,7 +416,10 @@ def main():
         "rel_kkt_residual": chosen["rel_kkt_residual"],
         "kernels": chosen["kernels"],
         "kernel_timing": f"HIP events on the library's stream around every "
-                         f"{PROFILE_STRIDE}th launch of each kernel in the timed steps",
+                         f"{PROFILE_STRIDE}th launch of each kernel in the timed steps, "
+                         "without the check batch in which each PCG run stops (its "
+                         "launches may exit at once); a timed launch includes its "
+                         "dispatch and completion",
         "roofline": roofline,
         "plain_fp64": None if plain is None else {
             k: plain[k] for k in ("value", "ms_per_step", "converged", "pcg_iterations",

@@ -185,9 +185,11 @@ LQGRID_API int lqgrid_apply_operator(lqgrid_ctx *ctx, int op, int outer_S, int i
  * context's stream around every enable-th launch of each hot kernel
  * (enable = 1: every launch; enable <= 0 stops recording).  An event pair
  * between two launches serialises their dispatch, so a stride above 1 keeps
- * the timed calls close to untimed ones.  Used by the benchmark to time the
- * dominant kernel.  Returns LQGRID_EINVAL for a null ctx, LQGRID_EHIP if
- * resolving pending events fails. */
+ * the timed calls close to untimed ones.  Samples from the last convergence
+ * check batch (opts.check_every iterations) of each PCG run are dropped:
+ * launches enqueued after the run converged exit at once.  Used by the
+ * benchmark to time the dominant kernel.  Returns LQGRID_EINVAL for a null
+ * ctx, LQGRID_EHIP if resolving pending events fails. */
 LQGRID_API int lqgrid_profile_enable(lqgrid_ctx *ctx, int enable);
 /* kernel: 0 = Delta apply, 1 = Phi solve, 2 = Omega/Xi right-hand side,
  * 3 = vector update.  Returns the timed launches and their summed

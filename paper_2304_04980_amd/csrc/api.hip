@@ -121,7 +121,10 @@ struct lqgrid_ctx {
   double prof_ms[4] = {0, 0, 0, 0};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<int> prof_kind;
+  std::vector<int> prof_batch;  // PCG check batch of the sample (-1: none)
   int prof_used = 0;
+  int prof_batch_cur = -1;
+  int prof_batches = 0;
   ~lqgrid_ctx() {
     for (auto& e : prof_ev) {
       (void)hipEventDestroy(e.first);
@@ -176,9 +179,11 @@ struct ProfScope {
         return;
       c->prof_ev.push_back({a, b});
       c->prof_kind.push_back(0);
+      c->prof_batch.push_back(-1);
     }
     slot = c->prof_used++;
     c->prof_kind[slot] = k;
+    c->prof_batch[slot] = c->prof_batch_cur;
     (void)hipEventRecord(c->prof_ev[slot].first, c->stream);
   }
   ~ProfScope() {
@@ -186,8 +191,16 @@ struct ProfScope {
   }
 };
 
+// Launches of the check batch in which a PCG run stops may exit at once
+// (device-side gate); their samples are dropped.
+void prof_drop_batch(lqgrid_ctx* c, int batch) {
+  for (int e = 0; e < c->prof_used; ++e)
+    if (c->prof_batch[e] == batch) c->prof_kind[e] = -1;
+}
+
 void prof_resolve(lqgrid_ctx* c) {
   for (int e = 0; e < c->prof_used; ++e) {
+    if (c->prof_kind[e] < 0) continue;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->prof_ev[e].first, c->prof_ev[e].second) ==
         hipSuccess) {
@@ -216,11 +229,13 @@ bool opts_valid(const lqgrid_solve_opts& o) {
 
 namespace {
 
-int read_scalars(lqgrid_ctx* c, const Scalars* src, Scalars* h) {
+// Copies the scalars to the host (stream synchronised); pending timing
+// samples are resolved unless the caller still has to drop some.
+int read_scalars(lqgrid_ctx* c, const Scalars* src, Scalars* h, bool resolve = true) {
   HIPCHECK(hipMemcpyAsync(h, src, sizeof(Scalars), hipMemcpyDeviceToHost,
                           c->stream));
   HIPCHECK(hipStreamSynchronize(c->stream));
-  if (c->prof_used) prof_resolve(c);
+  if (resolve && c->prof_used) prof_resolve(c);
   return LQGRID_OK;
 }
 
@@ -303,6 +318,7 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
   vec_zero<T>(d, D.vlen, s);
   Scalars h{};
   for (;;) {
+    c->prof_batch_cur = ++c->prof_batches;
     for (int k = 0; k < check_every; ++k) {
       vec_dir<T>(D, q, d, sc, s);  // d = q + beta d (beta = 0 after init)
       {
@@ -319,9 +335,12 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
       np = vec_dot<T>(D, q, r, c->psum, sc, 1, s);
       scalar_step(kModeMu, c->psum, nullptr, np, sc, 0.0, s);
     }
+    c->prof_batch_cur = -1;
     HIPCHECK(hipGetLastError());
-    const int st = read_scalars(c, sc, &h);
+    const int st = read_scalars(c, sc, &h, false);
     if (st != LQGRID_OK) return st;
+    if (h.done != kRunning) prof_drop_batch(c, c->prof_batches);
+    if (c->prof_used) prof_resolve(c);
     if (h.done != kRunning) break;
   }
   *iters = h.iter;
