@@ -640,7 +640,7 @@ __device__ __forceinline__ void delta_rows(const Dims& D, const OpCoef<T>& C,
         prod(c + 1, nxt);
       } else {
 #pragma unroll
-        for (int a = 0; a < NS; ++a) nxt.v[a] = T(0);
+        for (int a = 0; a < NS; ++a) nxt.self[a] = nxt.g[a] = nxt.w[a] = nxt.v[a] = T(0);
       }
       const TileTime tt = tile_time<T>(D, c);
       T acc[NS], sq[NS], a1[NS], a2[NS];
