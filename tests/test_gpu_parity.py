@@ -57,6 +57,10 @@ CASES = [
     (33, 2, 20, 4, 3, 1.0),     # odd K
     (64, 2, 64, 1, 1, 1.0),     # T+1 = 65, n = 1
     (128, 2, 20, 4, 2, 1.0),    # K of the headline workload
+    # T+1 a multiple of 64: the t-1 / t+1 terms cross every chunk boundary
+    # at full lanes (lane 63 from the previous chunk, lane 0 from the next)
+    (4, 3, 127, 2, 1, 1.0),     # two full time tiles, odd N
+    (9, 4, 191, 3, 2, 1.5),     # three full time tiles, twisted, QT != Q
 ]
 
 
@@ -219,9 +223,11 @@ def test_error_paths(lib, torch):
 F32_CASES = [(4, 4, 20, 2, 1, 1.0), (5, 7, 150, 3, 2, 1.0), (3, 5, 64, 4, 2, 0.7),
              (6, 1, 9, 2, 2, 1.0), (8, 4, 70, 4, 2, 1.0), (9, 6, 40, 3, 2, 2.5),
              (33, 2, 20, 4, 3, 1.0), (128, 2, 20, 4, 2, 1.3),
-             # last 64-step tile of at most 16 steps: packed 4-node tails, node
-             # count not a multiple of 4 (or of 16), n = 3 and n = 2
-             (7, 3, 129, 3, 2, 1.0), (5, 3, 66, 2, 1, 1.0)]
+             # a short last 64-step tile, node count not a multiple of 4,
+             # n = 3 and n = 2
+             (7, 3, 129, 3, 2, 1.0), (5, 3, 66, 2, 1, 1.0),
+             # T+1 a multiple of 64 (full-lane chunk boundaries)
+             (4, 3, 127, 2, 1, 1.0), (9, 4, 191, 3, 2, 1.5)]
 
 
 @pytest.mark.parametrize("case", F32_CASES, ids=[str(c) for c in F32_CASES])
