@@ -41,7 +41,7 @@ __device__ __forceinline__ bool gated_out(const Scalars& sc, int check) {
   return check && sc.done != kRunning;
 }
 
-template <int NS>
+template <int NS, bool ROWS>
 __global__ __launch_bounds__(256) void kb_delta(LQG_BATCH_ARGS,
                                                 double* __restrict__ psum,
                                                 int in, int out, int partial,
@@ -52,8 +52,17 @@ __global__ __launch_bounds__(256) void kb_delta(LQG_BATCH_ARGS,
     const Item w = live[it];
     const BatchProb& P = probs[w.prob];
     if (gated_out(scs[w.prob], check)) continue;
-    delta_tile<double, NS>(P.D, op64(P.C), P.v[in], P.v[out],
-                           partial ? psum + w.slot : nullptr, w.a, w.b);
+    if constexpr (ROWS) {  // the group's first chunk item covers every chunk
+      if (w.b != 0) {
+        if (partial && threadIdx.x == 0) psum[w.slot] = 0.0;
+        continue;
+      }
+      delta_rows<double, NS>(P.D, op64(P.C), P.v[in], P.v[out],
+                             partial ? psum + w.slot : nullptr, w.a);
+    } else {
+      delta_tile<double, NS>(P.D, op64(P.C), P.v[in], P.v[out],
+                             partial ? psum + w.slot : nullptr, w.a, w.b);
+    }
   }
 }
 
@@ -71,7 +80,7 @@ __global__ __launch_bounds__(256) void kb_omega(LQG_BATCH_ARGS, int rho, int th,
   }
 }
 
-template <int NS>
+template <int NS, bool ROWS>
 __global__ __launch_bounds__(256) void kb_xi(LQG_BATCH_ARGS, int r, int dl,
                                              int rho, int check) {
   int lo, hi;
@@ -80,8 +89,14 @@ __global__ __launch_bounds__(256) void kb_xi(LQG_BATCH_ARGS, int r, int dl,
     const Item w = live[it];
     const BatchProb& P = probs[w.prob];
     if (gated_out(scs[w.prob], check)) continue;
-    xi_tile<double, NS>(P.D, op64(P.C), r >= 0 ? P.v[r] : nullptr, P.v[dl],
-                        P.v[rho], w.a, w.b, w.b + 1);
+    if constexpr (ROWS) {  // as in kb_delta
+      if (w.b != 0) continue;
+      xi_rows<double, NS>(P.D, op64(P.C), r >= 0 ? P.v[r] : nullptr, P.v[dl], P.v[rho],
+                          w.a);
+    } else {
+      xi_tile<double, NS>(P.D, op64(P.C), r >= 0 ? P.v[r] : nullptr, P.v[dl],
+                          P.v[rho], w.a, w.b, w.b + 1);
+    }
   }
 }
 
@@ -367,10 +382,15 @@ __global__ void kb_to_abi(BatchDev B) {
 
 void batch_delta(const BatchDev& B, int n, int in, int out, int partial,
                  int check, int grid, hipStream_t s) {
-#define CALL(NS)                                                              \
-  hipLaunchKernelGGL(kb_delta<NS>, dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
-                     B.live[kItemNode], B.nlive + kItemNode, B.psum_node, in, \
-                     out, partial, check)
+#define CALL(NS)                                                                     \
+  if (B.node_rows)                                                                    \
+    hipLaunchKernelGGL((kb_delta<NS, true>), dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
+                       B.live[kItemNode], B.nlive + kItemNode, B.psum_node, in, out,  \
+                       partial, check);                                               \
+  else                                                                                \
+    hipLaunchKernelGGL((kb_delta<NS, false>), dim3(grid), dim3(256), 0, s, B.probs,   \
+                       B.sc, B.live[kItemNode], B.nlive + kItemNode, B.psum_node, in, \
+                       out, partial, check)
   LQG_DISPATCH_N(n, CALL)
 #undef CALL
 }
@@ -384,9 +404,13 @@ void batch_omega(const BatchDev& B, int n, int rho, int th, int tau, int check,
 }
 void batch_xi(const BatchDev& B, int n, int r, int dl, int rho, int check,
               int grid, hipStream_t s) {
-#define CALL(NS)                                                      \
-  hipLaunchKernelGGL(kb_xi<NS>, dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
-                     B.live[kItemNode], B.nlive + kItemNode, r, dl, rho, check)
+#define CALL(NS)                                                                      \
+  if (B.node_rows)                                                                     \
+    hipLaunchKernelGGL((kb_xi<NS, true>), dim3(grid), dim3(256), 0, s, B.probs, B.sc,  \
+                       B.live[kItemNode], B.nlive + kItemNode, r, dl, rho, check);     \
+  else                                                                                 \
+    hipLaunchKernelGGL((kb_xi<NS, false>), dim3(grid), dim3(256), 0, s, B.probs, B.sc, \
+                       B.live[kItemNode], B.nlive + kItemNode, r, dl, rho, check)
   LQG_DISPATCH_N(n, CALL)
 #undef CALL
 }

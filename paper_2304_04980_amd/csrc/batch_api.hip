@@ -336,9 +336,11 @@ int autotune(Batch& b, const Layout& Lay, char* w, const std::vector<Dims>& Ds,
     int st = upload_items(b, Lay, w, *Ls, kItemNode);
     if (st != LQGRID_OK) return st;
     batch_compact(B, 0, b.s);
+    b.B.node_rows = order == 1;
     for (int g : {1024, 2048, 4096, 8192}) {
       const float ms = time_ms(b.s, reps, [&] {
         batch_delta(B, b.n, kBRd, kBYt, 1, 0, g, b.s);
+        batch_xi(B, b.n, -1, kBRd, kBA, 0, g, b.s);
       });
       if (ms < best_node) {
         best_node = ms;
@@ -366,6 +368,7 @@ int autotune(Batch& b, const Layout& Lay, char* w, const std::vector<Dims>& Ds,
     }
   }
   b.tp = best;
+  b.B.node_rows = best.node_order == 1;
   build_node_items(Ds, best.node_order, Ls);
   const int st = upload_items(b, Lay, w, *Ls, kItemNode);
   if (st != LQGRID_OK) return st;
@@ -489,6 +492,7 @@ int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
     B.nunits[k] = Lay.nunits[k];
   }
   B.psum_node = reinterpret_cast<double*>(w + Lay.psum_node);
+  B.node_rows = b.tp.node_order == 1;
   B.psum_flat = reinterpret_cast<double*>(w + Lay.psum_flat);
   B.pmax_flat = reinterpret_cast<double*>(w + Lay.pmax_flat);
   Scalars* sc = reinterpret_cast<Scalars*>(w + Lay.sc);

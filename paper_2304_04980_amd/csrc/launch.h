@@ -180,6 +180,9 @@ struct BatchDev {
   Item* units[kNumUnitKinds];
   int nunits[kNumUnitKinds];
   double *psum_node, *psum_flat, *pmax_flat;
+  // node list with time chunks fastest: the first chunk item of a node group
+  // runs all its chunks in the Delta apply and the Xi~ right-hand side
+  int node_rows = 0;
 };
 
 enum FlatOp {
