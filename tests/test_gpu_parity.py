@@ -283,3 +283,32 @@ def test_fp32_refinement_reaches_fp64_accuracy(lib, torch, tol):
     assert g32["rel2"] <= tol * 1.01 and g64["rel2"] <= tol * 1.01
     rel = np.linalg.norm((d32 - d64).cpu().numpy()) / np.linalg.norm(d64.cpu().numpy())
     assert rel <= 1e-3   # both within kappa * tol of delta*
+
+
+# ------------------------------------------------------------ kernel timing
+def test_profile_samples_leave_out_the_stopping_batch(lib, torch):
+    """The per-kernel timing (lqgrid_profile_*) counts the block-solve
+    launches of the initial preconditioner and of every check batch before
+    the one in which the run stops: with one iteration per batch, a run that
+    stops in iteration k keeps 4 + 4 (k - 1) samples (S = L = 2: four solves
+    per preconditioner); with every iteration in one batch, only the initial
+    four."""
+    from paper_2304_04980_amd import lqgrid
+    p = make_problem(4, 4, 20, 2, 1, seed=21)
+    ctx = lqgrid.Context(p)
+    x0 = torch.as_tensor(p.x0)
+    ctx.profile_enable(True, stride=1)
+    _, _, _, info = ctx.solve(x0, lqgrid.default_opts(tol=1e-8, check_every=1))
+    n1, ms1 = ctx.profile_read(1)
+    say(f"  check_every 1: {info['iterations']} it, {info['refinements']} passes, "
+        f"{n1} timed solves, {ms1:.3f} ms")
+    assert info["status"] == lqgrid.OK and info["refinements"] == 1
+    assert n1 == 4 * info["iterations"] and ms1 > 0.0
+    ctx.profile_enable(True, stride=1)
+    _, _, _, info = ctx.solve(x0, lqgrid.default_opts(tol=1e-8, check_every=64))
+    n2, _ = ctx.profile_read(1)
+    say(f"  check_every 64: {info['iterations']} it, {n2} timed solves")
+    assert info["status"] == lqgrid.OK and info["refinements"] == 1
+    assert info["iterations"] < 64 and n2 == 4
+    ctx.profile_enable(False)
+    ctx.close()
