@@ -151,7 +151,12 @@ LQGRID_API int lqgrid_pcg_solve(lqgrid_ctx *ctx, const double *x0,
  * describe problem p (device pointers, layouts as above); all share n, m and
  * opts.  workspace sized by lqgrid_batch_workspace_bytes.  infos[p] receives
  * problem p's result.  Synchronises the stream before returning.
- * Returns LQGRID_OK only if every problem converged. */
+ * Returns LQGRID_OK only if every problem converged.  The first call for a
+ * set of problem sizes times the persistent grids and the order of the node
+ * work items and caches the choice; the environment variable
+ * LQGRID_BATCH_NODE_ORDER = 0 or 1 fixes that order (0: node groups
+ * fastest, per-chunk stencil tiles; 1: time chunks fastest, the Delta apply
+ * and Xi~ right-hand side run each node group over all its chunks). */
 LQGRID_API size_t lqgrid_batch_workspace_bytes(int P, const lqgrid_problem_desc *descs,
                                     const lqgrid_solve_opts *opts);
 LQGRID_API int lqgrid_batch_solve(int P, const lqgrid_problem_desc *descs,

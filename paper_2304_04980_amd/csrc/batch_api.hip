@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -322,6 +323,16 @@ float time_ms(hipStream_t s, int reps, F f) {
   return ms / reps;
 }
 
+// LQGRID_BATCH_NODE_ORDER = 0 or 1 fixes the node-tile order (tests run both
+// the per-chunk and the all-chunks stencil paths); -1 when unset.
+int forced_node_order() {
+  const char* e = std::getenv("LQGRID_BATCH_NODE_ORDER");
+  if (!e) return -1;
+  if (e[0] == '0' && e[1] == 0) return 0;
+  if (e[0] == '1' && e[1] == 0) return 1;
+  return -1;
+}
+
 // Autotune the persistent grids and the node-tile order on pure operator
 // applications (inputs: r_delta; outputs: scratch roles).  Leaves the node
 // list in the chosen order and every item live.
@@ -331,7 +342,9 @@ int autotune(Batch& b, const Layout& Lay, char* w, const std::vector<Dims>& Ds,
   const int reps = 3;
   Tuned best = b.tp;
   float best_node = 1e30f;
+  const int forced = forced_node_order();
   for (int order = 0; order < 2; ++order) {
+    if (forced >= 0 && order != forced) continue;
     build_node_items(Ds, order, Ls);
     int st = upload_items(b, Lay, w, *Ls, kItemNode);
     if (st != LQGRID_OK) return st;
@@ -463,7 +476,7 @@ int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
   b.S = o.outer_S;
   b.L = o.inner_L;
   b.s = sg.own;
-  const uint64_t key = dims_key(Ds);
+  const uint64_t key = dims_key(Ds) ^ ((uint64_t)(forced_node_order() + 2) << 60);
   bool tuned = false;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -77,6 +77,20 @@ def test_uneven_batch_matches_oracle(lib, torch, tol):
         check_against_oracle(p, d, info, tol)
 
 
+@pytest.mark.parametrize("order", ["0", "1"])
+def test_uneven_batch_in_each_node_order(lib, torch, order, monkeypatch):
+    """Both node-item orders (per-chunk stencil tiles; all-chunks Delta and
+    Xi~ with the other chunk items idle) against the oracle."""
+    from paper_2304_04980_amd import lqgrid
+    monkeypatch.setenv("LQGRID_BATCH_NODE_ORDER", order)
+    probs = uneven_problems()
+    say("uneven batch, node order", order)
+    outs, infos, st = lqgrid.batch_solve(probs, opts=lqgrid.default_opts(tol=1e-9))
+    assert st == lqgrid.OK, [i["status"] for i in infos]
+    for p, d, info in zip(probs, outs, infos):
+        check_against_oracle(p, d, info, 1e-9)
+
+
 def test_batch_equals_single_problem_path(lib, torch):
     """Each problem of a batch takes the same iterations as the
     single-problem solve and lands within kappa * tol of it."""
