@@ -175,7 +175,9 @@ struct ProfScope {
     if (c->prof_seen[k]++ % c->prof_stride != 0) return;
     if (c->prof_used >= (int)c->prof_ev.size()) {
       hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+      // timing only: no system-scope fence (no L2 writeback per sample)
+      if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess ||
+          hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess)
         return;
       c->prof_ev.push_back({a, b});
       c->prof_kind.push_back(0);
