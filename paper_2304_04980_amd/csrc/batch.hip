@@ -314,13 +314,14 @@ __global__ void kb_node_prep(BatchDev B) {
     if (q < w.b) node_prep(P.D, P.in, P.C, P.sc, q);
   }
 }
+template <int NS>
 __global__ void kb_stencil(BatchDev B) {
   const Item* u = B.units[kUnitStencil];
   for (int it = blockIdx.x; it < B.nunits[kUnitStencil]; it += gridDim.x) {
     const Item w = u[it];
     const BatchProb& P = B.probs[w.prob];
     const int q = w.a + threadIdx.x;
-    if (q < w.b) stencil(P.D, P.in, P.C, q);
+    if (q < w.b) stencil<NS>(P.D, P.in, P.C, q);
   }
 }
 // Factor units of the problems factored in the twisted order (128 threads,
@@ -442,9 +443,11 @@ void batch_compact(const BatchDev& B, int running_only, hipStream_t s) {
 void batch_set_active(const BatchDev& B, hipStream_t s) {
   hipLaunchKernelGGL(kb_set_active, dim3((B.P + 255) / 256), dim3(256), 0, s, B);
 }
-void batch_setup(const BatchDev& B, hipStream_t s) {
+void batch_setup(const BatchDev& B, int n, hipStream_t s) {
   hipLaunchKernelGGL(kb_node_prep, dim3(1024), dim3(128), 0, s, B);
-  hipLaunchKernelGGL(kb_stencil, dim3(2048), dim3(128), 0, s, B);
+#define CALL(NS) hipLaunchKernelGGL(kb_stencil<NS>, dim3(2048), dim3(128), 0, s, B)
+  LQG_DISPATCH_N(n, CALL)
+#undef CALL
 }
 void batch_factor(const BatchDev& B, hipStream_t s) {
   const dim3 g(std::max(1, std::min(B.nunits[kUnitFactor], 16384)));

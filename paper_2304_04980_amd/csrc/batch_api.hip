@@ -550,7 +550,7 @@ int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
                               hipMemcpyHostToDevice, b.s));
 
   // a1-a3: ingest, assembly, factorisation of every problem
-  batch_setup(B, b.s);
+  batch_setup(B, b.n, b.s);
   batch_factor(B, b.s);
   HIPCHECK(hipGetLastError());
   std::vector<Scalars> hs;

@@ -131,17 +131,20 @@ __device__ inline void node_prep(const Dims& D, const ProblemIn& P, const Coef& 
 }
 
 // Work unit gid = 18 p + k of node p: k < 13 -> G13[p][k]; 13 <= k < 18 ->
-// the 5-point blocks Cdn, AT5, Cup for k5 = k - 13.
+// the 5-point blocks Cdn, AT5, Cup for k5 = k - 13.  NS = D.n at compile
+// time, so the n x n work blocks stay in registers.
+template <int NS>
 __device__ inline void stencil(const Dims& D, const ProblemIn& P, const Coef& C,
                                long long gid) {
   if (gid >= (long long)D.nodes * 18) return;
   const int p = (int)(gid / 18), k = (int)(gid % 18);
-  const int n = D.n, K = D.K, N = D.N;
-  const size_t nn = (size_t)n * n;
+  constexpr int n = NS;
+  constexpr size_t nn = (size_t)n * n;
+  const int K = D.K, N = D.N;
   const int j = p / K, i = p - j * K;
-  double out[kMaxN * kMaxN];
-  double out2[kMaxN * kMaxN];
-  double out3[kMaxN * kMaxN];
+  double out[nn];
+  double out2[nn];
+  double out3[nn];
   for (size_t e = 0; e < nn; ++e) out[e] = out2[e] = out3[e] = 0.0;
   const bool real = p < D.real_nodes;
   if (k < 13) {
@@ -154,7 +157,7 @@ __device__ inline void stencil(const Dims& D, const ProblemIn& P, const Coef& C,
         const double* Aqs = ahat_block(P, iq, jq, is, js);
         if (!Aps || !Aqs) continue;
         const double* Qis = C.Qi + ((size_t)js * K + is) * nn;
-        double tmp[kMaxN * kMaxN];
+        double tmp[nn];
         for (int a = 0; a < n; ++a)  // tmp = A_ps Q_s^-1
           for (int b = 0; b < n; ++b) {
             double s = 0.0;

@@ -213,7 +213,7 @@ void batch_scalar(const BatchDev& B, int mode, int kind, int outer, double tol,
                   hipStream_t s);
 void batch_compact(const BatchDev& B, int running_only, hipStream_t s);
 void batch_set_active(const BatchDev& B, hipStream_t s);
-void batch_setup(const BatchDev& B, hipStream_t s);
+void batch_setup(const BatchDev& B, int n, hipStream_t s);
 void batch_factor(const BatchDev& B, hipStream_t s);
 void batch_rhs_init(const BatchDev& B, hipStream_t s);
 void batch_to_abi(const BatchDev& B, hipStream_t s);

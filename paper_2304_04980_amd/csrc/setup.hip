@@ -10,8 +10,9 @@ using namespace dev;
 __global__ void k_node_prep(Dims D, ProblemIn P, Coef C, Scalars* sc) {
   node_prep(D, P, C, sc, blockIdx.x * blockDim.x + threadIdx.x);
 }
+template <int NS>
 __global__ void k_stencil(Dims D, ProblemIn P, Coef C) {
-  stencil(D, P, C, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  stencil<NS>(D, P, C, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 // one 64-thread workgroup per (v, cls)
 __global__ __launch_bounds__(64) void k_factor(Dims D, Coef C, Scalars* sc) {
@@ -32,8 +33,14 @@ void launch_setup(const Dims& D, const ProblemIn& P, const Coef& C,
   hipLaunchKernelGGL(k_node_prep, dim3((D.nodes + 127) / 128), dim3(128), 0, s,
                      D, P, C, sc);
   const long long work = (long long)D.nodes * 18;
-  hipLaunchKernelGGL(k_stencil, dim3((unsigned)((work + 127) / 128)), dim3(128),
-                     0, s, D, P, C);
+  const dim3 g((unsigned)((work + 127) / 128));
+  switch (D.n) {
+    case 1: hipLaunchKernelGGL(k_stencil<1>, g, dim3(128), 0, s, D, P, C); break;
+    case 2: hipLaunchKernelGGL(k_stencil<2>, g, dim3(128), 0, s, D, P, C); break;
+    case 3: hipLaunchKernelGGL(k_stencil<3>, g, dim3(128), 0, s, D, P, C); break;
+    case 4: hipLaunchKernelGGL(k_stencil<4>, g, dim3(128), 0, s, D, P, C); break;
+    default: break;
+  }
 }
 
 void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s) {
