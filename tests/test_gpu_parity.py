@@ -227,7 +227,9 @@ F32_CASES = [(4, 4, 20, 2, 1, 1.0), (5, 7, 150, 3, 2, 1.0), (3, 5, 64, 4, 2, 0.7
              # n = 3 and n = 2
              (7, 3, 129, 3, 2, 1.0), (5, 3, 66, 2, 1, 1.0),
              # T+1 a multiple of 64 (full-lane chunk boundaries)
-             (4, 3, 127, 2, 1, 1.0), (9, 4, 191, 3, 2, 1.5)]
+             (4, 3, 127, 2, 1, 1.0), (9, 4, 191, 3, 2, 1.5),
+             # n = 1: one coefficient register per 16 blocks' worth
+             (4, 3, 70, 1, 1, 1.0), (16, 2, 129, 1, 1, 0.7)]
 
 
 @pytest.mark.parametrize("case", F32_CASES, ids=[str(c) for c in F32_CASES])
