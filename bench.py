@@ -5,11 +5,15 @@ One step = one pass of the whole path over one synthetic problem whose arrays
 are already resident in HBM: lqgrid_setup (ingest + Schur-block assembly),
 lqgrid_factor (banded block Cholesky of every Phi_bar), lqgrid_pcg_solve
 (Algorithm 1 + Algorithm 2 preconditioner to the tolerance, true FP64
-residual check) and the output transpose.  Both forms run in one invocation
-on the same inputs: plain FP64 PCG, then the chosen form (default: FP32
-stencil apply and sweeps inside FP64 iterative refinement).  value = steps /
-wall time of the chosen form's timed steps (solves/s); the plain figures are
-reported beside it.
+residual check, output transpose and the recovery of x~ and u~).  Both forms
+run in one invocation on the same inputs: plain FP64 PCG, then the chosen form
+(default: FP32 stencil apply and sweeps inside FP64 iterative refinement).
+value = steps / wall time of the chosen form's timed steps (solves/s); the
+plain figures are reported beside it.  After timing, the FP64 oracle evaluates
+the KKT residual of each form's last solution (delta~, x~, u~).  The default
+headline run also times the batched form (256 uneven problems) and the learned
+warm start (64 x 64 x 100) on their own workloads and adds their summaries to
+the same line.
 
 Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
@@ -103,39 +107,75 @@ def traffic_from_profiles(kernel, w):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(p, tol, gpu_iters):
-    """The FP64 oracle (numpy/scipy, one thread) timed on a bounded sample of
-    the same workload: slab-operator setup with the Phi_bar factorisation,
-    the initial residual and preconditioner, and one PCG iteration; the
-    per-solve time is extrapolated with the GPU's iteration count."""
+    """The FP64 oracle (numpy/scipy slab operators, Algorithm 1 with the
+    Algorithm 2 preconditioner) timed on complete solves of a bounded sample:
+    the 32 x 32 x 100 problem (n = 4, m = 2, seed 0) to the same tolerance,
+    once with every core of this process's affinity mask available to the
+    numerical libraries and once with one thread.  Generation is excluded;
+    operator setup and factorisation are included.  The per-solve time of
+    the benchmarked workload is estimated from the measured one by the
+    per-iteration cost being linear in the number of unknowns (Table I):
+    t_solve * (U / U_sample) * (iterations / sample iterations)."""
     from threadpoolctl import threadpool_limits
+    from lqgrid_synth import config_problem
     from oracle import slab, nbjm, pcg
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        ops = slab.SlabOperators(p)
-        for t in sorted({0, 1, p.T}):
-            ops._factor(t)
-        t1 = time.perf_counter()
-        pre = nbjm.slab_preconditioner(ops, 2, 2)
-        r = ops.r_delta()
-        d = pre(r)
-        float((d * r).sum())
-        t2 = time.perf_counter()
-        y = ops.delta(d)
-        th = float((r * d).sum()) / float((y * d).sum())
-        r = r - th * y
-        q = pre(r)
-        float((q * r).sum())
-        t3 = time.perf_counter()
-    setup, init, it = t1 - t0, t2 - t1, t3 - t2
-    per_solve = setup + init + gpu_iters * it
+    sample, _ = config_problem("plain", 0)
+    cores = len(os.sched_getaffinity(0))
+
+    def timed(threads):
+        with threadpool_limits(threads):
+            t0 = time.perf_counter()
+            ops = slab.SlabOperators(sample)
+            pre = nbjm.slab_preconditioner(ops, 2, 2)
+            _, it, _ = pcg.pcg(ops.delta, pre, ops.r_delta(), tol=tol)
+            return time.perf_counter() - t0, it
+
+    t_all, it_all = timed(cores)
+    t_one, it_one = timed(1)
+    scale = (p.unknowns / sample.unknowns) * (gpu_iters / it_all)
+    est = t_all * scale
     return {
-        "value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle slab setup+factor ({setup:.1f}s), initial preconditioner "
-                   f"({init:.1f}s) and 1 PCG iteration ({it:.2f}s) at K={p.K} N={p.N} "
-                   f"T={p.T}; per-solve time = setup + init + {gpu_iters} iterations"),
-        "seconds_per_solve": per_solve,
+        "value": 1.0 / est, "unit": "solves/s", "cores": cores, "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "sample": (f"complete oracle solves (setup + factor + PCG to tol {tol}) at "
+                   f"K={sample.K} N={sample.N} T={sample.T} n={sample.n} m={sample.m}: "
+                   f"{t_all:.2f} s with {cores} threads, {t_one:.2f} s with 1 thread, "
+                   f"{it_all} iterations; value = estimated solves/s at K={p.K} N={p.N} "
+                   f"T={p.T}: measured time x {p.unknowns}/{sample.unknowns} unknowns x "
+                   f"{gpu_iters}/{it_all} iterations (cost per iteration linear in the "
+                   f"unknowns); the sparse products run on one thread whatever the limit"),
+        "measured": {"K": sample.K, "N": sample.N, "T": sample.T, "tol": tol,
+                     "iterations": it_all,
+                     "seconds_all_cores": t_all, "solves_per_s_all_cores": 1.0 / t_all,
+                     "seconds_1_thread": t_one, "solves_per_s_1_thread": 1.0 / t_one,
+                     "iterations_1_thread": it_one},
+        "estimated_seconds_per_solve": est,
     }
+
+
+def iteration_bytes(p, w, qt_distinct=False):
+    """Algorithmic HBM bytes of one PCG iteration (S = L = 2) over the whole
+    path: 21 full vector passes (Delta apply 2, update + first solve 7,
+    second and third solves 3 each, fourth solve with the dot product 4 --
+    the count of a fully fused iteration) plus the factor rows of four block
+    solves and the operator blocks of the Delta apply, the two Omega~ and
+    the Xi~ right-hand sides."""
+    kb = kernel_bytes(p, w, qt_distinct)
+    U = p.K * p.N * p.n * (p.T + 1)
+    nodes = p.K * p.N
+    factors = kb["phi_solve"] - 2 * U * w - nodes * p.n * p.n * w
+    return 21 * U * w + 4 * factors + nodes * (25 + 2 * 10 + 10) * p.n * p.n * w
 
 
 def make_inputs(p, torch, dev):
@@ -157,15 +197,17 @@ def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
     else:
         opts = lqgrid.default_opts(tol=tol)
     w = 4 if precision == "fp32r" else 8
-    delta = torch.empty((p.T + 1, p.N, p.K, p.n), dtype=torch.float64,
-                        device=x0.device)
+    f64 = dict(dtype=torch.float64, device=x0.device)
+    delta = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
+    xs = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
+    us = torch.empty((p.T, p.N, p.K, p.m), **f64)
 
     def step(profile):
         ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=False)
         if profile:
             ctx.profile_enable(True, stride=PROFILE_STRIDE)
         ctx.factor()
-        _, _, _, info = ctx.solve(x0, opts, out=delta)
+        _, _, _, info = ctx.solve(x0, opts, out=delta, out_x=xs, out_u=us)
         prof = {k: ctx.profile_read(k) for k in range(4)} if profile else None
         ctx.close()
         return info, prof
@@ -210,6 +252,7 @@ def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
         "pcg_iters_per_s": iters * steps / elapsed,
         "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
         "kernels": kern, "hot": per_kernel, "dominant": dom,
+        "solution": (delta, xs, us),
     }
 
 
@@ -270,6 +313,8 @@ def bench_batched(args, torch, lqgrid):
                "converged": all(i["status"] == lqgrid.OK for i in sinfos)}
         log(f"sequential single-problem path: {st:.3f} s for {len(probs)} solves")
     value = len(probs) * args.steps / elapsed
+    path_bytes = sum(i["iterations"] * iteration_bytes(p, 8) for p, i in zip(probs, infos))
+    achieved = path_bytes / (elapsed / args.steps) / 1e9
     result = {
         "metric": "batched solves/s to 1e-8 rel. KKT residual, 256 problems "
                   "K,N~U{8..64} T~U{50..200}",
@@ -286,9 +331,16 @@ def bench_batched(args, torch, lqgrid):
         "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
         "sequential_fp64": seq,
         "speedup_vs_sequential": None if seq is None else value / seq["value"],
-        "roofline": None, "cpu_baseline": None,
+        "roofline": {"bound": "hbm", "kernel": "whole path (every kernel of the batched "
+                     "solve)", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "note": "algorithmic bytes of every problem's PCG iterations "
+                             "(21 vector passes + factor rows + operator blocks per "
+                             "iteration) over the wall time of one batched solve"},
+        "cpu_baseline": None,
     }
-    print(json.dumps(result), flush=True)
+    return result
 
 
 def bench_learned(args, torch, lqgrid):
@@ -319,9 +371,19 @@ def bench_learned(args, torch, lqgrid):
         "zero_start_solves_per_s": len(rows) / zs,
         "speedup_vs_zero_start": zs / wsec,
         "predictions_kept": sum(r["warm_used"] for r in rows),
+        "predictions": len(rows),
         "roofline": None, "cpu_baseline": None,
     }
-    print(json.dumps(result), flush=True)
+    from lqgrid_synth import learned_problem
+    p = learned_problem(seeds[0])
+    achieved = wi * iteration_bytes(p, 8) / (wsec / len(rows)) / 1e9
+    result["roofline"] = {
+        "bound": "hbm", "kernel": "whole path (inference + solve)",
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "note": "algorithmic bytes of the PCG iterations over the wall time of a "
+                "warm-started solve (features and network inference included)"}
+    return result
 
 
 def main():
@@ -339,6 +401,11 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="headline only: skip the batched and learned summaries")
+    ap.add_argument("--form-steps", type=int, default=2,
+                    help="timed steps of the batched and learned summaries")
     ap.add_argument("--copy-ref-mib", type=int, default=512,
                     help="size of the plain copy used to scale PMC counters")
     args = ap.parse_args()
@@ -352,9 +419,11 @@ def main():
     from paper_2304_04980_amd import lqgrid
 
     if args.workload == "batched":
-        return bench_batched(args, torch, lqgrid)
+        print(json.dumps(bench_batched(args, torch, lqgrid)), flush=True)
+        return
     if args.workload == "learned":
-        return bench_learned(args, torch, lqgrid)
+        print(json.dumps(bench_learned(args, torch, lqgrid)), flush=True)
+        return
     p, tol = config_problem(args.workload, args.seed)
     dev = "cuda"
     arrays, x0 = make_inputs(p, torch, dev)
@@ -427,10 +496,47 @@ def main():
         "speedup_vs_plain": None if plain is None else chosen["value"] / plain["value"],
         "cpu_baseline": None,
     }
+    if not args.no_oracle_check:
+        # the oracle's FP64 KKT residual of the last timed step's delta~, x~, u~
+        # (all three blocks of the KKT system), for each form
+        from oracle import slab, residual
+        log("checking the solutions with the FP64 oracle ...")
+        ops = slab.SlabOperators(p)
+        for name, rec in (("chosen", chosen), ("plain", plain)):
+            if rec is None:
+                continue
+            d, xs, us = (t.cpu().numpy() for t in rec["solution"])
+            g = residual.kkt_residual(ops, d.reshape(p.T + 1, -1),
+                                      xs.reshape(p.T + 1, -1), us.reshape(p.T, -1))
+            target = result if name == "chosen" else result["plain_fp64"]
+            target["oracle_rel_kkt_residual"] = g["rel2"]
+            target["converged"] = bool(target["converged"] and g["rel2"] <= tol)
+            log(f"  {name}: oracle relative KKT residual {g['rel2']:.3e}")
+        del ops
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(p, tol, int(round(
             plain["pcg_iterations"] if plain else chosen["pcg_iterations"])))
+    if args.workload == "headline" and not args.no_forms:
+        # the other two forms of the method on their own workloads, as
+        # summaries in the same line
+        del chosen, plain, ws, arrays
+        torch.cuda.empty_cache()
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = args.form_steps, 1
+        for key, fn in (("batched", bench_batched), ("learned", bench_learned)):
+            try:
+                r = fn(sub, torch, lqgrid)
+                result[key] = {k: r.get(k) for k in (
+                    "metric", "value", "unit", "ms_per_step", "converged", "config",
+                    "roofline", "speedup_vs_sequential", "sequential_fp64",
+                    "speedup_vs_zero_start", "zero_start_solves_per_s",
+                    "warm_pcg_iterations", "zero_pcg_iterations", "predictions_kept",
+                    "predictions", "pcg_iterations_total", "rel_kkt_residual")
+                    if k in r}
+            except Exception as e:  # reported, never hides the headline line
+                result[key] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
     print(json.dumps(result), flush=True)
 
 

@@ -16,9 +16,10 @@
  *           by the caller.  The library never allocates device memory: all
  *           scratch lives in the caller's workspace (size from
  *           lqgrid_workspace_bytes).  It allocates only the small host-side
- *           context, freed by lqgrid_destroy.
- * Streams.  All device work is enqueued on the caller's HIP stream
- *           (hipStream_t passed as void*; NULL = the null stream).
+ *           context, freed by lqgrid_destroy, and HIP events for timing.
+ * Streams.  Device work is enqueued on the caller's HIP stream (hipStream_t
+ *           passed as void*; NULL = the null stream); lqgrid_batch_solve
+ *           alone also uses an internal stream of its own (see there).
  * Layout.   Row-major C arrays, node (i, j) with i = 0..K-1 the vertical and
  *           j = 0..N-1 the horizontal grid index, column j outermost exactly as
  *           in the paper's stacking x_hat_t = col_j col_i x_{i,j,t}
@@ -148,9 +149,14 @@ LQGRID_API int lqgrid_pcg_solve(lqgrid_ctx *ctx, const double *x0,
                      double *delta, double *x, double *u, lqgrid_info *info);
 
 /* Several independent problems solved together.  descs[p], x0s[p], deltas[p]
- * describe problem p (device pointers, layouts as above); all share n, m and
- * opts.  workspace sized by lqgrid_batch_workspace_bytes.  infos[p] receives
- * problem p's result.  Synchronises the stream before returning.
+ * describe problem p (device pointers, layouts as above); all share n and
+ * opts, while K, N, T and m may differ from problem to problem.  workspace
+ * sized by lqgrid_batch_workspace_bytes.  infos[p] receives problem p's
+ * result.  Synchronises the stream before returning.  Device memory: none
+ * is allocated (everything lives in the workspace), but each call creates one
+ * internal HIP stream and a few events (the iteration block is captured on
+ * that stream into a HIP graph, instantiated and replayed, ordered after the
+ * caller's stream by an event) and destroys them before returning.
  * Returns LQGRID_OK only if every problem converged.  The first call for a
  * set of problem sizes times the persistent grids and the order of the node
  * work items and caches the choice; the environment variable

@@ -32,6 +32,15 @@ Recipe (all draws from numpy ``default_rng(seed)``, PCG64, in this order):
   3. B = standard_normal((N,K,n,m));
   4. x0 = standard_normal((N,K,n)).
 Q = QT = I_n, R = r_scale * I_m, zero spatial boundary states.
+
+With ``weights="spd"`` (off by default, so the recipe above is unchanged) the
+weights are instead drawn per node after x0, from the same generator:
+  5. Q  = q_scale  * (M M' / n + I_n / 2),  M = standard_normal((N,K,n,n));
+  6. QT = qt_scale * (M M' / n + I_n / 2),  a fresh M of the same shape;
+  7. R  = r_scale  * (M M' / m + I_m / 2),  M = standard_normal((N,K,m,m)).
+Each is symmetric positive definite (smallest eigenvalue >= scale / 2) and
+differs from node to node, so a mix-up of the weights of two nodes (or of Q
+and QT) changes the solution.
 """
 from __future__ import annotations
 
@@ -71,11 +80,14 @@ def _spectral_radius(M: np.ndarray) -> float:
 
 def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
                  cs: float = 0.1, seed: int = 0, r_scale: float = 0.1,
-                 q_scale: float = 1.0, qt_scale: float | None = None) -> Problem:
+                 q_scale: float = 1.0, qt_scale: float | None = None,
+                 weights: str = "identity") -> Problem:
     """Draw one problem by the recipe in the module docstring.
 
-    ``q_scale``/``qt_scale`` scale the identity weights; they exist so tests can
-    exercise a terminal weight different from Q (default QT = Q)."""
+    ``q_scale``/``qt_scale`` scale the weights; they exist so tests can
+    exercise a terminal weight different from Q (default QT = Q).
+    ``weights``: "identity" (the recipe's scaled identities) or "spd"
+    (random per-node SPD weights, drawn after x0)."""
     if min(K, N, T, n, m) < 1:
         raise ValueError("all dimensions must be >= 1")
     rng = np.random.default_rng(seed)
@@ -94,13 +106,27 @@ def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
     A_nbr = cs * rng.standard_normal((N, K, 4, n, n))
     B = rng.standard_normal((N, K, n, m))
     x0 = rng.standard_normal((N, K, n))
-    eye_n = np.eye(n)
-    Q = np.broadcast_to(q_scale * eye_n, (N, K, n, n)).copy()
     qt = q_scale if qt_scale is None else qt_scale
-    QT = np.broadcast_to(qt * eye_n, (N, K, n, n)).copy()
-    R = np.broadcast_to(r_scale * np.eye(m), (N, K, m, m)).copy()
+    if weights == "identity":
+        eye_n = np.eye(n)
+        Q = np.broadcast_to(q_scale * eye_n, (N, K, n, n)).copy()
+        QT = np.broadcast_to(qt * eye_n, (N, K, n, n)).copy()
+        R = np.broadcast_to(r_scale * np.eye(m), (N, K, m, m)).copy()
+    elif weights == "spd":
+        Q = q_scale * _random_spd(rng, N, K, n)
+        QT = qt * _random_spd(rng, N, K, n)
+        R = r_scale * _random_spd(rng, N, K, m)
+    else:
+        raise ValueError(f"unknown weights {weights!r}")
     return Problem(K, N, T, n, m, A, A_nbr, B, Q, R, QT, x0, seed,
-                   dict(rho=rho, cs=cs, r_scale=r_scale))
+                   dict(rho=rho, cs=cs, r_scale=r_scale, weights=weights))
+
+
+def _random_spd(rng, N: int, K: int, k: int) -> np.ndarray:
+    """M M' / k + I / 2 per node, M standard normal (N, K, k, k)."""
+    M = rng.standard_normal((N, K, k, k))
+    S = np.einsum("jiab,jicb->jiac", M, M) / k + 0.5 * np.eye(k)
+    return 0.5 * (S + np.swapaxes(S, -1, -2))
 
 
 def redraw_x0(p: Problem, seed: int) -> np.ndarray:

@@ -118,7 +118,7 @@ def check_func(name, body):
 
 
 def main(argv):
-    srcs = argv or ["ops.hip", "batch.hip"]
+    srcs = argv or ["ops.hip", "batch.hip", "warm.hip"]
     bad, n = [], 0
     with tempfile.TemporaryDirectory() as tmp:
         for src in srcs:

@@ -528,9 +528,17 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
   const Dims& D = c->D;
   hipStream_t s = c->stream;
   clear_stale_error();
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0));
-  HIPCHECK(hipEventCreate(&e1));
+  // the solve's timing events, destroyed on every return path
+  struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIPCHECK(hipEventCreate(&ev.a));
+  HIPCHECK(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   HIPCHECK(hipEventRecord(e0, s));
 
   // r_delta, ||r_delta||, tol^2 ||r_delta||^2 (outer scalars)
@@ -589,8 +597,6 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
   if (c->prof_used) prof_resolve(c);
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   HIPCHECK(hipGetLastError());
   if (info) {
     info->status = status;

@@ -84,8 +84,8 @@ struct OpCoef {
 // factorisation uses K + 1 of them, the twisted one K + 2.
 __host__ __device__ inline int fw_rows(int K) { return K + 2; }
 
-// The single-problem path factors and solves Phi_bar in the twisted order
-// from this many block rows on (the batched form keeps the one-chain order).
+// Phi_bar is factored and solved in the twisted order from this many block
+// rows on, in the single-problem and in the batched form alike.
 constexpr int kTwistMin = 8;
 __host__ __device__ inline bool twisted(const Dims& D) { return D.K >= kTwistMin; }
 

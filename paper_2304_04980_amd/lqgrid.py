@@ -232,9 +232,12 @@ class Context:
             raise LqgridError(st, "lqgrid_factor")
 
     def solve(self, x0, opts: SolveOpts | None = None, delta_init=None,
-              want_primal=False, out=None, raise_on_error=True):
+              want_primal=False, out=None, raise_on_error=True, out_x=None,
+              out_u=None):
         """x0: [N][K][n] float64 CUDA tensor (or array).  Returns
-        (delta [T+1][N][K][n], x or None, u or None, info dict)."""
+        (delta [T+1][N][K][n], x or None, u or None, info dict).  out, out_x,
+        out_u: optional preallocated outputs (out_x / out_u imply
+        want_primal)."""
         import torch
         K, N, T, n, m = self.dims
         dev = self.arrays["A"].device
@@ -242,9 +245,10 @@ class Context:
         if opts is None:
             opts = default_opts()
         delta = out if out is not None else torch.empty((T + 1, N, K, n), dtype=torch.float64, device=dev)
-        x = u = None
-        if want_primal:
+        x, u = out_x, out_u
+        if want_primal and x is None:
             x = torch.empty((T + 1, N, K, n), dtype=torch.float64, device=dev)
+        if want_primal and u is None:
             u = torch.empty((T, N, K, m), dtype=torch.float64, device=dev)
         di = None
         if delta_init is not None:

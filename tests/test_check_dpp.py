@@ -45,5 +45,9 @@ def test_branch_into_window_is_followed():
 
 @pytest.mark.skipif(shutil.which(cd.HIPCC) is None and not __import__("os").path.exists(cd.HIPCC),
                     reason="hipcc not available")
-def test_solve_kernels_have_no_dpp_hazards():
-    assert cd.main(["ops.hip"]) == 0
+@pytest.mark.parametrize("src", ["ops.hip", "batch.hip", "warm.hip"])
+def test_kernels_have_no_dpp_hazards(src):
+    """Every source whose kernels are built from the DPP-folded FMAs (the
+    single-problem and the batched stencil / block-solve kernels; the network
+    kernels, which use none, are scanned too)."""
+    assert cd.main([src]) == 0

@@ -45,8 +45,8 @@ def torch():
     return t
 
 
-def uneven_problems():
-    return [make_problem(K, N, T, n, m, seed=11 * k + 5, qt_scale=qt)
+def uneven_problems(weights="identity"):
+    return [make_problem(K, N, T, n, m, seed=11 * k + 5, qt_scale=qt, weights=weights)
             for k, (K, N, T, n, m, qt) in enumerate(UNEVEN)]
 
 
@@ -75,6 +75,17 @@ def test_uneven_batch_matches_oracle(lib, torch, tol):
     assert st == lqgrid.OK, [i["status"] for i in infos]
     for p, d, info in zip(probs, outs, infos):
         check_against_oracle(p, d, info, tol)
+
+
+def test_uneven_batch_with_spd_weights(lib, torch):
+    """The uneven batch with per-node random SPD Q, Q_T and R."""
+    from paper_2304_04980_amd import lqgrid
+    probs = uneven_problems("spd")
+    say("uneven batch, spd weights")
+    outs, infos, st = lqgrid.batch_solve(probs, opts=lqgrid.default_opts(tol=1e-9))
+    assert st == lqgrid.OK, [i["status"] for i in infos]
+    for p, d, info in zip(probs, outs, infos):
+        check_against_oracle(p, d, info, 1e-9)
 
 
 @pytest.mark.parametrize("order", ["0", "1"])

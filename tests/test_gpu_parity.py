@@ -71,12 +71,26 @@ def torch():
     return t
 
 
-@pytest.mark.parametrize("case", CASES, ids=[str(c) for c in CASES])
+# per-node random SPD Q, Q_T and R (a weight of the wrong node, or Q in place
+# of Q_T, changes every operator): one-chain and twisted factorisations,
+# odd N, ragged time tiles
+SPD_CASES = [
+    (4, 4, 20, 2, 1, 1.0, "spd"),
+    (5, 7, 150, 3, 2, 1.3, "spd"),
+    (7, 6, 64, 4, 2, 0.8, "spd"),
+    (9, 5, 40, 4, 3, 1.0, "spd"),
+    (16, 4, 70, 4, 2, 2.0, "spd"),
+    (33, 3, 20, 2, 2, 1.0, "spd"),
+]
+
+
+@pytest.mark.parametrize("case", CASES + SPD_CASES, ids=[str(c) for c in CASES + SPD_CASES])
 def test_operators_match_oracle(lib, torch, case):
     from paper_2304_04980_amd import lqgrid
-    K, N, T, n, m, qt = case
+    K, N, T, n, m, qt = case[:6]
+    w = case[6] if len(case) > 6 else "identity"
     say("operators case", case)
-    p = make_problem(K, N, T, n, m, seed=K * 100 + N * 10 + T, qt_scale=qt)
+    p = make_problem(K, N, T, n, m, seed=K * 100 + N * 10 + T, qt_scale=qt, weights=w)
     ctx = lqgrid.Context(p)
     ops = slab.SlabOperators(p)
     v = rand_vec(p, 7)
@@ -101,12 +115,18 @@ def test_operators_match_oracle(lib, torch, case):
     ctx.close()
 
 
-@pytest.mark.parametrize("seed", range(3))
-def test_tiny_solve_matches_dense_kkt(lib, torch, seed):
-    """Tiny configuration: GPU PCG vs brute-force dense KKT LDL'."""
+@pytest.mark.parametrize("seed,w", [(0, "identity"), (1, "identity"), (2, "identity"),
+                                    (3, "spd"), (4, "spd")])
+def test_tiny_solve_matches_dense_kkt(lib, torch, seed, w):
+    """Tiny configuration: GPU PCG vs brute-force dense KKT LDL' (also with
+    per-node SPD weights and Q_T != Q)."""
     from paper_2304_04980_amd import lqgrid
-    p, tol = config_problem("tiny", seed)
-    say("tiny solve seed", seed)
+    if w == "identity":
+        p, tol = config_problem("tiny", seed)
+    else:
+        tol = 1e-10
+        p = make_problem(4, 4, 20, 2, 1, rho=0.9, seed=seed, qt_scale=1.6, weights=w)
+    say("tiny solve seed", seed, w)
     ctx = lqgrid.Context(p)
     delta, x, u, info = ctx.solve(torch.as_tensor(p.x0), lqgrid.default_opts(tol=tol),
                                   want_primal=True)
@@ -137,11 +157,13 @@ def test_tiny_solve_matches_dense_kkt(lib, torch, seed):
     ctx.close()
 
 
-def test_riccati_single_node(lib, torch):
-    """K = N = 1: the GPU solution equals the textbook Riccati LQR."""
+@pytest.mark.parametrize("w", ["identity", "spd"])
+def test_riccati_single_node(lib, torch, w):
+    """K = N = 1: the GPU solution equals the textbook Riccati LQR (scaled
+    identity weights, and full SPD Q, R, Q_T)."""
     from paper_2304_04980_amd import lqgrid
     from oracle import riccati
-    p = make_problem(1, 1, 60, 4, 2, rho=1.05, seed=3, qt_scale=2.0)
+    p = make_problem(1, 1, 60, 4, 2, rho=1.05, seed=3, qt_scale=2.0, weights=w)
     R = riccati.lqr_of_problem(p)
     ctx = lqgrid.Context(p)
     delta, x, u, info = ctx.solve(torch.as_tensor(p.x0),
@@ -232,7 +254,7 @@ F32_CASES = [(4, 4, 20, 2, 1, 1.0), (5, 7, 150, 3, 2, 1.0), (3, 5, 64, 4, 2, 0.7
              (4, 3, 70, 1, 1, 1.0), (16, 2, 129, 1, 1, 0.7)]
 
 
-@pytest.mark.parametrize("case", F32_CASES, ids=[str(c) for c in F32_CASES])
+@pytest.mark.parametrize("case", F32_CASES + SPD_CASES, ids=[str(c) for c in F32_CASES + SPD_CASES])
 def test_fp32_operators_match_oracle(lib, torch, case):
     """FP32 kernels of the precision form against the FP64 oracle.  Inputs and
     coefficients are rounded to FP32 (unit roundoff u = 2^-24 ~ 6e-8); each
@@ -241,9 +263,10 @@ def test_fp32_operators_match_oracle(lib, torch, case):
     cancellation of terms of either sign).  Phi~^-1 adds the conditioning of
     the 2n x 2n Cholesky blocks: 1e-4 * max|ref|."""
     from paper_2304_04980_amd import lqgrid
-    K, N, T, n, m, qt = case
+    K, N, T, n, m, qt = case[:6]
+    w = case[6] if len(case) > 6 else "identity"
     say("fp32 operators case", case)
-    p = make_problem(K, N, T, n, m, seed=K * 100 + N * 10 + T, qt_scale=qt)
+    p = make_problem(K, N, T, n, m, seed=K * 100 + N * 10 + T, qt_scale=qt, weights=w)
     ctx = lqgrid.Context(p)
     ops = slab.SlabOperators(p)
     v = rand_vec(p, 7)
@@ -285,6 +308,43 @@ def test_fp32_refinement_reaches_fp64_accuracy(lib, torch, tol):
     assert g32["rel2"] <= tol * 1.01 and g64["rel2"] <= tol * 1.01
     rel = np.linalg.norm((d32 - d64).cpu().numpy()) / np.linalg.norm(d64.cpu().numpy())
     assert rel <= 1e-3   # both within kappa * tol of delta*
+
+
+# ------------------------------------------------------------ headline size
+@pytest.fixture(scope="module")
+def headline():
+    """The 128 x 128 x 200 workload and the oracle's slab operators of it."""
+    p, tol = config_problem("headline", 0)
+    return p, tol, slab.SlabOperators(p)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_headline_solve_checked_by_oracle(lib, torch, headline, precision):
+    """K = N = 128, T = 200, n = 4, m = 2 (the benchmarked workload) at
+    tol 1e-8 in both forms: the oracle's FP64 KKT residual of the returned
+    delta~, x~ and u~ (all three blocks of the KKT system) meets the
+    tolerance, and the library's own reported residual agrees with the
+    oracle's Schur-complement residual to 1e-3 tol."""
+    from paper_2304_04980_amd import lqgrid
+    p, tol, ops = headline
+    say("headline solve", precision)
+    ctx = lqgrid.Context(p)
+    prec = lqgrid.FP64 if precision == "fp64" else lqgrid.FP32_REFINE
+    opts = lqgrid.default_opts(tol=tol, precision=prec, inner_tol=1e-4)
+    delta, x, u, info = ctx.solve(torch.as_tensor(p.x0), opts, want_primal=True)
+    d = delta.cpu().numpy().reshape(p.T + 1, -1)
+    xs = x.cpu().numpy().reshape(p.T + 1, -1)
+    us = u.cpu().numpy().reshape(p.T, -1)
+    gate = residual.kkt_residual(ops, d, xs, us)
+    own = residual.kkt_residual(ops, d)
+    say(f"  {info['iterations']} it, {info['refinements']} passes; reported "
+        f"{info['rel_kkt_residual']:.3e}, oracle {gate['rel2']:.3e} "
+        f"(with recovered primal {own['rel2']:.3e})")
+    assert info["status"] == lqgrid.OK
+    assert gate["rel2"] <= 1.01 * tol
+    assert own["rel2"] <= 1.01 * tol
+    assert abs(info["rel_kkt_residual"] - own["schur_rel2"]) <= 1e-3 * tol
+    ctx.close()
 
 
 # ------------------------------------------------------------ kernel timing

@@ -58,11 +58,16 @@ def shapes(p, sol):
 
 
 # ---------------------------------------------------------------- pins
-@pytest.mark.parametrize("seed,n,m,T,qt", [(0, 2, 1, 12, 1.0), (1, 3, 2, 25, 1.0),
-                                           (2, 4, 2, 40, 3.0), (3, 1, 1, 7, 0.5)])
-def test_riccati_special_case(seed, n, m, T, qt):
+@pytest.mark.parametrize("seed,n,m,T,qt,w", [(0, 2, 1, 12, 1.0, "identity"),
+                                             (1, 3, 2, 25, 1.0, "identity"),
+                                             (2, 4, 2, 40, 3.0, "identity"),
+                                             (3, 1, 1, 7, 0.5, "identity"),
+                                             # full SPD Q, R and Q_T != Q
+                                             (4, 4, 2, 30, 1.0, "spd"),
+                                             (5, 3, 3, 17, 2.0, "spd")])
+def test_riccati_special_case(seed, n, m, T, qt, w):
     """K = N = 1 must equal the textbook Riccati LQR solution."""
-    p = make_problem(1, 1, T, n, m, rho=1.1, seed=seed, qt_scale=qt)
+    p = make_problem(1, 1, T, n, m, rho=1.1, seed=seed, qt_scale=qt, weights=w)
     R = riccati.lqr_of_problem(p)
     sol = kkt.solve_kkt(p)
     x, u = shapes(p, sol)
@@ -78,11 +83,16 @@ def test_riccati_special_case(seed, n, m, T, qt):
     assert np.abs(xs - R["delta"]).max() <= 1e-9 * max(1, np.abs(R["delta"]).max())
 
 
-@pytest.mark.parametrize("seed", range(5))
-def test_kkt_solution_is_feasible_and_optimal(seed):
+@pytest.mark.parametrize("seed,w", [(s, "identity") for s in range(5)]
+                         + [(5, "spd"), (6, "spd")])
+def test_kkt_solution_is_feasible_and_optimal(seed, w):
     """Brute force on the tiny configuration: the LDL' KKT solution obeys the
-    node-level dynamics, and no random feasible perturbation lowers the cost."""
-    p, _ = config_problem("tiny", seed)
+    node-level dynamics, and no random feasible perturbation lowers the cost
+    (the cost written with loops over the per-node weights)."""
+    if w == "identity":
+        p, _ = config_problem("tiny", seed)
+    else:
+        p = make_problem(4, 4, 20, 2, 1, rho=0.9, seed=seed, qt_scale=1.7, weights=w)
     sol = kkt.solve_kkt(p)
     x, u = shapes(p, sol)
     xs = simulate(p, u)
@@ -112,11 +122,15 @@ def test_schur_solve_equals_kkt_ldl(K, N, T, n, m):
     assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("K,N,T,n,m,qt", [(4, 4, 20, 2, 1, 1.0), (3, 5, 6, 3, 2, 2.0),
-                                          (5, 3, 3, 4, 2, 1.0), (2, 7, 4, 2, 1, 0.3),
-                                          (1, 1, 3, 2, 2, 1.0)])
-def test_slab_operators_match_full_matrices(K, N, T, n, m, qt):
-    p = make_problem(K, N, T, n, m, seed=11, qt_scale=qt)
+@pytest.mark.parametrize("K,N,T,n,m,qt,w", [(4, 4, 20, 2, 1, 1.0, "identity"),
+                                            (3, 5, 6, 3, 2, 2.0, "identity"),
+                                            (5, 3, 3, 4, 2, 1.0, "identity"),
+                                            (2, 7, 4, 2, 1, 0.3, "identity"),
+                                            (1, 1, 3, 2, 2, 1.0, "identity"),
+                                            (4, 5, 6, 3, 2, 1.0, "spd"),
+                                            (5, 3, 4, 4, 2, 0.6, "spd")])
+def test_slab_operators_match_full_matrices(K, N, T, n, m, qt, w):
+    p = make_problem(K, N, T, n, m, seed=11, qt_scale=qt, weights=w)
     ops = slab.SlabOperators(p)
     spl = splitting.splittings(p)
     rng = np.random.default_rng(5)
@@ -130,10 +144,12 @@ def test_slab_operators_match_full_matrices(K, N, T, n, m, qt):
     assert np.linalg.norm(spl["Phi"] @ tau.ravel() - d.ravel()) <= 1e-12 * np.linalg.norm(d)
 
 
-def test_delta_from_node_level_definition():
+@pytest.mark.parametrize("w", ["identity", "spd"])
+def test_delta_from_node_level_definition(w):
     """Delta d equals A~(Q~^-1 A~' d) + B~(R~^-1 B~' d) evaluated with
-    node-level loops (no stacked matrices)."""
-    p = make_problem(3, 4, 5, 2, 1, seed=4)
+    node-level loops (no stacked matrices); with per-node SPD weights a weight
+    taken from the wrong node changes the result."""
+    p = make_problem(3, 4, 5, 2, 2, seed=4, weights=w, qt_scale=1.0 if w == "identity" else 1.4)
     rng = np.random.default_rng(0)
     d = rng.standard_normal((p.T + 1, p.N, p.K, p.n))
     Qi = np.linalg.inv(p.Q)

@@ -85,6 +85,28 @@ def test_missing_terminal_weight_is_caught(monkeypatch):
     assert np.abs(bad["x"].reshape(11, 2) - R["x"]).max() > 1e-4
 
 
+def test_weight_of_the_wrong_node_is_caught(monkeypatch):
+    """With per-node SPD weights, a Q^-1 taken from the wrong node (the node
+    order of the weight blocks reversed) breaks the node-level feasibility
+    pin of the KKT solution."""
+    p = make_problem(3, 4, 6, 2, 1, seed=3, weights="spd")
+    good = kkt.solve_kkt(p)
+    x, u = shapes(p, good)
+    assert np.abs(simulate(p, u) - x).max() < 1e-10
+    real = stack._blkdiag_nodes
+
+    def reversed_nodes(_p, blocks):
+        flip = blocks[::-1, ::-1].copy() if blocks.shape[-1] == _p.n else blocks
+        return real(_p, flip)
+
+    monkeypatch.setattr(stack, "_blkdiag_nodes", reversed_nodes)
+    bad = kkt.solve_kkt(p)
+    xb, ub = shapes(p, bad)
+    # the wrong weights give another (feasible) trajectory: its cost is higher
+    from test_oracle_pins import cost
+    assert cost(p, xb, ub) > cost(p, x, u) * (1 + 1e-6)
+
+
 # ------------------------------------------------------------ warm start
 def _fd_check_fails(monkeypatch_fn=None):
     """Runs the network finite-difference pin; returns True when it fails."""
