@@ -349,3 +349,70 @@ def test_per_iteration_cost_is_linear():
         assert nz["Phi"].max() <= 13 * n and nz["Omega"].max() <= 13 * n
         per.append(spl["Delta"].count_nonzero() / p.unknowns)
     assert per[-1] <= 23 * n and per[-1] > 0.5 * 23 * n
+
+
+# ------------------------------------------------ standalone NBJM, spectra
+def test_lanczos_estimate_on_a_known_spectrum():
+    """CG on a diagonal matrix with a known spectrum: the Lanczos matrix built
+    from the CG coefficients has the exact extreme eigenvalues (textbook
+    equivalence of CG and Lanczos)."""
+    from oracle import lanczos
+    ev = np.concatenate([[1.0], np.linspace(2.0, 50.0, 60), [100.0]])
+    rng = np.random.default_rng(0)
+    b = rng.standard_normal(ev.size)
+    est = lanczos.condition_from_cg(lambda x: ev * x, lambda r: r.copy(), b, tol=1e-13)
+    assert abs(est["lambda_min"] - 1.0) <= 1e-8
+    assert abs(est["lambda_max"] - 100.0) <= 1e-8 * 100
+    # with a diagonal preconditioner P = diag(ev): P^-1 A = I, one step, kappa 1
+    est = lanczos.condition_from_cg(lambda x: ev * x, lambda r: r / ev, b, tol=1e-13)
+    assert est["iterations"] == 1 and abs(est["kappa"] - 1.0) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lanczos_estimates_match_dense_spectra(seed):
+    """On the tiny configuration, the CG estimate of kappa(Delta) and the
+    PCG estimate of kappa(P_S^-1 Delta) (S = L = 2) agree with the dense
+    eigenvalues (Sec. V's conditioning comparison) to 1 %."""
+    from oracle import lanczos
+    p, _ = config_problem("tiny", seed)
+    ops = slab.SlabOperators(p)
+    spl = splitting.splittings(p)
+    D = spl["Delta"].toarray()
+    ev = np.linalg.eigvalsh(D)
+    Pinv = splitting.preconditioner_inverse(spl, 2, 2)
+    evp = np.sort(np.linalg.eigvals(Pinv @ D).real)
+    cg = lanczos.condition_from_cg(ops.delta, lambda r: r.copy(), ops.r_delta(), tol=1e-10)
+    pc = lanczos.condition_from_cg(ops.delta, nbjm.slab_preconditioner(ops, 2, 2),
+                                   ops.r_delta(), tol=1e-10)
+    assert abs(cg["kappa"] / (ev[-1] / ev[0]) - 1) <= 1e-2
+    assert abs(pc["kappa"] / (evp[-1] / evp[0]) - 1) <= 1e-2
+    assert pc["kappa"] < cg["kappa"] / 10        # the preconditioner's gain
+
+
+def test_standalone_nbjm_converges_at_the_predicted_rate():
+    """Standalone NBJM (inner iterations started from the outer iterate):
+    converges to the dense solution, at the rate rho(G) of its iteration
+    matrix G = Upsilon_L Xi~ + (Phi~^-1 Omega~)^L; started from theta = 0 in
+    every outer iteration (as printed, for the preconditioner) it converges to
+    (Upsilon_L^-1 - Xi~)^-1 r_delta instead, which is not the solution."""
+    p, _ = config_problem("tiny", 0)
+    ops = slab.SlabOperators(p)
+    spl = splitting.splittings(p)
+    Phi, Om, Xi = (spl[k].toarray() for k in ("Phi", "Omega", "Xi"))
+    U = splitting.upsilon(spl["Phi"], spl["Omega"], 2)
+    G = U @ Xi + np.linalg.matrix_power(np.linalg.solve(Phi, Om), 2)
+    rho = np.abs(np.linalg.eigvals(G)).max()
+    d, s, h = nbjm.slab_nbjm_solve(ops, 2, tol=1e-10)
+    ds = kkt.solve_schur_dense(p)
+    assert np.linalg.norm(d.ravel() - ds) <= 1e-8 * np.linalg.norm(ds)
+    rate = (h["res"][-1] / h["res"][-201]) ** (1 / 200)
+    assert abs(rate - rho) <= 1e-3
+    assert 100 < s < 5000
+    # the printed zero inner start: fixed point (Upsilon_L^-1 - Xi~)^-1 r
+    rd = ops.r_delta().ravel()
+    fixed = np.linalg.solve(np.linalg.inv(U) - Xi, rd)
+    x = np.zeros_like(rd)
+    for _ in range(3000):
+        x = U @ (rd + Xi @ x)
+    assert np.linalg.norm(x - fixed) <= 1e-8 * np.linalg.norm(fixed)
+    assert np.linalg.norm(fixed - ds) >= 1e-2 * np.linalg.norm(ds)
