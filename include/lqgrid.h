@@ -269,10 +269,35 @@ LQGRID_API int lqgrid_wsnet_predict(const lqgrid_wsnet_desc *desc, const void *f
                                     void *workspace, size_t workspace_bytes,
                                     void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same computation as lqgrid_setup + lqgrid_factor +
+ * lqgrid_pcg_solve (zero start, same kernels and results), with the
+ * workspace in a static device array of the library instead of the caller's
+ * buffer: lqgrid_noalloc_capacity() bytes (80 MiB, enough for the
+ * 32 x 32 x 100, n = 4, m = 2 workload), held by every GPU the library runs
+ * on until the process ends.  The caller passes inputs and outputs as for
+ * the three calls it replaces; the call runs on the stream's device, which
+ * must be the current device.  It calls no hipMalloc, hipFree or other
+ * allocating routine, creates no event and keeps its context on the stack
+ * (info->seconds is host time around the synchronised solve).
+ * Errors: as lqgrid_setup / lqgrid_factor / lqgrid_pcg_solve, and
+ * LQGRID_EWORKSPACE when lqgrid_workspace_bytes(desc) exceeds the capacity
+ * (lqgrid_last_error() names both sizes).  Every call on one GPU uses that
+ * GPU's one array: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller. */
+LQGRID_API size_t lqgrid_noalloc_capacity(void);
+LQGRID_API int lqgrid_solve_noalloc(const lqgrid_problem_desc *desc, const double *x0,
+                                    const lqgrid_solve_opts *opts, double *delta,
+                                    double *x, double *u, void *hip_stream,
+                                    lqgrid_info *info);
+
 LQGRID_API void lqgrid_destroy(lqgrid_ctx *ctx);
 LQGRID_API const char *lqgrid_status_string(int status);
 LQGRID_API int lqgrid_abi_version(void);
-/* Text of the last HIP runtime failure seen by this thread (for EHIP). */
+/* Text of the last HIP runtime failure seen by this thread (for EHIP), or of
+ * the scratch-size error of lqgrid_solve_noalloc. */
 LQGRID_API const char *lqgrid_last_error(void);
 
 #ifdef __cplusplus

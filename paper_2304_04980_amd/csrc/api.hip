@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -396,6 +398,94 @@ void make_f32_blocks(lqgrid_ctx* c, bool factors) {
   }
 }
 
+
+// Scratch of the allocation-free entry point: the whole workspace of one
+// solve, in a file-scope device array that every GPU the library runs on
+// holds until the process ends.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returns, looked up once per device
+// with that device current.
+constexpr size_t kNoAllocBytes = (size_t)80 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return LQGRID_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (reinterpret_cast<uintptr_t>(p) % kAlign) != 0)
+      return hip_fail(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LQGRID_OK;
+}
+
+// Argument checks shared by lqgrid_setup and lqgrid_solve_noalloc.
+int check_problem(const lqgrid_problem_desc* desc, Dims* D) {
+  if (!make_dims(desc, D)) return LQGRID_EINVAL;
+  if (!desc->A || !desc->A_nbr || !desc->B || !desc->Q || !desc->R)
+    return LQGRID_EINVAL;
+  if (D->n > kMaxN || D->m > kMaxM) return LQGRID_EUNSUPPORTED;
+  // the block solves address each vector with 32-bit byte offsets
+  if (D->vlen * 8 >= (1LL << 31)) return LQGRID_EUNSUPPORTED;
+  return LQGRID_OK;
+}
+
+// Lays the workspace out for the problem, clears what must start at zero and
+// enqueues ingest and assembly into c (a fresh context).
+int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
+               void* workspace, size_t workspace_bytes, void* hip_stream) {
+  const Plan P = make_plan(D);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 ||
+      workspace_bytes < P.total)
+    return LQGRID_EWORKSPACE;
+  c->D = D;
+  c->P = P;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<char*>(workspace);
+  char* w = c->ws;
+  auto dp = [&](size_t off) { return reinterpret_cast<double*>(w + off); };
+  auto fp = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
+  c->sc = reinterpret_cast<Scalars*>(w + P.scal);
+  c->sco = reinterpret_cast<Scalars*>(w + P.scal_outer);
+  c->C = Coef{dp(P.G13), dp(P.Cdn), dp(P.Cup), dp(P.AT5), dp(P.Qi), dp(P.QTi),
+              dp(P.QTd), dp(P.Qm), dp(P.RiBT), dp(P.Fw), dp(P.Bw), dp(P.Xw)};
+  c->op64 = OpCoef<double>{c->C.G13, c->C.Cdn, c->C.Cup, c->C.Qi, c->C.QTd,
+                           c->C.Qm, c->C.Fw, c->C.Bw, c->C.Xw};
+  c->op32 = OpCoef<float>{fp(P.G13f), fp(P.Cdnf), fp(P.Cupf), fp(P.Qif),
+                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf), fp(P.Xwf)};
+  for (int v = 0; v < kNumOuter; ++v) c->outer[v] = dp(P.outer[v]);
+  for (int v = 0; v < kNumPcg; ++v) {
+    c->b64.v[v] = dp(P.p64[v]);
+    c->b32.v[v] = fp(P.p32[v]);
+  }
+  c->psum = dp(P.psum);
+  c->pmax = dp(P.pmax);
+  clear_stale_error();
+  // zero the scalars and every vector (padding entries must stay zero)
+  vec_zero<double>(dp(P.scal), (long long)(P.G13 - P.scal) / 8, c->stream);
+  for (int v = 0; v < kNumOuter; ++v) vec_zero<double>(c->outer[v], D.vlen, c->stream);
+  for (int v = 0; v < kNumPcg; ++v) {
+    vec_zero<double>(c->b64.v[v], D.vlen, c->stream);
+    vec_zero<float>(c->b32.v[v], D.vlen, c->stream);
+  }
+  ProblemIn in{D.K, D.N, D.n, D.m, desc->A, desc->A_nbr, desc->B,
+               desc->Q, desc->R, desc->QT};
+  launch_setup(D, in, c->C, c->sc, c->stream);
+  make_f32_blocks(c, false);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "lqgrid_setup launch");
+  return LQGRID_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -441,56 +531,14 @@ int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
   if (!out) return LQGRID_EINVAL;
   *out = nullptr;
   Dims D;
-  if (!make_dims(desc, &D)) return LQGRID_EINVAL;
-  if (!desc->A || !desc->A_nbr || !desc->B || !desc->Q || !desc->R)
-    return LQGRID_EINVAL;
-  if (D.n > kMaxN || D.m > kMaxM) return LQGRID_EUNSUPPORTED;
-  // the block solves address each vector with 32-bit byte offsets
-  if (D.vlen * 8 >= (1LL << 31)) return LQGRID_EUNSUPPORTED;
-  const Plan P = make_plan(D);
-  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 ||
-      workspace_bytes < P.total)
-    return LQGRID_EWORKSPACE;
+  const int chk = check_problem(desc, &D);
+  if (chk != LQGRID_OK) return chk;
   lqgrid_ctx* c = new (std::nothrow) lqgrid_ctx();
   if (!c) return LQGRID_EHIP;
-  c->D = D;
-  c->P = P;
-  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->ws = static_cast<char*>(workspace);
-  char* w = c->ws;
-  auto dp = [&](size_t off) { return reinterpret_cast<double*>(w + off); };
-  auto fp = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
-  c->sc = reinterpret_cast<Scalars*>(w + P.scal);
-  c->sco = reinterpret_cast<Scalars*>(w + P.scal_outer);
-  c->C = Coef{dp(P.G13), dp(P.Cdn), dp(P.Cup), dp(P.AT5), dp(P.Qi), dp(P.QTi),
-              dp(P.QTd), dp(P.Qm), dp(P.RiBT), dp(P.Fw), dp(P.Bw), dp(P.Xw)};
-  c->op64 = OpCoef<double>{c->C.G13, c->C.Cdn, c->C.Cup, c->C.Qi, c->C.QTd,
-                           c->C.Qm, c->C.Fw, c->C.Bw, c->C.Xw};
-  c->op32 = OpCoef<float>{fp(P.G13f), fp(P.Cdnf), fp(P.Cupf), fp(P.Qif),
-                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf), fp(P.Xwf)};
-  for (int v = 0; v < kNumOuter; ++v) c->outer[v] = dp(P.outer[v]);
-  for (int v = 0; v < kNumPcg; ++v) {
-    c->b64.v[v] = dp(P.p64[v]);
-    c->b32.v[v] = fp(P.p32[v]);
-  }
-  c->psum = dp(P.psum);
-  c->pmax = dp(P.pmax);
-  clear_stale_error();
-  // zero the scalars and every vector (padding entries must stay zero)
-  vec_zero<double>(dp(P.scal), (long long)(P.G13 - P.scal) / 8, c->stream);
-  for (int v = 0; v < kNumOuter; ++v) vec_zero<double>(c->outer[v], D.vlen, c->stream);
-  for (int v = 0; v < kNumPcg; ++v) {
-    vec_zero<double>(c->b64.v[v], D.vlen, c->stream);
-    vec_zero<float>(c->b32.v[v], D.vlen, c->stream);
-  }
-  ProblemIn in{D.K, D.N, D.n, D.m, desc->A, desc->A_nbr, desc->B,
-               desc->Q, desc->R, desc->QT};
-  launch_setup(D, in, c->C, c->sc, c->stream);
-  make_f32_blocks(c, false);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
+  const int st = setup_into(c, desc, D, workspace, workspace_bytes, hip_stream);
+  if (st != LQGRID_OK) {
     delete c;
-    return hip_fail(e, "lqgrid_setup launch");
+    return st;
   }
   *out = c;
   return LQGRID_OK;
@@ -517,9 +565,15 @@ int lqgrid_factor(lqgrid_ctx* c) {
   return LQGRID_OK;
 }
 
-int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
-                     const lqgrid_solve_opts* opts_in, const double* delta_init,
-                     double* delta, double* x, double* u, lqgrid_info* info) {
+namespace {
+
+// The body of lqgrid_pcg_solve.  With timed_events the device time comes from
+// two HIP events around the solve; without (the allocation-free entry point)
+// from the host clock around the synchronised solve.
+int pcg_solve_impl(lqgrid_ctx* c, const double* x0,
+                   const lqgrid_solve_opts* opts_in, const double* delta_init,
+                   double* delta, double* x, double* u, lqgrid_info* info,
+                   bool timed_events) {
   if (info) std::memset(info, 0, sizeof(*info));
   if (!c || !x0 || !delta) return LQGRID_EINVAL;
   lqgrid_solve_opts o;
@@ -536,10 +590,12 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
       if (b) (void)hipEventDestroy(b);
     }
   } ev;
-  HIPCHECK(hipEventCreate(&ev.a));
-  HIPCHECK(hipEventCreate(&ev.b));
-  hipEvent_t e0 = ev.a, e1 = ev.b;
-  HIPCHECK(hipEventRecord(e0, s));
+  const auto h0 = std::chrono::steady_clock::now();
+  if (timed_events) {
+    HIPCHECK(hipEventCreate(&ev.a));
+    HIPCHECK(hipEventCreate(&ev.b));
+    HIPCHECK(hipEventRecord(ev.a, s));
+  }
 
   // r_delta, ||r_delta||, tol^2 ||r_delta||^2 (outer scalars)
   launch_rhs_init(D, x0, c->outer[kRd], s);
@@ -592,11 +648,17 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
   }
   to_abi(D, c->outer[kDl], delta, s);
   if (x || u) recover(D, c->C, c->outer[kDl], x, u, s);
-  HIPCHECK(hipEventRecord(e1, s));
-  HIPCHECK(hipEventSynchronize(e1));
-  if (c->prof_used) prof_resolve(c);
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
+  if (timed_events) {
+    HIPCHECK(hipEventRecord(ev.b, s));
+    HIPCHECK(hipEventSynchronize(ev.b));
+    (void)hipEventElapsedTime(&ms, ev.a, ev.b);
+  } else {
+    HIPCHECK(hipStreamSynchronize(s));
+    ms = (float)std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now() - h0).count();
+  }
+  if (c->prof_used) prof_resolve(c);
   HIPCHECK(hipGetLastError());
   if (info) {
     info->status = status;
@@ -609,6 +671,14 @@ int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
     info->warm_start_used = warm ? 1 : 0;
   }
   return status;
+}
+
+}  // namespace
+
+int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
+                     const lqgrid_solve_opts* opts_in, const double* delta_init,
+                     double* delta, double* x, double* u, lqgrid_info* info) {
+  return pcg_solve_impl(c, x0, opts_in, delta_init, delta, x, u, info, true);
 }
 
 int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
@@ -678,6 +748,34 @@ int lqgrid_profile_read(lqgrid_ctx* c, int kernel, long long* launches,
   if (launches) *launches = c->prof_launches[kernel];
   if (total_ms) *total_ms = c->prof_ms[kernel];
   return LQGRID_OK;
+}
+
+size_t lqgrid_noalloc_capacity(void) { return kNoAllocBytes; }
+
+int lqgrid_solve_noalloc(const lqgrid_problem_desc* desc, const double* x0,
+                         const lqgrid_solve_opts* opts, double* delta, double* x,
+                         double* u, void* hip_stream, lqgrid_info* info) {
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!x0 || !delta) return LQGRID_EINVAL;
+  Dims D;
+  const int chk = check_problem(desc, &D);
+  if (chk != LQGRID_OK) return chk;
+  const size_t need = make_plan(D).total;
+  if (need > kNoAllocBytes) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "lqgrid_solve_noalloc: the problem needs %zu bytes of scratch, "
+                  "the library's static scratch holds %zu", need, kNoAllocBytes);
+    return LQGRID_EWORKSPACE;
+  }
+  void* ws = nullptr;
+  const int st = scratch_of_current_device(&ws);
+  if (st != LQGRID_OK) return st;
+  lqgrid_ctx c;  // on the stack: nothing is allocated on the host either
+  int r = setup_into(&c, desc, D, ws, kNoAllocBytes, hip_stream);
+  if (r != LQGRID_OK) return r;
+  r = lqgrid_factor(&c);
+  if (r != LQGRID_OK) return r;
+  return pcg_solve_impl(&c, x0, opts, nullptr, delta, x, u, info, false);
 }
 
 void lqgrid_destroy(lqgrid_ctx* c) { delete c; }

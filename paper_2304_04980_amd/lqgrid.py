@@ -131,6 +131,12 @@ def load(path: str = LIB_PATH):
     L.lqgrid_wsnet_predict.argtypes = [W, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_size_t, c_void_p]
     L.lqgrid_wsnet_predict.restype = c_int
+    L.lqgrid_noalloc_capacity.argtypes = []
+    L.lqgrid_noalloc_capacity.restype = c_size_t
+    L.lqgrid_solve_noalloc.argtypes = [POINTER(ProblemDesc), c_void_p, POINTER(SolveOpts),
+                                       c_void_p, c_void_p, c_void_p, c_void_p,
+                                       POINTER(Info)]
+    L.lqgrid_solve_noalloc.restype = c_int
     _lib = L
     return L
 
@@ -143,7 +149,8 @@ EXPORTED = ["lqgrid_default_opts", "lqgrid_workspace_bytes", "lqgrid_setup",
             "lqgrid_wsnet_param_count", "lqgrid_wsnet_sample_bytes",
             "lqgrid_wsnet_workspace_bytes", "lqgrid_wsnet_features",
             "lqgrid_wsnet_targets", "lqgrid_wsnet_forward", "lqgrid_wsnet_gradient",
-            "lqgrid_wsnet_adam", "lqgrid_wsnet_predict"]
+            "lqgrid_wsnet_adam", "lqgrid_wsnet_predict", "lqgrid_noalloc_capacity",
+            "lqgrid_solve_noalloc"]
 
 
 class LqgridError(RuntimeError):
@@ -338,6 +345,16 @@ class Batch:
         st = self.L.lqgrid_batch_solve(self.P, self.descs, self.x0p, byref(o), self.outp,
                                        c_void_p(self.wp), self.nbytes, _stream(), infos)
         return self.outs, [i.as_dict() for i in infos], st
+
+
+def solve_noalloc(desc: ProblemDesc, x0, opts: SolveOpts, delta, x=None, u=None):
+    """lqgrid_solve_noalloc: setup + factor + solve in the library's static
+    device scratch (no workspace, no allocation).  desc holds device arrays;
+    x0, delta, x, u are device tensors.  Returns (status, info dict)."""
+    info = Info()
+    st = load().lqgrid_solve_noalloc(byref(desc), _ptr(x0), byref(opts), _ptr(delta),
+                                     _ptr(x), _ptr(u), _stream(), byref(info))
+    return st, info.as_dict()
 
 
 def batch_solve(problems, x0s=None, opts: SolveOpts | None = None, device="cuda"):
