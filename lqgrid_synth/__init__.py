@@ -67,6 +67,23 @@ class Problem:
     x0: np.ndarray
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    # spatial boundary states (Sec. II, eqs. "boundary_condition_i/j"), None
+    # meaning zero: alpha_lo = x_{0,j,t} [T+1][N][n], alpha_hi = x_{K+1,j,t}
+    # [T+1][N][n], beta_lo = x_{i,0,t} [T+1][K][n], beta_hi = x_{i,N+1,t}
+    # [T+1][K][n] (0-based: the rows i = -1, i = K and the columns j = -1,
+    # j = N next to the grid)
+    alpha_lo: np.ndarray | None = None
+    alpha_hi: np.ndarray | None = None
+    beta_lo: np.ndarray | None = None
+    beta_hi: np.ndarray | None = None
+    # per-node state / input sizes (Sec. II), None meaning n and m everywhere
+    n_node: np.ndarray | None = None
+    m_node: np.ndarray | None = None
+
+    @property
+    def has_boundary(self) -> bool:
+        return any(b is not None for b in (self.alpha_lo, self.alpha_hi,
+                                           self.beta_lo, self.beta_hi))
 
     @property
     def unknowns(self) -> int:
@@ -81,13 +98,20 @@ def _spectral_radius(M: np.ndarray) -> float:
 def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
                  cs: float = 0.1, seed: int = 0, r_scale: float = 0.1,
                  q_scale: float = 1.0, qt_scale: float | None = None,
-                 weights: str = "identity") -> Problem:
+                 weights: str = "identity", boundary: bool = False,
+                 sizes: bool = False) -> Problem:
     """Draw one problem by the recipe in the module docstring.
 
     ``q_scale``/``qt_scale`` scale the weights; they exist so tests can
     exercise a terminal weight different from Q (default QT = Q).
     ``weights``: "identity" (the recipe's scaled identities) or "spd"
-    (random per-node SPD weights, drawn after x0)."""
+    (random per-node SPD weights, drawn after x0).  ``boundary``: draw
+    non-zero spatial boundary states (standard normal, in the order
+    alpha_lo, alpha_hi, beta_lo, beta_hi, after everything else).
+    ``sizes``: heterogeneous sub-systems -- per-node n_node in U{1..n} and
+    m_node in U{1..m} ([N][K] int arrays, drawn last); the arrays keep their
+    padded shapes and the entries past a node's sizes hold the values drawn
+    above, which a solver must ignore."""
     if min(K, N, T, n, m) < 1:
         raise ValueError("all dimensions must be >= 1")
     rng = np.random.default_rng(seed)
@@ -118,8 +142,17 @@ def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
         R = r_scale * _random_spd(rng, N, K, m)
     else:
         raise ValueError(f"unknown weights {weights!r}")
-    return Problem(K, N, T, n, m, A, A_nbr, B, Q, R, QT, x0, seed,
-                   dict(rho=rho, cs=cs, r_scale=r_scale, weights=weights))
+    p = Problem(K, N, T, n, m, A, A_nbr, B, Q, R, QT, x0, seed,
+                dict(rho=rho, cs=cs, r_scale=r_scale, weights=weights))
+    if boundary:
+        p.alpha_lo = rng.standard_normal((T + 1, N, n))
+        p.alpha_hi = rng.standard_normal((T + 1, N, n))
+        p.beta_lo = rng.standard_normal((T + 1, K, n))
+        p.beta_hi = rng.standard_normal((T + 1, K, n))
+    if sizes:
+        p.n_node = rng.integers(1, n + 1, size=(N, K)).astype(np.int32)
+        p.m_node = rng.integers(1, m + 1, size=(N, K)).astype(np.int32)
+    return p
 
 
 def _random_spd(rng, N: int, K: int, k: int) -> np.ndarray:

@@ -169,6 +169,4 @@ class SlabOperators:
 
     # -- problem data ---------------------------------------------------
     def r_delta(self) -> np.ndarray:
-        r = np.zeros((self.T + 1, self.KNn))
-        r[0] = -stack.gamma_hat(self.p)
-        return r
+        return stack.r_delta(self.p).reshape(self.T + 1, self.KNn)

@@ -10,10 +10,15 @@ so (0-based) entry c of node (i, j) at time t sits at
 The multiplier vector delta_tilde uses the same ordering.
 
 Readings used here (the paper is garbled or silent at these points):
-  * omega_tilde = col(gamma_hat, 0, ..., 0) for zero spatial boundary states:
-    the printed col(0, omega_hat_0, ...) with gamma_hat inside omega_hat_0
+  * omega_tilde = col(gamma_hat, omega_hat_0, ..., omega_hat_{T-1}): the
+    printed col(0, omega_hat_0, ...) with gamma_hat inside omega_hat_0
     would contradict x_{i,j,0} = gamma; the first block row of A_tilde is -I,
-    so the constraint reads -x_hat_0 + gamma_hat = 0.
+    so the constraint reads -x_hat_0 + gamma_hat = 0.  omega_hat_t holds the
+    known boundary states' contribution to x_hat_{t+1} (M_hat alpha_hat_t +
+    N_hat beta_hat_t): for node (i, j) the coupling blocks whose neighbour
+    lies just outside the grid (G at i = 0, H at i = K-1, E at j = 0, F at
+    j = N-1, 0-based) times that boundary state at time t; zero boundary
+    states give omega_hat_t = 0.
   * r_delta = -omega_tilde (Sec. II-B).
   * Q_hat_T = Q_T, Q_hat_t = Q for t < T; R_tilde stops at t = T-1 because
     R_T = 0 removes u_T (Sec. II, after the cost).
@@ -94,6 +99,35 @@ def gamma_hat(p) -> np.ndarray:
     return np.asarray(p.x0, dtype=np.float64).reshape(-1).copy()
 
 
+def omega_hat(p, t: int) -> np.ndarray:
+    """Boundary contribution to x_hat_{t+1} (stacking order), t = 0..T-1,
+    written out per node from eq. "2d_graph_dynamics"."""
+    K, N, n = p.K, p.N, p.n
+    w = np.zeros((N, K, n))
+    if getattr(p, "alpha_lo", None) is not None:
+        for j in range(N):
+            w[j, 0] += p.A_nbr[j, 0, 2] @ p.alpha_lo[t, j]        # G x_{0,j}
+    if getattr(p, "alpha_hi", None) is not None:
+        for j in range(N):
+            w[j, K - 1] += p.A_nbr[j, K - 1, 3] @ p.alpha_hi[t, j]  # H x_{K+1,j}
+    if getattr(p, "beta_lo", None) is not None:
+        for i in range(K):
+            w[0, i] += p.A_nbr[0, i, 0] @ p.beta_lo[t, i]         # E x_{i,0}
+    if getattr(p, "beta_hi", None) is not None:
+        for i in range(K):
+            w[N - 1, i] += p.A_nbr[N - 1, i, 1] @ p.beta_hi[t, i]   # F x_{i,N+1}
+    return w.reshape(-1)
+
+
+def omega_tilde(p) -> np.ndarray:
+    KNn = p.K * p.N * p.n
+    omega = np.zeros((p.T + 1) * KNn)
+    omega[:KNn] = gamma_hat(p)
+    for t in range(p.T):
+        omega[(t + 1) * KNn:(t + 2) * KNn] = omega_hat(p, t)
+    return omega
+
+
 def stacked(p) -> dict:
     """A_tilde, B_tilde, Q_tilde, R_tilde, omega_tilde, r_delta
     (eq. "t_stacked_LQ_problem" and the definitions after it)."""
@@ -117,8 +151,7 @@ def stacked(p) -> dict:
     Bt = sp.bmat(bb, format="csr")
     Qt = sp.block_diag([Q_hat(p, t) for t in range(T + 1)], format="csr")
     Rt = sp.block_diag([R_hat(p) for _ in range(T)], format="csr")
-    omega = np.zeros((T + 1) * KNn)
-    omega[:KNn] = gamma_hat(p)
+    omega = omega_tilde(p)
     return dict(At=At, Bt=Bt, Qt=Qt, Rt=Rt, omega=omega, r_delta=-omega)
 
 
@@ -140,7 +173,6 @@ def delta_matrix(p, S: dict | None = None) -> sp.csr_matrix:
 
 
 def r_delta(p) -> np.ndarray:
-    """r_delta = -omega_tilde = col(-gamma_hat, 0, ..., 0)."""
-    r = np.zeros((p.T + 1) * p.K * p.N * p.n)
-    r[: p.K * p.N * p.n] = -gamma_hat(p)
-    return r
+    """r_delta = -omega_tilde = col(-gamma_hat, -omega_hat_0, ...,
+    -omega_hat_{T-1})."""
+    return -omega_tilde(p)

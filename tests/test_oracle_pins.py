@@ -17,23 +17,27 @@ from oracle import stack, kkt, riccati, splitting, slab, nbjm, pcg, residual
 # ---------------------------------------------------------------- helpers
 def simulate(p, u):
     """x_{i,j,t+1} = A x + B u + E x_{i,j-1} + F x_{i,j+1} + G x_{i-1,j}
-    + H x_{i+1,j}, zero boundary states, x_{.,.,0} = gamma.
-    u: [T][N][K][m] -> x: [T+1][N][K][n]."""
+    + H x_{i+1,j}, x_{.,.,0} = gamma; a neighbour outside the grid is the
+    boundary state of eqs. "boundary_condition_i/j" (zero when the problem
+    has none).  u: [T][N][K][m] -> x: [T+1][N][K][n]."""
     K, N, T, n = p.K, p.N, p.T, p.n
     x = np.zeros((T + 1, N, K, n))
     x[0] = p.x0
+    zero = np.zeros(n)
+
+    def bnd(arr, t, k):
+        return zero if arr is None else arr[t, k]
+
     for t in range(T):
         for j in range(N):
             for i in range(K):
                 acc = p.A[j, i] @ x[t, j, i] + p.B[j, i] @ u[t, j, i]
-                if j - 1 >= 0:
-                    acc += p.A_nbr[j, i, 0] @ x[t, j - 1, i]
-                if j + 1 < N:
-                    acc += p.A_nbr[j, i, 1] @ x[t, j + 1, i]
-                if i - 1 >= 0:
-                    acc += p.A_nbr[j, i, 2] @ x[t, j, i - 1]
-                if i + 1 < K:
-                    acc += p.A_nbr[j, i, 3] @ x[t, j, i + 1]
+                west = x[t, j - 1, i] if j - 1 >= 0 else bnd(p.beta_lo, t, i)
+                east = x[t, j + 1, i] if j + 1 < N else bnd(p.beta_hi, t, i)
+                north = x[t, j, i - 1] if i - 1 >= 0 else bnd(p.alpha_lo, t, j)
+                south = x[t, j, i + 1] if i + 1 < K else bnd(p.alpha_hi, t, j)
+                acc += p.A_nbr[j, i, 0] @ west + p.A_nbr[j, i, 1] @ east
+                acc += p.A_nbr[j, i, 2] @ north + p.A_nbr[j, i, 3] @ south
                 x[t + 1, j, i] = acc
     return x
 
@@ -83,16 +87,19 @@ def test_riccati_special_case(seed, n, m, T, qt, w):
     assert np.abs(xs - R["delta"]).max() <= 1e-9 * max(1, np.abs(R["delta"]).max())
 
 
-@pytest.mark.parametrize("seed,w", [(s, "identity") for s in range(5)]
-                         + [(5, "spd"), (6, "spd")])
-def test_kkt_solution_is_feasible_and_optimal(seed, w):
+@pytest.mark.parametrize("seed,w,bnd", [(s, "identity", False) for s in range(5)]
+                         + [(5, "spd", False), (6, "spd", False),
+                            (7, "identity", True), (8, "spd", True)])
+def test_kkt_solution_is_feasible_and_optimal(seed, w, bnd):
     """Brute force on the tiny configuration: the LDL' KKT solution obeys the
-    node-level dynamics, and no random feasible perturbation lowers the cost
-    (the cost written with loops over the per-node weights)."""
-    if w == "identity":
+    node-level dynamics (with the boundary states as the neighbours outside
+    the grid), and no random feasible perturbation lowers the cost (the cost
+    written with loops over the per-node weights)."""
+    if w == "identity" and not bnd:
         p, _ = config_problem("tiny", seed)
     else:
-        p = make_problem(4, 4, 20, 2, 1, rho=0.9, seed=seed, qt_scale=1.7, weights=w)
+        p = make_problem(4, 4, 20, 2, 1, rho=0.9, seed=seed, qt_scale=1.7, weights=w,
+                         boundary=bnd)
     sol = kkt.solve_kkt(p)
     x, u = shapes(p, sol)
     xs = simulate(p, u)
@@ -416,3 +423,94 @@ def test_standalone_nbjm_converges_at_the_predicted_rate():
         x = U @ (rd + Xi @ x)
     assert np.linalg.norm(x - fixed) <= 1e-8 * np.linalg.norm(fixed)
     assert np.linalg.norm(fixed - ds) >= 1e-2 * np.linalg.norm(ds)
+
+
+# ------------------------------------------------ heterogeneous sizes
+def simulate_hetero(p, u):
+    """The dynamics with per-node sizes n_{i,j}, m_{i,j} (only the leading
+    n_p x n_q part of each coupling block), written with loops."""
+    K, N, T = p.K, p.N, p.T
+    ns, ms = p.n_node, p.m_node
+    x = [[[np.asarray(p.x0[j, i][:ns[j, i]], dtype=float) for i in range(K)]
+          for j in range(N)]]
+    for t in range(T):
+        nxt = []
+        for j in range(N):
+            col = []
+            for i in range(K):
+                a = ns[j, i]
+                acc = p.A[j, i][:a, :a] @ x[t][j][i] + p.B[j, i][:a, :ms[j, i]] @ u[t][j][i]
+                for slot, (ii, jj) in enumerate([(i, j - 1), (i, j + 1), (i - 1, j), (i + 1, j)]):
+                    if 0 <= ii < K and 0 <= jj < N:
+                        acc = acc + p.A_nbr[j, i, slot][:a, :ns[jj, ii]] @ x[t][jj][ii]
+                col.append(acc)
+            nxt.append(col)
+        x.append(nxt)
+    return x
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_heterogeneous_sizes(seed):
+    """Per-node sizes: the variable-block KKT solution obeys the node-level
+    dynamics and is optimal against random feasible perturbations; with
+    every size at its maximum it is the uniform solution; and padding each
+    node to n, m with decoupled rows (zero coupling rows and columns, unit
+    weights, zero initial state) reproduces it, with zero multipliers and
+    inputs in the padding."""
+    from oracle import hetero
+    p = make_problem(3, 4, 6, 3, 2, seed=seed, sizes=True, weights="spd")
+    h = hetero.solve(p, p.n_node, p.m_node)
+    ns, ms = p.n_node, p.m_node
+    K, N, T = p.K, p.N, p.T
+    uu = [[[h["u"][t, j, i, :ms[j, i]] for i in range(K)] for j in range(N)] for t in range(T)]
+    xs = simulate_hetero(p, uu)
+    err = max(np.abs(xs[t][j][i] - h["x"][t, j, i, :ns[j, i]]).max()
+              for t in range(T + 1) for j in range(N) for i in range(K))
+    assert err <= 1e-11 * np.abs(h["x"]).max()
+
+    def J(xs, uu):
+        s = 0.0
+        for t in range(T + 1):
+            for j in range(N):
+                for i in range(K):
+                    a = ns[j, i]
+                    Qm = (p.QT if t == T else p.Q)[j, i][:a, :a]
+                    s += xs[t][j][i] @ Qm @ xs[t][j][i]
+                    if t < T:
+                        b = ms[j, i]
+                        s += uu[t][j][i] @ p.R[j, i][:b, :b] @ uu[t][j][i]
+        return 0.5 * s
+
+    J0 = J(xs, uu)
+    rng = np.random.default_rng(seed)
+    for _ in range(3):
+        u2 = [[[v + 1e-3 * rng.standard_normal(v.shape) for v in col] for col in sl] for sl in uu]
+        assert J(simulate_hetero(p, u2), u2) > J0
+    # all sizes at the maximum: the uniform problem
+    full = hetero.solve(p, np.full((N, K), p.n), np.full((N, K), p.m))
+    ref = kkt.solve_kkt(p)
+    assert np.abs(full["delta"].ravel() - ref["delta"]).max() <= 1e-11 * np.abs(ref["delta"]).max()
+    # padding with decoupled rows
+    q = make_problem(3, 4, 6, 3, 2, seed=seed, sizes=True, weights="spd")
+    for j in range(N):
+        for i in range(K):
+            a, b = ns[j, i], ms[j, i]
+            q.A[j, i][a:, :] = 0.0
+            q.A[j, i][:, a:] = 0.0
+            q.B[j, i][a:, :] = 0.0
+            q.B[j, i][:, b:] = 0.0
+            q.x0[j, i][a:] = 0.0
+            for slot, (ii, jj) in enumerate([(i, j - 1), (i, j + 1), (i - 1, j), (i + 1, j)]):
+                q.A_nbr[j, i, slot][a:, :] = 0.0
+                if 0 <= ii < K and 0 <= jj < N:
+                    q.A_nbr[j, i, slot][:, ns[jj, ii]:] = 0.0
+            for W, k in ((q.Q, a), (q.QT, a), (q.R, b)):
+                blk = W[j, i].copy()
+                W[j, i] = np.eye(W.shape[-1])
+                W[j, i][:k, :k] = blk[:k, :k]
+    padded = kkt.solve_kkt(q)
+    for key in ("delta", "x"):
+        got = padded[key].reshape(T + 1, N, K, p.n)
+        assert np.abs(got - h[key]).max() <= 1e-11 * np.abs(h[key]).max()
+    gotu = padded["u"].reshape(T, N, K, p.m)
+    assert np.abs(gotu - h["u"]).max() <= 1e-11 * np.abs(h["u"]).max()

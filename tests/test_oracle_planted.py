@@ -107,6 +107,23 @@ def test_weight_of_the_wrong_node_is_caught(monkeypatch):
     assert cost(p, xb, ub) > cost(p, x, u) * (1 + 1e-6)
 
 
+def test_boundary_state_on_the_wrong_edge_is_caught(monkeypatch):
+    """Boundary states of the north edge fed through the south coupling (G
+    and H swapped in the boundary term of omega~) break the node-level
+    feasibility pin."""
+    p = make_problem(4, 3, 6, 2, 1, seed=5, boundary=True)
+    good = kkt.solve_kkt(p)
+    x, u = shapes(p, good)
+    assert np.abs(simulate(p, u) - x).max() < 1e-10
+    q = make_problem(4, 3, 6, 2, 1, seed=5, boundary=True)
+    q.alpha_lo, q.alpha_hi = p.alpha_hi, p.alpha_lo
+    real = stack.omega_hat
+    monkeypatch.setattr(stack, "omega_hat", lambda _p, t: real(q, t))
+    bad = kkt.solve_kkt(p)
+    xb, ub = shapes(p, bad)
+    assert np.abs(simulate(p, ub) - xb).max() > 1e-3
+
+
 # ------------------------------------------------------------ warm start
 def _fd_check_fails(monkeypatch_fn=None):
     """Runs the network finite-difference pin; returns True when it fails."""
