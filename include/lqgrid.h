@@ -29,7 +29,9 @@
  * Sign.     delta~ follows the Schur-complement convention of Sec. II-B:
  *           Q~ x~ = A~' delta~, R~ u~ = B~' delta~, Delta delta~ = r_delta.
  * Data.     Time-invariant A, B, Q, R (the paper allows time variation; this
- *           library does not yet).  Zero spatial boundary states.
+ *           library does not yet).  Spatial boundary states: zero, or given
+ *           per solve to lqgrid_pcg_solve_bc.  Per-node sizes: optional
+ *           (lqgrid_problem_desc n_node / m_node).
  * Errors.   Every call returns an lqgrid_status; none aborts.
  * Threads.  A context is not thread safe; distinct contexts are independent.
  */
@@ -42,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LQGRID_ABI_VERSION 1
+#define LQGRID_ABI_VERSION 2
 
 #if defined(__GNUC__) || defined(__clang__)
 #define LQGRID_API __attribute__((visibility("default")))
@@ -83,6 +85,17 @@ typedef struct {
   const double *Q;         /* [N][K][n][n] SPD stage weight, t = 0..T-1          */
   const double *R;         /* [N][K][m][m] SPD input weight                       */
   const double *QT;        /* [N][K][n][n] SPD terminal weight; NULL means QT = Q */
+  /* Heterogeneous sub-systems (Sec. II: x_{i,j} in R^{n_{i,j}}, u_{i,j} in
+   * R^{m_{i,j}}); NULL means n (m) at every node.  [N][K] int arrays with
+   * 1 <= n_node <= n, 1 <= m_node <= m.  The arrays above keep their padded
+   * shapes; only the leading n_{i,j} x n_{i,j} part of A_{i,j}, Q, QT, the
+   * leading n_{i,j} x n_q part of the block coupling neighbour q, the leading
+   * n_{i,j} x m_{i,j} part of B and m_{i,j} x m_{i,j} of R are read, and the
+   * other entries may hold anything.  Outputs keep the padded layouts with
+   * zeros past each node's sizes; x0 entries there are ignored.  A size
+   * outside its range makes lqgrid_factor return LQGRID_EINVAL.  (ABI 2.)  */
+  const int *n_node;
+  const int *m_node;
 } lqgrid_problem_desc;
 
 typedef struct {
@@ -148,9 +161,35 @@ LQGRID_API int lqgrid_pcg_solve(lqgrid_ctx *ctx, const double *x0,
                      const lqgrid_solve_opts *opts, const double *delta_init,
                      double *delta, double *x, double *u, lqgrid_info *info);
 
+/* Known spatial boundary states (Sec. II, eqs. "boundary_condition_i" and
+ * "boundary_condition_j"), DEVICE arrays over t = 0..T (entries at t = T do
+ * not enter the dynamics), each nullable (zero):
+ *   alpha_lo [T+1][N][n]  x_{0,j,t}    the row above the grid (coupled by G
+ *                                       of the nodes with i = 1)
+ *   alpha_hi [T+1][N][n]  x_{K+1,j,t}  the row below (H of i = K)
+ *   beta_lo  [T+1][K][n]  x_{i,0,t}    the column left of it (E of j = 1)
+ *   beta_hi  [T+1][K][n]  x_{i,N+1,t}  the column right of it (F of j = N)
+ * They enter only the right-hand side: r_delta at t+1 gets -(G alpha_lo +
+ * H alpha_hi + E beta_lo + F beta_hi) of time t for the nodes on the edges
+ * (the affine term omega_hat_t of Sec. II-A).  With per-node sizes the
+ * boundary states are padded to n and the coupling blocks' columns are used
+ * as given (zero-pad both past the boundary node's size). */
+typedef struct {
+  const double *alpha_lo, *alpha_hi, *beta_lo, *beta_hi;
+} lqgrid_boundary;
+
+/* lqgrid_pcg_solve with known boundary states (bc NULL: zero, which is
+ * lqgrid_pcg_solve). */
+LQGRID_API int lqgrid_pcg_solve_bc(lqgrid_ctx *ctx, const double *x0,
+                                   const lqgrid_boundary *bc,
+                                   const lqgrid_solve_opts *opts, const double *delta_init,
+                                   double *delta, double *x, double *u, lqgrid_info *info);
+
 /* Several independent problems solved together.  descs[p], x0s[p], deltas[p]
  * describe problem p (device pointers, layouts as above); all share n and
- * opts, while K, N, T and m may differ from problem to problem.  workspace
+ * opts, while K, N, T and m may differ from problem to problem.  Uniform
+ * sizes per problem (n_node / m_node non-null: EUNSUPPORTED) and zero
+ * boundary states.  workspace
  * sized by lqgrid_batch_workspace_bytes.  infos[p] receives problem p's
  * result.  Synchronises the stream before returning.  Device memory: none
  * is allocated (everything lives in the workspace), but each call creates one
@@ -268,6 +307,41 @@ LQGRID_API int lqgrid_wsnet_predict(const lqgrid_wsnet_desc *desc, const void *f
                                     const float *params, double *delta_init,
                                     void *workspace, size_t workspace_bytes,
                                     void *hip_stream);
+
+/* Standalone NBJM solver (the paper's comparison method, Sec. IV eq.
+ * "outer_jacobi_iterations" with opts->inner_L inner sweeps of eq.
+ * "inner_iteration_NBJM", Algorithm 2 run to convergence): from delta = 0,
+ *   rho = r_delta + Xi~ delta^(s),  theta^(0) = delta^(s),
+ *   theta^(l+1) = Phi~^-1 (rho + Omega~ theta^(l)),  delta^(s+1) = theta^(L).
+ * Each inner iteration starts from the outer iterate (with theta^(0) = 0, as
+ * in the preconditioner, the iteration would converge to another point for
+ * finite L).  Stops when the FP64 relative residual ||r_delta - Delta
+ * delta||_2 / ||r_delta||_2 <= opts->tol, tested every opts->check_every
+ * sweeps (1: every sweep); opts->max_iter caps the sweeps (ENOCONV).
+ * info->iterations = outer sweeps.  FP64 only (FP32_REFINE: EUNSUPPORTED).
+ * Outputs as lqgrid_pcg_solve (x, u optional).  Requires lqgrid_factor.
+ * Synchronises the stream. */
+LQGRID_API int lqgrid_nbjm_solve(lqgrid_ctx *ctx, const double *x0,
+                                 const lqgrid_solve_opts *opts, double *delta,
+                                 double *x, double *u, lqgrid_info *info);
+
+/* Spectrum of the (preconditioned) Schur complement from the coefficients of
+ * Algorithm 1 (Sec. III: the CG rate is set by the condition number; Sec. V
+ * compares kappa(Delta) with kappa(P_S^-1/2 Delta P_S^-1/2)).  Runs one FP64
+ * Algorithm 1 from zero on Delta delta = r_delta(x0) to the relative
+ * tolerance tol (at most max_iter <= 8192 iterations; <= 0: 8192) with the
+ * S x L NBJM preconditioner (preconditioned != 0) or P = I (plain CG), and
+ * returns the extreme eigenvalues of the Lanczos matrix built from its step
+ * lengths theta_k and direction coefficients beta_k (diagonal 1/theta_k +
+ * beta_{k-1}/theta_{k-1}, off-diagonal sqrt(beta_k)/theta_k), which converge
+ * to those of P^-1 Delta from inside its spectrum; kappa = lambda_max /
+ * lambda_min.  Output pointers are host memory and may be NULL.  Requires
+ * lqgrid_factor; synchronises the stream.  Errors: EINVAL, EBREAKDOWN, EHIP. */
+LQGRID_API int lqgrid_condition_estimate(lqgrid_ctx *ctx, const double *x0,
+                                         int preconditioned, int outer_S, int inner_L,
+                                         double tol, int max_iter, double *kappa,
+                                         double *lambda_min, double *lambda_max,
+                                         int *iterations);
 
 /* ------------------------------------------------------------------------
  * Allocation-free solve, for callers that cannot allocate device memory

@@ -40,10 +40,14 @@ struct Plan {
   size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Fw, Bw, Xw;
   size_t G13f, Cdnf, Cupf, Qif, QTdf, Qmf, Fwf, Bwf, Xwf;
   size_t outer[kNumOuter], p64[kNumPcg], p32[kNumPcg];
-  size_t psum, pmax, scal, scal_outer;
+  size_t psum, pmax, scal, scal_outer, hist;
+  size_t inA, inAnbr, inB, inQ, inQT, inR, nsz;  // ingested (size-masked) arrays
   int npartial;
   size_t total;
 };
+
+// PCG iterations whose coefficients lqgrid_condition_estimate can record.
+constexpr int kHistCap = 8192;
 
 Plan make_plan(const Dims& D) {
   Plan P{};
@@ -59,6 +63,15 @@ Plan make_plan(const Dims& D) {
   const size_t xw = (size_t)2 * D.V * NB * kFwRow;
   P.scal = take(sizeof(Scalars));
   P.scal_outer = take(sizeof(Scalars));
+  P.hist = take((size_t)kHistCap * 2 * sizeof(double));
+  const size_t rn = (size_t)D.real_nodes;
+  P.inA = take(rn * nn * 8);
+  P.inAnbr = take(rn * 4 * nn * 8);
+  P.inB = take(rn * D.n * D.m * 8);
+  P.inQ = take(rn * nn * 8);
+  P.inQT = take(rn * nn * 8);
+  P.inR = take(rn * D.m * D.m * 8);
+  P.nsz = take(rn * sizeof(int));
   P.G13 = take(nodes * 13 * nn * 8);
   P.Cdn = take(nodes * 5 * nn * 8);
   P.Cup = take(nodes * 5 * nn * 8);
@@ -114,6 +127,11 @@ struct lqgrid_ctx {
   double *psum, *pmax;
   bool factored = false;
   bool qt_distinct = false;
+  bool precond_identity = false;  // P = I in Algorithm 1 (plain CG)
+  bool sized = false;     // per-node sizes given: x0 is masked by nsz
+  bool rd_dirty = false;  // r_delta holds boundary terms of an earlier solve
+  const int* nsz = nullptr;       // per-node state sizes (workspace copy)
+  const double* Anbr = nullptr;   // ingested coupling blocks (boundary terms)
   int host_iter[2];   // staging for resetting the device iteration counters
   // profiling
   bool prof = false;
@@ -316,7 +334,8 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
   c->host_iter[1] = max_iter;
   HIPCHECK(hipMemcpyAsync(&sc->iter, c->host_iter, 2 * sizeof(int),
                           hipMemcpyHostToDevice, s));
-  T* q = precondition<T>(c, r, S, L, 0);
+  // P = I (plain CG): q aliases r, every read of q sees the current residual
+  T* q = c->precond_identity ? r : precondition<T>(c, r, S, L, 0);
   np = vec_dot<T>(D, q, r, c->psum, sc, 0, s);
   scalar_step(kModeMuInit, c->psum, nullptr, np, sc, 0.0, s);
   vec_zero<T>(d, D.vlen, s);
@@ -335,7 +354,7 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
         np = vec_update<T>(D, d, y, x, r, c->psum, sc, s);
       }
       scalar_step(kModeRr, c->psum, nullptr, np, sc, 0.0, s);
-      q = precondition<T>(c, r, S, L, 1);
+      if (!c->precond_identity) q = precondition<T>(c, r, S, L, 1);
       np = vec_dot<T>(D, q, r, c->psum, sc, 1, s);
       scalar_step(kModeMu, c->psum, nullptr, np, sc, 0.0, s);
     }
@@ -352,11 +371,24 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
   return LQGRID_OK;
 }
 
+// r_delta of a solve: -gamma at t = 0 (padding masked with per-node sizes)
+// and the boundary terms at t >= 1 (cleared when an earlier solve left some).
+void rhs_of(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc) {
+  launch_rhs_init(c->D, x0, c->outer[kRd], c->stream, c->sized ? c->nsz : nullptr);
+  const bool any = bc && (bc->alpha_lo || bc->alpha_hi || bc->beta_lo || bc->beta_hi);
+  if (any || c->rd_dirty) {
+    Boundary b{any ? bc->alpha_lo : nullptr, any ? bc->alpha_hi : nullptr,
+               any ? bc->beta_lo : nullptr, any ? bc->beta_hi : nullptr};
+    launch_rhs_boundary(c->D, c->Anbr, b, c->outer[kRd], c->stream);
+  }
+  c->rd_dirty = any;
+}
+
 // r = r_delta - Delta dl (FP64), true residual norms into the outer scalars.
-void true_residual(lqgrid_ctx* c) {
+void true_residual(lqgrid_ctx* c, const double* dl = nullptr) {
   const Dims& D = c->D;
-  delta_apply<double>(D, c->op64, c->outer[kDl], c->outer[kYt], nullptr, c->sco,
-                      0, c->stream);
+  delta_apply<double>(D, c->op64, dl ? dl : c->outer[kDl], c->outer[kYt], nullptr,
+                      c->sco, 0, c->stream);
   const int np = vec_sub_norm(D, c->outer[kRd], c->outer[kYt], c->outer[kRt],
                               c->psum, c->pmax, c->stream);
   scalar_step(kModeTrue, c->psum, c->pmax, np, c->sco, 0.0, c->stream);
@@ -428,6 +460,37 @@ int scratch_of_current_device(void** out) {
   return LQGRID_OK;
 }
 
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal a and off-diagonal b (Sturm sequence of the LDL' pivots).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t k = 0; k < a.size(); ++k) {
+    const double off = k ? b[k - 1] * b[k - 1] : 0.0;
+    q = a[k] - x - (k ? off / q : 0.0);
+    if (q == 0.0) q = -1e-300;  // a zero pivot counts as negative
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// The k-th smallest eigenvalue (k = 0 .. size-1) by bisection inside the
+// Gershgorin interval, to a relative width of 1e-14.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k) {
+  double lo = a[0], hi = a[0];
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-14 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(a, b, mid) > k) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 // Argument checks shared by lqgrid_setup and lqgrid_solve_noalloc.
 int check_problem(const lqgrid_problem_desc* desc, Dims* D) {
   if (!make_dims(desc, D)) return LQGRID_EINVAL;
@@ -477,8 +540,18 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
     vec_zero<double>(c->b64.v[v], D.vlen, c->stream);
     vec_zero<float>(c->b32.v[v], D.vlen, c->stream);
   }
-  ProblemIn in{D.K, D.N, D.n, D.m, desc->A, desc->A_nbr, desc->B,
-               desc->Q, desc->R, desc->QT};
+  // ingest: copies of the problem arrays, padded where a node is smaller than
+  // n, m (a plain copy for uniform sizes); the setup reads only the copies,
+  // and the coupling blocks stay for the boundary terms of later solves
+  ProblemIn user{D.K, D.N, D.n, D.m, desc->A, desc->A_nbr, desc->B,
+                 desc->Q, desc->R, desc->QT};
+  ProblemIn in{D.K, D.N, D.n, D.m, dp(P.inA), dp(P.inAnbr), dp(P.inB),
+               dp(P.inQ), dp(P.inR), dp(P.inQT)};
+  int* nsz = reinterpret_cast<int*>(w + P.nsz);
+  launch_ingest(D, user, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
+  c->sized = desc->n_node != nullptr;
+  c->nsz = nsz;
+  c->Anbr = in.A_nbr;
   launch_setup(D, in, c->C, c->sc, c->stream);
   make_f32_blocks(c, false);
   const hipError_t e = hipGetLastError();
@@ -560,6 +633,7 @@ int lqgrid_factor(lqgrid_ctx* c) {
   int st = read_scalars(c, c->sc, &h);
   if (st != LQGRID_OK) return st;
   c->qt_distinct = h.qt_differs != 0;
+  if (h.flag_badsize) return LQGRID_EINVAL;
   if (h.flag_notspd) return LQGRID_ENOTSPD;
   c->factored = true;
   return LQGRID_OK;
@@ -570,7 +644,7 @@ namespace {
 // The body of lqgrid_pcg_solve.  With timed_events the device time comes from
 // two HIP events around the solve; without (the allocation-free entry point)
 // from the host clock around the synchronised solve.
-int pcg_solve_impl(lqgrid_ctx* c, const double* x0,
+int pcg_solve_impl(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc,
                    const lqgrid_solve_opts* opts_in, const double* delta_init,
                    double* delta, double* x, double* u, lqgrid_info* info,
                    bool timed_events) {
@@ -598,7 +672,7 @@ int pcg_solve_impl(lqgrid_ctx* c, const double* x0,
   }
 
   // r_delta, ||r_delta||, tol^2 ||r_delta||^2 (outer scalars)
-  launch_rhs_init(D, x0, c->outer[kRd], s);
+  rhs_of(c, x0, bc);
   int np = vec_norms<double>(D, c->outer[kRd], c->psum, c->pmax, s);
   scalar_step(kModeRd2, c->psum, c->pmax, np, c->sco, o.tol, s);
   if (delta_init) to_internal(D, delta_init, c->outer[kDl], s);
@@ -678,7 +752,13 @@ int pcg_solve_impl(lqgrid_ctx* c, const double* x0,
 int lqgrid_pcg_solve(lqgrid_ctx* c, const double* x0,
                      const lqgrid_solve_opts* opts_in, const double* delta_init,
                      double* delta, double* x, double* u, lqgrid_info* info) {
-  return pcg_solve_impl(c, x0, opts_in, delta_init, delta, x, u, info, true);
+  return pcg_solve_impl(c, x0, nullptr, opts_in, delta_init, delta, x, u, info, true);
+}
+
+int lqgrid_pcg_solve_bc(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc,
+                        const lqgrid_solve_opts* opts_in, const double* delta_init,
+                        double* delta, double* x, double* u, lqgrid_info* info) {
+  return pcg_solve_impl(c, x0, bc, opts_in, delta_init, delta, x, u, info, true);
 }
 
 int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
@@ -750,6 +830,130 @@ int lqgrid_profile_read(lqgrid_ctx* c, int kernel, long long* launches,
   return LQGRID_OK;
 }
 
+int lqgrid_nbjm_solve(lqgrid_ctx* c, const double* x0, const lqgrid_solve_opts* opts_in,
+                      double* delta, double* x, double* u, lqgrid_info* info) {
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!c || !x0 || !delta) return LQGRID_EINVAL;
+  lqgrid_solve_opts o;
+  opts_fill(opts_in, &o);
+  if (!opts_valid(o) || !c->factored) return LQGRID_EINVAL;
+  if (o.precision != LQGRID_FP64) return LQGRID_EUNSUPPORTED;
+  const Dims& D = c->D;
+  hipStream_t s = c->stream;
+  clear_stale_error();
+  const auto h0 = std::chrono::steady_clock::now();
+  double* rd = c->outer[kRd];
+  rhs_of(c, x0, nullptr);
+  int np = vec_norms<double>(D, rd, c->psum, c->pmax, s);
+  scalar_step(kModeRd2, c->psum, c->pmax, np, c->sco, o.tol, s);
+  double* dcur = c->b64.v[kX];
+  double* dnext = c->b64.v[kD];
+  double* rho = c->b64.v[kBufA];
+  double* tau = c->b64.v[kBufB];
+  vec_zero<double>(dcur, D.vlen, s);
+  const OpCoef<double>& C = c->op64;
+  const int qtd = c->qt_distinct ? 1 : 0;
+  int sweeps = 0, status = LQGRID_OK;
+  Scalars h{};
+  for (;;) {
+    // delta^(s+1): rho = r_delta + Xi~ delta^(s); the inner iteration starts
+    // from theta^(0) = delta^(s), theta^(l+1) = Phi~^-1 (rho + Omega~ theta^(l))
+    xi_rhs<double>(D, C, rd, dcur, rho, c->sc, 0, s);
+    const double* th = dcur;
+    for (int l = 0; l < o.inner_L; ++l) {
+      omega_rhs<double>(D, C, rho, th, tau, c->sc, 0, s);
+      phi_solve<double>(D, C, tau, dnext, c->sc, 0, qtd, s);
+      th = dnext;
+    }
+    std::swap(dcur, dnext);
+    ++sweeps;
+    if (sweeps % o.check_every == 0 || sweeps >= o.max_iter) {
+      true_residual(c, dcur);
+      HIPCHECK(hipGetLastError());
+      const int st = read_scalars(c, c->sco, &h);
+      if (st != LQGRID_OK) return st;
+      if (!std::isfinite(h.rr)) {
+        status = LQGRID_EBREAKDOWN;
+        break;
+      }
+      if (h.rr <= h.tol2) break;
+      if (sweeps >= o.max_iter) {
+        status = LQGRID_ENOCONV;
+        break;
+      }
+    }
+  }
+  to_abi(D, dcur, delta, s);
+  if (x || u) recover(D, c->C, dcur, x, u, s);
+  HIPCHECK(hipStreamSynchronize(s));
+  HIPCHECK(hipGetLastError());
+  if (info) {
+    info->status = status;
+    info->iterations = sweeps;
+    info->rel_kkt_residual = h.rd2 > 0 ? std::sqrt(h.rr / h.rd2) : 0.0;
+    info->rel_res_inf = h.rdinf > 0 ? h.rinf / h.rdinf : 0.0;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - h0).count();
+  }
+  return status;
+}
+
+int lqgrid_condition_estimate(lqgrid_ctx* c, const double* x0, int preconditioned,
+                              int outer_S, int inner_L, double tol, int max_iter,
+                              double* kappa, double* lambda_min, double* lambda_max,
+                              int* iterations) {
+  if (!c || !x0 || !c->factored) return LQGRID_EINVAL;
+  lqgrid_solve_opts o;
+  opts_fill(nullptr, &o);
+  o.outer_S = outer_S;
+  o.inner_L = inner_L;
+  o.tol = tol;
+  o.max_iter = max_iter > 0 ? max_iter : kHistCap;
+  if (!opts_valid(o) || o.max_iter > kHistCap) return LQGRID_EINVAL;
+  const Dims& D = c->D;
+  hipStream_t s = c->stream;
+  clear_stale_error();
+  rhs_of(c, x0, nullptr);
+  int np = vec_norms<double>(D, c->outer[kRd], c->psum, c->pmax, s);
+  scalar_step(kModeRd2, c->psum, c->pmax, np, c->sco, o.tol, s);
+  vec_zero<double>(c->outer[kDl], D.vlen, s);
+  true_residual(c);
+  Scalars h{};
+  int st = read_scalars(c, c->sco, &h);
+  if (st != LQGRID_OK) return st;
+  if (!(h.rr > 0.0) || !std::isfinite(h.rr)) return LQGRID_EBREAKDOWN;
+  // record the coefficients of this one FP64 run of Algorithm 1 from zero
+  struct { double* p; int cap; } stage{reinterpret_cast<double*>(c->ws + c->P.hist), kHistCap};
+  HIPCHECK(hipMemcpyAsync(&c->sc->hist, &stage, sizeof(double*) + sizeof(int),
+                          hipMemcpyHostToDevice, s));
+  c->precond_identity = preconditioned == 0;
+  int it = 0, done = kRunning;
+  st = refine_pass<double>(c, std::sqrt(h.rr), o.tol, o.max_iter, o, &it, &done);
+  c->precond_identity = false;
+  const decltype(stage) none{nullptr, 0};
+  HIPCHECK(hipMemcpyAsync(&c->sc->hist, &none, sizeof(double*) + sizeof(int),
+                          hipMemcpyHostToDevice, s));
+  if (st != LQGRID_OK) return st;
+  if (it < 1) return LQGRID_EBREAKDOWN;
+  std::vector<double> coef(2 * (size_t)it);
+  HIPCHECK(hipMemcpyAsync(coef.data(), c->ws + c->P.hist, coef.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  // Lanczos matrix of P^-1 Delta from the CG coefficients (Sec. III): diag
+  // 1/theta_k + beta_{k-1}/theta_{k-1}, off-diagonal sqrt(beta_k)/theta_k
+  std::vector<double> a(it), b(it > 1 ? it - 1 : 0);
+  for (int k = 0; k < it; ++k) {
+    const double th = coef[2 * k];
+    a[k] = 1.0 / th + (k ? coef[2 * (k - 1) + 1] / coef[2 * (k - 1)] : 0.0);
+    if (k + 1 < it) b[k] = std::sqrt(coef[2 * k + 1]) / th;
+  }
+  const double lo = tridiag_eig(a, b, 0), hi = tridiag_eig(a, b, it - 1);
+  if (lambda_min) *lambda_min = lo;
+  if (lambda_max) *lambda_max = hi;
+  if (kappa) *kappa = hi / lo;
+  if (iterations) *iterations = it;
+  return done == kBreakdown ? LQGRID_EBREAKDOWN : LQGRID_OK;
+}
+
 size_t lqgrid_noalloc_capacity(void) { return kNoAllocBytes; }
 
 int lqgrid_solve_noalloc(const lqgrid_problem_desc* desc, const double* x0,
@@ -775,7 +979,7 @@ int lqgrid_solve_noalloc(const lqgrid_problem_desc* desc, const double* x0,
   if (r != LQGRID_OK) return r;
   r = lqgrid_factor(&c);
   if (r != LQGRID_OK) return r;
-  return pcg_solve_impl(&c, x0, opts, nullptr, delta, x, u, info, false);
+  return pcg_solve_impl(&c, x0, nullptr, opts, nullptr, delta, x, u, info, false);
 }
 
 void lqgrid_destroy(lqgrid_ctx* c) { delete c; }

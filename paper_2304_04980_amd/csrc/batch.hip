@@ -349,7 +349,7 @@ __global__ void kb_rhs_init(BatchDev B) {
     const Item w = u[it];
     const BatchProb& P = B.probs[w.prob];
     const int q = w.a + threadIdx.x;
-    if (q < w.b) rhs_init(P.D, P.x0, P.v[kBRd], q);
+    if (q < w.b) rhs_init(P.D, P.x0, nullptr, P.v[kBRd], q);
   }
 }
 // delta~ of each problem from the internal to the interface layout

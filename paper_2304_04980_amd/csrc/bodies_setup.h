@@ -599,10 +599,111 @@ __device__ inline void factor_twisted(const Dims& D, const Coef& C, Scalars* sc,
 
 // r_delta = col(-gamma_hat, 0, ..., 0) in the internal layout, entry g =
 // p n + c (the vector is zeroed beforehand).
+// r_delta at t = 0: -gamma (Sec. II-A, reading of omega~); components past
+// a node's state size (nsz, nullable) are padding and read as zero.
 __device__ inline void rhs_init(const Dims& D, const double* __restrict__ x0,
-                                double* __restrict__ rd, int g) {
+                                const int* __restrict__ nsz, double* __restrict__ rd,
+                                int g) {
   if (g >= D.real_nodes * D.n) return;
-  rd[(size_t)g * D.ldt] = -x0[g];  // g = p*n + c in both layouts
+  const int p = g / D.n, c = g % D.n;
+  const bool real = !nsz || c < nsz[p];
+  rd[(size_t)g * D.ldt] = real ? -x0[g] : 0.0;  // g = p*n + c in both layouts
+}
+
+// Known spatial boundary states (Sec. II, eqs. "boundary_condition_i/j")
+// enter the dynamics of the nodes next to the grid's edges as the affine term
+// omega_hat_t = M_hat alpha_hat_t + N_hat beta_hat_t, so r_delta at t + 1
+// holds -(G x_{0,j,t} + H x_{K+1,j,t} + E x_{i,0,t} + F x_{i,N+1,t}) for the
+// couplings of node (i, j) that point outside the grid.  Work unit g = p T + t
+// (real node p, t = 0..T-1) writes r_delta(p, ., t + 1); nodes away from the
+// edges (and null state arrays) give zero, so the call also clears the
+// entries of an earlier solve.  Anbr holds the node's four coupling blocks
+// (rows past its state size already zero).
+__device__ inline void rhs_boundary(const Dims& D, const double* __restrict__ Anbr,
+                                    const double* __restrict__ alo,
+                                    const double* __restrict__ ahi,
+                                    const double* __restrict__ blo,
+                                    const double* __restrict__ bhi,
+                                    double* __restrict__ rd, long long g) {
+  if (g >= (long long)D.real_nodes * D.T) return;
+  const int p = (int)(g / D.T), t = (int)(g % D.T);
+  const int n = D.n, K = D.K, N = D.N;
+  const int i = p % K, j = p / K;
+  double w[kMaxN];
+  for (int c = 0; c < n; ++c) w[c] = 0.0;
+  // slot 0: E (x_{i,j-1}), 1: F (x_{i,j+1}), 2: G (x_{i-1,j}), 3: H (x_{i+1,j})
+  const double* st[4] = {j == 0 && blo ? blo + ((size_t)t * K + i) * n : nullptr,
+                         j == N - 1 && bhi ? bhi + ((size_t)t * K + i) * n : nullptr,
+                         i == 0 && alo ? alo + ((size_t)t * N + j) * n : nullptr,
+                         i == K - 1 && ahi ? ahi + ((size_t)t * N + j) * n : nullptr};
+  for (int k = 0; k < 4; ++k) {
+    if (!st[k]) continue;
+    const double* M = Anbr + ((size_t)p * 4 + k) * n * n;
+    for (int a = 0; a < n; ++a)
+      for (int c = 0; c < n; ++c) w[a] += M[a * n + c] * st[k][c];
+  }
+  for (int c = 0; c < n; ++c) rd[((size_t)p * n + c) * D.ldt + t + 1] = -w[c];
+}
+
+// Ingest with per-node sizes (Sec. II: x_{i,j} in R^{n_{i,j}}, u_{i,j} in
+// R^{m_{i,j}}): every node is padded to n, m with decoupled components --
+// rows and columns past its sizes of A, of its coupling blocks (columns past
+// the neighbour's size) and of B are zero, Q, Q_T and R are the identity
+// there.  A padded state then starts at zero, is driven by nothing and
+// drives nothing, and costs nothing; a padded input acts on nothing and is
+// zero at the optimum; the multipliers of padded rows are zero.  The copies
+// (user layouts) replace the caller's arrays for the rest of the setup.
+// nsz / msz may be null (uniform sizes: a plain copy).  One thread per real
+// node; a size outside 1..n (1..m) raises flag_badsize.
+__device__ inline void ingest_mask(const Dims& D, const ProblemIn P, const int* nsz_in,
+                                   const int* msz_in, ProblemIn out, int* nsz_out,
+                                   Scalars* sc, int p) {
+  if (p >= D.real_nodes) return;
+  const int n = D.n, m = D.m, K = D.K, N = D.N;
+  const int i = p % K, j = p / K;
+  int np_ = nsz_in ? nsz_in[p] : n, mp = msz_in ? msz_in[p] : m;
+  if (np_ < 1 || np_ > n || mp < 1 || mp > m) {
+    atomicOr(&sc->flag_badsize, 1);
+    np_ = n;
+    mp = m;
+  }
+  nsz_out[p] = np_;
+  const size_t nn = (size_t)n * n;
+  double* A = const_cast<double*>(out.A) + p * nn;
+  const double* As = P.A + p * nn;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) A[a * n + b] = (a < np_ && b < np_) ? As[a * n + b] : 0.0;
+  const int ni[4] = {i, i, i - 1, i + 1}, nj[4] = {j - 1, j + 1, j, j};
+  for (int k = 0; k < 4; ++k) {
+    const bool in_grid = ni[k] >= 0 && ni[k] < K && nj[k] >= 0 && nj[k] < N;
+    int nq = n;
+    if (in_grid && nsz_in) {
+      nq = nsz_in[nj[k] * K + ni[k]];
+      nq = (nq < 1 || nq > n) ? n : nq;
+    }
+    double* E = const_cast<double*>(out.A_nbr) + ((size_t)p * 4 + k) * nn;
+    const double* Es = P.A_nbr + ((size_t)p * 4 + k) * nn;
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) E[a * n + b] = (a < np_ && b < nq) ? Es[a * n + b] : 0.0;
+  }
+  double* B = const_cast<double*>(out.B) + (size_t)p * n * m;
+  const double* Bs = P.B + (size_t)p * n * m;
+  for (int a = 0; a < n; ++a)
+    for (int c = 0; c < m; ++c) B[a * m + c] = (a < np_ && c < mp) ? Bs[a * m + c] : 0.0;
+  const double* QTs = P.QT ? P.QT : P.Q;
+  double* Q = const_cast<double*>(out.Q) + p * nn;
+  double* QT = const_cast<double*>(out.QT) + p * nn;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const bool in = a < np_ && b < np_;
+      Q[a * n + b] = in ? P.Q[p * nn + a * n + b] : (a == b ? 1.0 : 0.0);
+      QT[a * n + b] = in ? QTs[p * nn + a * n + b] : (a == b ? 1.0 : 0.0);
+    }
+  double* R = const_cast<double*>(out.R) + (size_t)p * m * m;
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      R[a * m + b] = (a < mp && b < mp) ? P.R[(size_t)p * m * m + a * m + b]
+                                        : (a == b ? 1.0 : 0.0);
 }
 
 }  // namespace dev

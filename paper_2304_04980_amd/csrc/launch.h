@@ -15,7 +15,17 @@ void launch_setup(const Dims& D, const ProblemIn& P, const Coef& C,
                   Scalars* sc, hipStream_t s);
 void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s);
 void launch_rhs_init(const Dims& D, const double* x0, double* rd,
-                     hipStream_t s);
+                     hipStream_t s, const int* nsz = nullptr);
+// Known spatial boundary states ([T+1][N][n] for the rows above / below the
+// grid, [T+1][K][n] for the columns left / right of it; null: zero).
+struct Boundary {
+  const double *alo, *ahi, *blo, *bhi;
+};
+void launch_rhs_boundary(const Dims& D, const double* Anbr, const Boundary& bc,
+                         double* rd, hipStream_t s);
+// Per-node sizes: padded copies of the problem arrays (see ingest_mask).
+void launch_ingest(const Dims& D, const ProblemIn& P, const int* nsz, const int* msz,
+                   const ProblemIn& out, int* nsz_out, Scalars* sc, hipStream_t s);
 
 // ops.hip (T = double or float).  delta_apply returns the number of partial
 // sums it wrote.  check_done != 0 makes the kernels return at once when the
@@ -95,8 +105,12 @@ __device__ inline void scalar_apply(int mode, double s, double m, Scalars* sc,
     }
     case kModeYd:
       sc->yd = s;
-      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->mu)) sc->done = kBreakdown;
-      else sc->theta = sc->mu / s;
+      if (!(s > 0.0) || !isfinite(s) || !isfinite(sc->mu)) {
+        sc->done = kBreakdown;
+      } else {
+        sc->theta = sc->mu / s;
+        if (sc->hist && sc->iter < sc->hist_cap) sc->hist[2 * sc->iter] = sc->theta;
+      }
       break;
     case kModeRr:
       sc->rr = s;
@@ -111,6 +125,9 @@ __device__ inline void scalar_apply(int mode, double s, double m, Scalars* sc,
       } else {
         sc->beta = s / sc->mu;
         sc->mu = s;
+        // iteration iter - 1 was counted by kModeRr
+        if (sc->hist && sc->iter >= 1 && sc->iter - 1 < sc->hist_cap)
+          sc->hist[2 * (sc->iter - 1) + 1] = sc->beta;
       }
       break;
     case kModeMuInit:

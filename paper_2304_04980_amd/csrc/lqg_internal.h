@@ -106,7 +106,11 @@ struct Scalars {
   int flag_notspd; // factor pivot failure
   int qt_differs;  // QT != Q somewhere
   int active;      // batched form: the problem takes part in the current phase
-  int pad[2];
+  int flag_badsize;// a per-node state or input size outside 1..n / 1..m
+  int pad;
+  double* hist;    // non-null: record theta_k at [2k] and beta_k at [2k+1]
+  int hist_cap;    // iterations the history holds
+  int pad2;
 };
 
 enum Done { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIter = 3 };

@@ -22,8 +22,17 @@ __global__ __launch_bounds__(128) void k_factor_twisted(Dims D, Coef C, Scalars*
   factor_twisted(D, C, sc, blockIdx.x, blockIdx.y);
 }
 __global__ void k_rhs_init(Dims D, const double* __restrict__ x0,
-                           double* __restrict__ rd) {
-  rhs_init(D, x0, rd, blockIdx.x * blockDim.x + threadIdx.x);
+                           const int* __restrict__ nsz, double* __restrict__ rd) {
+  rhs_init(D, x0, nsz, rd, blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void k_rhs_boundary(Dims D, const double* __restrict__ Anbr, Boundary bc,
+                               double* __restrict__ rd) {
+  rhs_boundary(D, Anbr, bc.alo, bc.ahi, bc.blo, bc.bhi, rd,
+               (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void k_ingest_mask(Dims D, ProblemIn P, const int* nsz, const int* msz,
+                              ProblemIn out, int* nsz_out, Scalars* sc) {
+  ingest_mask(D, P, nsz, msz, out, nsz_out, sc, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace
@@ -51,10 +60,23 @@ void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s) {
 }
 
 void launch_rhs_init(const Dims& D, const double* x0, double* rd,
-                     hipStream_t s) {
+                     hipStream_t s, const int* nsz) {
   const int work = D.real_nodes * D.n;
   hipLaunchKernelGGL(k_rhs_init, dim3((work + 255) / 256), dim3(256), 0, s, D,
-                     x0, rd);
+                     x0, nsz, rd);
+}
+
+void launch_rhs_boundary(const Dims& D, const double* Anbr, const Boundary& bc,
+                         double* rd, hipStream_t s) {
+  const long long work = (long long)D.real_nodes * D.T;
+  hipLaunchKernelGGL(k_rhs_boundary, dim3((unsigned)((work + 255) / 256)), dim3(256), 0,
+                     s, D, Anbr, bc, rd);
+}
+
+void launch_ingest(const Dims& D, const ProblemIn& P, const int* nsz, const int* msz,
+                   const ProblemIn& out, int* nsz_out, Scalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_ingest_mask, dim3((D.real_nodes + 127) / 128), dim3(128), 0, s, D,
+                     P, nsz, msz, out, nsz_out, sc);
 }
 
 }  // namespace lqg

@@ -25,7 +25,12 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("K", c_int), ("N", c_int), ("T", c_int), ("n", c_int),
                 ("m", c_int), ("A", c_void_p), ("A_nbr", c_void_p),
                 ("B", c_void_p), ("Q", c_void_p), ("R", c_void_p),
-                ("QT", c_void_p)]
+                ("QT", c_void_p), ("n_node", c_void_p), ("m_node", c_void_p)]
+
+
+class Boundary(ctypes.Structure):
+    _fields_ = [("alpha_lo", c_void_p), ("alpha_hi", c_void_p),
+                ("beta_lo", c_void_p), ("beta_hi", c_void_p)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -81,6 +86,10 @@ def load(path: str = LIB_PATH):
                                    c_void_p, c_void_p, c_void_p, c_void_p,
                                    POINTER(Info)]
     L.lqgrid_pcg_solve.restype = c_int
+    L.lqgrid_pcg_solve_bc.argtypes = [c_void_p, c_void_p, POINTER(Boundary),
+                                      POINTER(SolveOpts), c_void_p, c_void_p, c_void_p,
+                                      c_void_p, POINTER(Info)]
+    L.lqgrid_pcg_solve_bc.restype = c_int
     L.lqgrid_batch_workspace_bytes.argtypes = [c_int, POINTER(ProblemDesc),
                                                POINTER(SolveOpts)]
     L.lqgrid_batch_workspace_bytes.restype = c_size_t
@@ -131,6 +140,14 @@ def load(path: str = LIB_PATH):
     L.lqgrid_wsnet_predict.argtypes = [W, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_size_t, c_void_p]
     L.lqgrid_wsnet_predict.restype = c_int
+    L.lqgrid_nbjm_solve.argtypes = [c_void_p, c_void_p, POINTER(SolveOpts), c_void_p,
+                                    c_void_p, c_void_p, POINTER(Info)]
+    L.lqgrid_nbjm_solve.restype = c_int
+    L.lqgrid_condition_estimate.argtypes = [c_void_p, c_void_p, c_int, c_int, c_int,
+                                            c_double, c_int, POINTER(c_double),
+                                            POINTER(c_double), POINTER(c_double),
+                                            POINTER(c_int)]
+    L.lqgrid_condition_estimate.restype = c_int
     L.lqgrid_noalloc_capacity.argtypes = []
     L.lqgrid_noalloc_capacity.restype = c_size_t
     L.lqgrid_solve_noalloc.argtypes = [POINTER(ProblemDesc), c_void_p, POINTER(SolveOpts),
@@ -150,7 +167,8 @@ EXPORTED = ["lqgrid_default_opts", "lqgrid_workspace_bytes", "lqgrid_setup",
             "lqgrid_wsnet_workspace_bytes", "lqgrid_wsnet_features",
             "lqgrid_wsnet_targets", "lqgrid_wsnet_forward", "lqgrid_wsnet_gradient",
             "lqgrid_wsnet_adam", "lqgrid_wsnet_predict", "lqgrid_noalloc_capacity",
-            "lqgrid_solve_noalloc"]
+            "lqgrid_solve_noalloc", "lqgrid_nbjm_solve", "lqgrid_condition_estimate",
+            "lqgrid_pcg_solve_bc"]
 
 
 class LqgridError(RuntimeError):
@@ -185,11 +203,12 @@ def workspace_bytes(K, N, T, n, m) -> int:
     return load().lqgrid_workspace_bytes(byref(d), None)
 
 
-def problem_desc(K, N, T, n, m, A, A_nbr, B, Q, R, QT=None) -> ProblemDesc:
-    """Tensors must be contiguous float64 CUDA tensors in the header's
-    layouts; the caller keeps them alive while the setup work runs."""
+def problem_desc(K, N, T, n, m, A, A_nbr, B, Q, R, QT=None, n_node=None,
+                 m_node=None) -> ProblemDesc:
+    """Tensors must be contiguous float64 (sizes: int32) CUDA tensors in the
+    header's layouts; the caller keeps them alive while the setup work runs."""
     return ProblemDesc(K, N, T, n, m, _ptr(A), _ptr(A_nbr), _ptr(B), _ptr(Q),
-                       _ptr(R), _ptr(QT))
+                       _ptr(R), _ptr(QT), _ptr(n_node), _ptr(m_node))
 
 
 class Context:
@@ -209,10 +228,15 @@ class Context:
         if arrays is None:
             arrays = {k: torch.as_tensor(getattr(p, k)).to(**f64).contiguous()
                       for k in ("A", "A_nbr", "B", "Q", "R", "QT")}
+            for k in ("n_node", "m_node"):
+                v = getattr(p, k, None)
+                if v is not None:
+                    arrays[k] = torch.as_tensor(v).to(dtype=torch.int32,
+                                                      device=device).contiguous()
         self.arrays = arrays
         a = self.arrays
         self.desc = problem_desc(*self.dims, a["A"], a["A_nbr"], a["B"], a["Q"],
-                                 a["R"], a["QT"])
+                                 a["R"], a["QT"], a.get("n_node"), a.get("m_node"))
         nbytes = self.L.lqgrid_workspace_bytes(byref(self.desc), None)
         if nbytes == 0:
             raise LqgridError(EINVAL, "lqgrid_workspace_bytes")
@@ -240,11 +264,13 @@ class Context:
 
     def solve(self, x0, opts: SolveOpts | None = None, delta_init=None,
               want_primal=False, out=None, raise_on_error=True, out_x=None,
-              out_u=None):
+              out_u=None, boundary=None):
         """x0: [N][K][n] float64 CUDA tensor (or array).  Returns
         (delta [T+1][N][K][n], x or None, u or None, info dict).  out, out_x,
         out_u: optional preallocated outputs (out_x / out_u imply
-        want_primal)."""
+        want_primal).  boundary: optional dict (or object with attributes)
+        alpha_lo, alpha_hi, beta_lo, beta_hi of known boundary states
+        (lqgrid_pcg_solve_bc)."""
         import torch
         K, N, T, n, m = self.dims
         dev = self.arrays["A"].device
@@ -261,11 +287,62 @@ class Context:
         if delta_init is not None:
             di = torch.as_tensor(delta_init).to(dtype=torch.float64, device=dev).contiguous()
         info = Info()
-        st = self.L.lqgrid_pcg_solve(self.ctx, _ptr(x0), byref(opts), _ptr(di),
-                                     _ptr(delta), _ptr(x), _ptr(u), byref(info))
+        if boundary is None:
+            st = self.L.lqgrid_pcg_solve(self.ctx, _ptr(x0), byref(opts), _ptr(di),
+                                         _ptr(delta), _ptr(x), _ptr(u), byref(info))
+        else:
+            keep = {}
+            for k in ("alpha_lo", "alpha_hi", "beta_lo", "beta_hi"):
+                v = boundary.get(k) if isinstance(boundary, dict) else getattr(boundary, k, None)
+                if v is not None:
+                    keep[k] = torch.as_tensor(v).to(dtype=torch.float64, device=dev).contiguous()
+            bc = Boundary(*[_ptr(keep.get(k)) for k in ("alpha_lo", "alpha_hi",
+                                                        "beta_lo", "beta_hi")])
+            st = self.L.lqgrid_pcg_solve_bc(self.ctx, _ptr(x0), byref(bc), byref(opts),
+                                            _ptr(di), _ptr(delta), _ptr(x), _ptr(u),
+                                            byref(info))
+            torch.cuda.current_stream().synchronize()
+            del keep
         if st != OK and raise_on_error:
             raise LqgridError(st, "lqgrid_pcg_solve")
         return delta, x, u, info.as_dict()
+
+    def nbjm_solve(self, x0, opts: SolveOpts | None = None, want_primal=False,
+                   raise_on_error=True):
+        """Standalone NBJM (lqgrid_nbjm_solve).  Returns (delta, x or None,
+        u or None, info dict); info["iterations"] counts outer sweeps."""
+        import torch
+        K, N, T, n, m = self.dims
+        dev = self.arrays["A"].device
+        x0 = torch.as_tensor(x0).to(dtype=torch.float64, device=dev).contiguous()
+        opts = default_opts() if opts is None else opts
+        delta = torch.empty((T + 1, N, K, n), dtype=torch.float64, device=dev)
+        x = u = None
+        if want_primal:
+            x = torch.empty((T + 1, N, K, n), dtype=torch.float64, device=dev)
+            u = torch.empty((T, N, K, m), dtype=torch.float64, device=dev)
+        info = Info()
+        st = self.L.lqgrid_nbjm_solve(self.ctx, _ptr(x0), byref(opts), _ptr(delta),
+                                      _ptr(x), _ptr(u), byref(info))
+        if st != OK and raise_on_error:
+            raise LqgridError(st, "lqgrid_nbjm_solve")
+        return delta, x, u, info.as_dict()
+
+    def condition_estimate(self, x0, preconditioned=True, S=2, L=2, tol=1e-10,
+                           max_iter=0):
+        """lqgrid_condition_estimate: dict with kappa, lambda_min, lambda_max,
+        iterations of the Lanczos estimate from one run of Algorithm 1."""
+        import torch
+        dev = self.arrays["A"].device
+        x0 = torch.as_tensor(x0).to(dtype=torch.float64, device=dev).contiguous()
+        k, lo, hi, it = c_double(), c_double(), c_double(), c_int()
+        st = self.L.lqgrid_condition_estimate(self.ctx, _ptr(x0), 1 if preconditioned else 0,
+                                              S, L, tol, max_iter, byref(k), byref(lo),
+                                              byref(hi), byref(it))
+        if st != OK:
+            raise LqgridError(st, "lqgrid_condition_estimate")
+        return dict(kappa=k.value, lambda_min=lo.value, lambda_max=hi.value,
+                    iterations=it.value)
 
     def apply(self, op, vec, S=2, L=2):
         import torch
