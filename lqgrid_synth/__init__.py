@@ -79,6 +79,8 @@ class Problem:
     # per-node state / input sizes (Sec. II), None meaning n and m everywhere
     n_node: np.ndarray | None = None
     m_node: np.ndarray | None = None
+    # A, A_nbr, B, Q, R carry a leading time index t = 0..T-1
+    time_varying: bool = False
 
     @property
     def has_boundary(self) -> bool:
@@ -99,7 +101,7 @@ def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
                  cs: float = 0.1, seed: int = 0, r_scale: float = 0.1,
                  q_scale: float = 1.0, qt_scale: float | None = None,
                  weights: str = "identity", boundary: bool = False,
-                 sizes: bool = False) -> Problem:
+                 sizes: bool = False, time_varying: bool = False) -> Problem:
     """Draw one problem by the recipe in the module docstring.
 
     ``q_scale``/``qt_scale`` scale the weights; they exist so tests can
@@ -111,10 +113,17 @@ def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
     ``sizes``: heterogeneous sub-systems -- per-node n_node in U{1..n} and
     m_node in U{1..m} ([N][K] int arrays, drawn last); the arrays keep their
     padded shapes and the entries past a node's sizes hold the values drawn
-    above, which a solver must ignore."""
+    above, which a solver must ignore.
+    ``time_varying``: A, A_nbr, B, Q and R get a leading time index t =
+    0..T-1 (Sec. II: A_{i,j,t}, ...), each slice drawn as above in the same
+    order (A rescaled per time and node); Q_T keeps none.  With "spd" weights
+    every Q_t and R_t differs in t as well."""
     if min(K, N, T, n, m) < 1:
         raise ValueError("all dimensions must be >= 1")
     rng = np.random.default_rng(seed)
+    if time_varying:
+        return _make_tv(K, N, T, n, m, rho, cs, seed, r_scale, q_scale, qt_scale,
+                        weights, boundary, sizes, rng)
     A = rng.standard_normal((N, K, n, n))
     sr_all = np.max(np.abs(np.linalg.eigvals(A)), axis=-1)
     if np.all(sr_all > 0.0):
@@ -144,6 +153,43 @@ def make_problem(K: int, N: int, T: int, n: int, m: int, *, rho: float = 0.95,
         raise ValueError(f"unknown weights {weights!r}")
     p = Problem(K, N, T, n, m, A, A_nbr, B, Q, R, QT, x0, seed,
                 dict(rho=rho, cs=cs, r_scale=r_scale, weights=weights))
+    if boundary:
+        p.alpha_lo = rng.standard_normal((T + 1, N, n))
+        p.alpha_hi = rng.standard_normal((T + 1, N, n))
+        p.beta_lo = rng.standard_normal((T + 1, K, n))
+        p.beta_hi = rng.standard_normal((T + 1, K, n))
+    if sizes:
+        p.n_node = rng.integers(1, n + 1, size=(N, K)).astype(np.int32)
+        p.m_node = rng.integers(1, m + 1, size=(N, K)).astype(np.int32)
+    return p
+
+
+def _make_tv(K, N, T, n, m, rho, cs, seed, r_scale, q_scale, qt_scale, weights,
+             boundary, sizes, rng) -> Problem:
+    """Time-varying data: the recipe with a leading time index on A, A_nbr,
+    B (and on Q, R)."""
+    A = rng.standard_normal((T, N, K, n, n))
+    sr = np.max(np.abs(np.linalg.eigvals(A)), axis=-1)
+    if not np.all(sr > 0.0):
+        raise ValueError("a node block with spectral radius 0; use another seed")
+    A *= (rho / sr)[..., None, None]
+    A_nbr = cs * rng.standard_normal((T, N, K, 4, n, n))
+    B = rng.standard_normal((T, N, K, n, m))
+    x0 = rng.standard_normal((N, K, n))
+    qt = q_scale if qt_scale is None else qt_scale
+    if weights == "identity":
+        Q = np.broadcast_to(q_scale * np.eye(n), (T, N, K, n, n)).copy()
+        QT = np.broadcast_to(qt * np.eye(n), (N, K, n, n)).copy()
+        R = np.broadcast_to(r_scale * np.eye(m), (T, N, K, m, m)).copy()
+    elif weights == "spd":
+        Q = q_scale * np.stack([_random_spd(rng, N, K, n) for _ in range(T)])
+        QT = qt * _random_spd(rng, N, K, n)
+        R = r_scale * np.stack([_random_spd(rng, N, K, m) for _ in range(T)])
+    else:
+        raise ValueError(f"unknown weights {weights!r}")
+    p = Problem(K, N, T, n, m, A, A_nbr, B, Q, R, QT, x0, seed,
+                dict(rho=rho, cs=cs, r_scale=r_scale, weights=weights, time_varying=True))
+    p.time_varying = True
     if boundary:
         p.alpha_lo = rng.standard_normal((T + 1, N, n))
         p.alpha_hi = rng.standard_normal((T + 1, N, n))

@@ -22,6 +22,13 @@ from .slab import SlabOperators
 
 def recover(ops: SlabOperators, delta: np.ndarray):
     T = ops.T
+    if ops.tv:
+        X = np.empty_like(delta)
+        for t in range(T + 1):
+            a = -delta[t] + (ops.AT_t(t) @ delta[t + 1] if t < T else 0.0)
+            X[t] = ops.Qinv_t(t) @ a
+        U = np.stack([ops.Rinv_t(t) @ (ops.BT_t(t) @ delta[t + 1]) for t in range(T)])
+        return X, U
     D = delta.T
     AtD = -D.copy()
     AtD[:, :T] += ops.AhT @ D[:, 1:]
@@ -38,6 +45,8 @@ def kkt_residual(ops: SlabOperators, delta: np.ndarray, x=None, u=None):
     T = ops.T
     if x is None or u is None:
         x, u = recover(ops, delta)
+    if ops.tv:
+        return _kkt_residual_tv(ops, delta, x, u)
     D, X, Uu = delta.T, x.T, u.T
     # block 1: Q~ x~ - A~' delta~
     Qx = np.empty_like(X)
@@ -67,3 +76,25 @@ def ops_q(ops: SlabOperators):
         ops._qhat = (stack.Q_hat(ops.p, 0), stack.Q_hat(ops.p, ops.T),
                      stack.R_hat(ops.p))
     return ops._qhat
+
+
+def _kkt_residual_tv(ops, delta, x, u):
+    """kkt_residual for time-varying data (every slice matrix at its t)."""
+    from . import stack
+    p, T = ops.p, ops.T
+    rd = ops.r_delta()
+    r1 = np.empty_like(x)
+    r3 = np.empty_like(x)
+    r2 = np.empty_like(u)
+    for t in range(T + 1):
+        AtD = -delta[t] + (ops.AT_t(t) @ delta[t + 1] if t < T else 0.0)
+        r1[t] = stack.Q_hat(p, t) @ x[t] - AtD
+        AX = -x[t] + (ops.A_t(t - 1) @ x[t - 1] + ops.B_t(t - 1) @ u[t - 1] if t >= 1 else 0.0)
+        r3[t] = AX - rd[t]
+    for t in range(T):
+        r2[t] = stack.R_hat(p, t) @ u[t] - ops.BT_t(t) @ delta[t + 1]
+    nrd = np.linalg.norm(rd)
+    tot = np.sqrt(np.sum(r1 ** 2) + np.sum(r2 ** 2) + np.sum(r3 ** 2))
+    inf = max(np.max(np.abs(r1)), np.max(np.abs(r2)) if r2.size else 0.0, np.max(np.abs(r3)))
+    return dict(rel2=tot / nrd, inf=inf, rel_inf=inf / np.max(np.abs(rd)),
+                schur_rel2=np.linalg.norm(r3) / nrd)

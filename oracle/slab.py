@@ -26,8 +26,17 @@ half-bandwidth 3*w*n - 1 (w = columns in the pair), because Psi_hat_t couples
 nodes at Manhattan distance <= 2 only.  The paper only says "block Cholesky";
 any exact solver gives the same result up to rounding.
 
-The data are time invariant, so Psi_hat_t takes three values: t = 0,
-1 <= t <= T-1 and t = T (the latter differs through Q_T).
+For time-invariant data Psi_hat_t takes three values: t = 0, 1 <= t <= T-1
+and t = T (the latter differs through Q_T).  For time-varying data (Sec. II:
+A_{i,j,t}, B_{i,j,t}, E...H_{i,j,t}, Q_{i,j,t}, R_{i,j,t}) every slice
+matrix carries its time index -- A_hat_t, B_hat_t, Q_hat_t, R_hat_t -- and
+
+  (A~' d)_t = -d_t + A_hat_t' d_{t+1},  (A~ w)_t = A_hat_{t-1} w_{t-1} - w_t,
+  (B~' d)_t = B_hat_t' d_{t+1},         (B~ z)_t = B_hat_{t-1} z_{t-1},
+  Psi_hat_t = Q_hat_t^-1 + A_hat_{t-1} Q_hat_{t-1}^-1 A_hat_{t-1}'
+              + B_hat_{t-1} R_hat_{t-1}^-1 B_hat_{t-1}'   (t >= 1),
+
+so every t is a class of its own.
 """
 from __future__ import annotations
 
@@ -47,13 +56,23 @@ class SlabOperators:
         self.p = p
         self.K, self.N, self.n, self.T = p.K, p.N, p.n, p.T
         self.KNn = p.K * p.N * p.n
-        self.Ah = stack.A_hat(p)
-        self.AhT = sp.csr_matrix(self.Ah.T)
-        self.Bh = stack.B_hat(p)
-        self.BhT = sp.csr_matrix(self.Bh.T)
-        self.Qinv = stack.Q_hat_inv(p, 0)          # Q_hat_t^-1, t < T
+        self.tv = bool(getattr(p, "time_varying", False))
         self.QTinv = stack.Q_hat_inv(p, p.T)       # Q_hat_T^-1
-        self.Rinv = stack.R_hat_inv(p)
+        if self.tv:
+            T = p.T
+            self.Ahs = [stack.A_hat(p, t) for t in range(T)]
+            self.AhTs = [sp.csr_matrix(A.T) for A in self.Ahs]
+            self.Bhs = [stack.B_hat(p, t) for t in range(T)]
+            self.BhTs = [sp.csr_matrix(B.T) for B in self.Bhs]
+            self.Qinvs = [stack.Q_hat_inv(p, t) for t in range(T)] + [self.QTinv]
+            self.Rinvs = [stack.R_hat_inv(p, t) for t in range(T)]
+        else:
+            self.Ah = stack.A_hat(p)
+            self.AhT = sp.csr_matrix(self.Ah.T)
+            self.Bh = stack.B_hat(p)
+            self.BhT = sp.csr_matrix(self.Bh.T)
+            self.Qinv = stack.Q_hat_inv(p, 0)          # Q_hat_t^-1, t < T
+            self.Rinv = stack.R_hat_inv(p)
         self._psi, self._phi, self._omega, self._chol = {}, {}, {}, {}
         # column of every slice unknown, and its super-column
         idx = np.arange(self.KNn)
@@ -63,21 +82,41 @@ class SlabOperators:
 
     # -- slice matrices -------------------------------------------------
     def Qinv_t(self, t):
+        if self.tv:
+            return self.Qinvs[t]
         return self.QTinv if t == self.T else self.Qinv
 
+    def A_t(self, t):
+        return self.Ahs[t] if self.tv else self.Ah
+
+    def AT_t(self, t):
+        return self.AhTs[t] if self.tv else self.AhT
+
+    def B_t(self, t):
+        return self.Bhs[t] if self.tv else self.Bh
+
+    def BT_t(self, t):
+        return self.BhTs[t] if self.tv else self.BhT
+
+    def Rinv_t(self, t):
+        return self.Rinvs[t] if self.tv else self.Rinv
+
+    def cls(self, t):
+        return t if self.tv else time_class(t, self.T)
+
     def psi_hat(self, t) -> sp.csr_matrix:
-        c = time_class(t, self.T)
+        c = self.cls(t)
         if c not in self._psi:
             if t == 0:
                 M = self.Qinv_t(0)
             else:
-                M = (self.Qinv_t(t) + self.Ah @ self.Qinv_t(t - 1) @ self.AhT
-                     + self.Bh @ self.Rinv @ self.BhT)
+                M = (self.Qinv_t(t) + self.A_t(t - 1) @ self.Qinv_t(t - 1) @ self.AT_t(t - 1)
+                     + self.B_t(t - 1) @ self.Rinv_t(t - 1) @ self.BT_t(t - 1))
             self._psi[c] = sp.csr_matrix(M)
         return self._psi[c]
 
     def phi_hat(self, t) -> sp.csr_matrix:
-        c = time_class(t, self.T)
+        c = self.cls(t)
         if c not in self._phi:
             C = sp.coo_matrix(self.psi_hat(t))
             keep = self.sup[C.row] == self.sup[C.col]
@@ -86,7 +125,7 @@ class SlabOperators:
         return self._phi[c]
 
     def omega_hat(self, t) -> sp.csr_matrix:
-        c = time_class(t, self.T)
+        c = self.cls(t)
         if c not in self._omega:
             self._omega[c] = sp.csr_matrix(self.phi_hat(t) - self.psi_hat(t))
         return self._omega[c]
@@ -94,6 +133,16 @@ class SlabOperators:
     # -- operators on (T+1, KNn) arrays ---------------------------------
     def delta(self, d: np.ndarray) -> np.ndarray:
         T = self.T
+        if self.tv:
+            W = np.empty_like(d)
+            for t in range(T + 1):
+                a = -d[t] + (self.AT_t(t) @ d[t + 1] if t < T else 0.0)
+                W[t] = self.Qinv_t(t) @ a
+            Y = -W.copy()
+            for t in range(1, T + 1):
+                z = self.Rinv_t(t - 1) @ (self.BT_t(t - 1) @ d[t])
+                Y[t] += self.A_t(t - 1) @ W[t - 1] + self.B_t(t - 1) @ z
+            return Y
         D = d.T                                   # (KNn, T+1)
         AtD = -D.copy()
         AtD[:, :T] += self.AhT @ D[:, 1:]         # (A~' d)_t
@@ -128,7 +177,7 @@ class SlabOperators:
         T = self.T
         cls = {}
         for t in range(T + 1):
-            cls.setdefault(time_class(t, T), []).append(t)
+            cls.setdefault(self.cls(t), []).append(t)
         return {c: np.array(ts) for c, ts in cls.items()}
 
     # -- Phi_bar_{v,t} solves -------------------------------------------
@@ -141,7 +190,7 @@ class SlabOperators:
         return np.array(perm), w
 
     def _factor(self, t):
-        c = time_class(t, self.T)
+        c = self.cls(t)
         if c not in self._chol:
             Phi = self.phi_hat(t).tocsr()
             facs = []

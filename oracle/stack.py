@@ -29,17 +29,26 @@ import numpy as np
 import scipy.sparse as sp
 
 
+def data(p, name: str, t: int):
+    """The problem array `name` at time t: the array itself for time-invariant
+    data, its slice t when the problem is time varying (A, A_nbr, B, Q, R
+    carry a leading time index t = 0..T-1 there; Q_T has none)."""
+    arr = getattr(p, name)
+    return arr[t] if getattr(p, "time_varying", False) else arr
+
+
 def node(i: int, j: int, K: int) -> int:
     """Position of node (i, j) inside x_hat_t (column j outermost)."""
     return j * K + i
 
 
-def A_hat(p) -> sp.csr_matrix:
-    """A_hat_t (time invariant): block tri-diagonal over columns j with block
-    tri-diagonal diagonal blocks A_bar_j (Sec. II-A).  Block row of node (i,j):
-    A at (i,j), E at (i,j-1), F at (i,j+1), G at (i-1,j), H at (i+1,j), each
-    only when that neighbour lies inside the grid (zero boundary states)."""
+def A_hat(p, t: int = 0) -> sp.csr_matrix:
+    """A_hat_t: block tri-diagonal over columns j with block tri-diagonal
+    diagonal blocks A_bar_j (Sec. II-A).  Block row of node (i,j): A at (i,j),
+    E at (i,j-1), F at (i,j+1), G at (i-1,j), H at (i+1,j), each only when
+    that neighbour lies inside the grid (the boundary states enter omega~)."""
     K, N, n = p.K, p.N, p.n
+    Ad, An = data(p, "A", t), data(p, "A_nbr", t)
     rows, cols, vals = [], [], []
 
     def put(bi, bj, M):
@@ -53,15 +62,15 @@ def A_hat(p) -> sp.csr_matrix:
     for j in range(N):
         for i in range(K):
             me = node(i, j, K)
-            put(me, me, p.A[j, i])
+            put(me, me, Ad[j, i])
             if j - 1 >= 0:
-                put(me, node(i, j - 1, K), p.A_nbr[j, i, 0])   # E
+                put(me, node(i, j - 1, K), An[j, i, 0])   # E
             if j + 1 < N:
-                put(me, node(i, j + 1, K), p.A_nbr[j, i, 1])   # F
+                put(me, node(i, j + 1, K), An[j, i, 1])   # F
             if i - 1 >= 0:
-                put(me, node(i - 1, j, K), p.A_nbr[j, i, 2])   # G
+                put(me, node(i - 1, j, K), An[j, i, 2])   # G
             if i + 1 < K:
-                put(me, node(i + 1, j, K), p.A_nbr[j, i, 3])   # H
+                put(me, node(i + 1, j, K), An[j, i, 3])   # H
     KNn = K * N * n
     return sp.csr_matrix((vals, (rows, cols)), shape=(KNn, KNn))
 
@@ -72,25 +81,25 @@ def _blkdiag_nodes(p, blocks) -> sp.csr_matrix:
     return sp.block_diag(mats, format="csr")
 
 
-def B_hat(p) -> sp.csr_matrix:
-    return _blkdiag_nodes(p, p.B)
+def B_hat(p, t: int = 0) -> sp.csr_matrix:
+    return _blkdiag_nodes(p, data(p, "B", t))
 
 
 def Q_hat(p, t: int) -> sp.csr_matrix:
-    return _blkdiag_nodes(p, p.QT if t == p.T else p.Q)
+    return _blkdiag_nodes(p, p.QT if t == p.T else data(p, "Q", t))
 
 
 def Q_hat_inv(p, t: int) -> sp.csr_matrix:
-    Qs = p.QT if t == p.T else p.Q
+    Qs = p.QT if t == p.T else data(p, "Q", t)
     return _blkdiag_nodes(p, np.linalg.inv(Qs))
 
 
-def R_hat(p) -> sp.csr_matrix:
-    return _blkdiag_nodes(p, p.R)
+def R_hat(p, t: int = 0) -> sp.csr_matrix:
+    return _blkdiag_nodes(p, data(p, "R", t))
 
 
-def R_hat_inv(p) -> sp.csr_matrix:
-    return _blkdiag_nodes(p, np.linalg.inv(p.R))
+def R_hat_inv(p, t: int = 0) -> sp.csr_matrix:
+    return _blkdiag_nodes(p, np.linalg.inv(data(p, "R", t)))
 
 
 def gamma_hat(p) -> np.ndarray:
@@ -103,19 +112,20 @@ def omega_hat(p, t: int) -> np.ndarray:
     """Boundary contribution to x_hat_{t+1} (stacking order), t = 0..T-1,
     written out per node from eq. "2d_graph_dynamics"."""
     K, N, n = p.K, p.N, p.n
+    An = data(p, "A_nbr", t)
     w = np.zeros((N, K, n))
     if getattr(p, "alpha_lo", None) is not None:
         for j in range(N):
-            w[j, 0] += p.A_nbr[j, 0, 2] @ p.alpha_lo[t, j]        # G x_{0,j}
+            w[j, 0] += An[j, 0, 2] @ p.alpha_lo[t, j]        # G x_{0,j}
     if getattr(p, "alpha_hi", None) is not None:
         for j in range(N):
-            w[j, K - 1] += p.A_nbr[j, K - 1, 3] @ p.alpha_hi[t, j]  # H x_{K+1,j}
+            w[j, K - 1] += An[j, K - 1, 3] @ p.alpha_hi[t, j]  # H x_{K+1,j}
     if getattr(p, "beta_lo", None) is not None:
         for i in range(K):
-            w[0, i] += p.A_nbr[0, i, 0] @ p.beta_lo[t, i]         # E x_{i,0}
+            w[0, i] += An[0, i, 0] @ p.beta_lo[t, i]         # E x_{i,0}
     if getattr(p, "beta_hi", None) is not None:
         for i in range(K):
-            w[N - 1, i] += p.A_nbr[N - 1, i, 1] @ p.beta_hi[t, i]   # F x_{i,N+1}
+            w[N - 1, i] += An[N - 1, i, 1] @ p.beta_hi[t, i]   # F x_{i,N+1}
     return w.reshape(-1)
 
 
@@ -132,25 +142,27 @@ def stacked(p) -> dict:
     """A_tilde, B_tilde, Q_tilde, R_tilde, omega_tilde, r_delta
     (eq. "t_stacked_LQ_problem" and the definitions after it)."""
     T = p.T
-    Ah, Bh = A_hat(p), B_hat(p)
-    KNn = Ah.shape[0]
-    KNm = Bh.shape[1]
+    tv = getattr(p, "time_varying", False)
+    Ahs = [A_hat(p, t) for t in range(T)] if tv else [A_hat(p)] * T
+    Bhs = [B_hat(p, t) for t in range(T)] if tv else [B_hat(p)] * T
+    KNn = p.K * p.N * p.n
+    KNm = p.K * p.N * p.m
     I = sp.identity(KNn, format="csr")
-    # A_tilde: -I on the block diagonal, A_hat at block (t+1, t).
+    # A_tilde: -I on the block diagonal, A_hat_t at block (t+1, t).
     blocks = [[None] * (T + 1) for _ in range(T + 1)]
     for t in range(T + 1):
         blocks[t][t] = -I
         if t >= 1:
-            blocks[t][t - 1] = Ah
+            blocks[t][t - 1] = Ahs[t - 1]
     At = sp.bmat(blocks, format="csr")
-    # B_tilde: B_hat at block (t+1, t), first block row zero.
+    # B_tilde: B_hat_t at block (t+1, t), first block row zero.
     bb = [[None] * T for _ in range(T + 1)]
     for t in range(T):
-        bb[t + 1][t] = Bh
+        bb[t + 1][t] = Bhs[t]
     bb[0][0] = sp.csr_matrix((KNn, KNm))
     Bt = sp.bmat(bb, format="csr")
     Qt = sp.block_diag([Q_hat(p, t) for t in range(T + 1)], format="csr")
-    Rt = sp.block_diag([R_hat(p) for _ in range(T)], format="csr")
+    Rt = sp.block_diag([R_hat(p, t) for t in range(T)], format="csr")
     omega = omega_tilde(p)
     return dict(At=At, Bt=Bt, Qt=Qt, Rt=Rt, omega=omega, r_delta=-omega)
 
@@ -160,7 +172,7 @@ def Q_tilde_inv(p) -> sp.csr_matrix:
 
 
 def R_tilde_inv(p) -> sp.csr_matrix:
-    return sp.block_diag([R_hat_inv(p) for _ in range(p.T)], format="csr")
+    return sp.block_diag([R_hat_inv(p, t) for t in range(p.T)], format="csr")
 
 
 def delta_matrix(p, S: dict | None = None) -> sp.csr_matrix:

@@ -29,17 +29,24 @@ def simulate(p, u):
         return zero if arr is None else arr[t, k]
 
     for t in range(T):
+        A, An, B = at(p, "A", t), at(p, "A_nbr", t), at(p, "B", t)
         for j in range(N):
             for i in range(K):
-                acc = p.A[j, i] @ x[t, j, i] + p.B[j, i] @ u[t, j, i]
+                acc = A[j, i] @ x[t, j, i] + B[j, i] @ u[t, j, i]
                 west = x[t, j - 1, i] if j - 1 >= 0 else bnd(p.beta_lo, t, i)
                 east = x[t, j + 1, i] if j + 1 < N else bnd(p.beta_hi, t, i)
                 north = x[t, j, i - 1] if i - 1 >= 0 else bnd(p.alpha_lo, t, j)
                 south = x[t, j, i + 1] if i + 1 < K else bnd(p.alpha_hi, t, j)
-                acc += p.A_nbr[j, i, 0] @ west + p.A_nbr[j, i, 1] @ east
-                acc += p.A_nbr[j, i, 2] @ north + p.A_nbr[j, i, 3] @ south
+                acc += An[j, i, 0] @ west + An[j, i, 1] @ east
+                acc += An[j, i, 2] @ north + An[j, i, 3] @ south
                 x[t + 1, j, i] = acc
     return x
+
+
+def at(p, name, t):
+    """Problem array `name` at time t (time-varying data carry a leading t)."""
+    a = getattr(p, name)
+    return a[t] if p.time_varying else a
 
 
 def cost(p, x, u):
@@ -48,10 +55,10 @@ def cost(p, x, u):
     for t in range(p.T + 1):
         for j in range(p.N):
             for i in range(p.K):
-                Qm = p.QT[j, i] if t == p.T else p.Q[j, i]
+                Qm = p.QT[j, i] if t == p.T else at(p, "Q", t)[j, i]
                 J += x[t, j, i] @ Qm @ x[t, j, i]
                 if t < p.T:
-                    J += u[t, j, i] @ p.R[j, i] @ u[t, j, i]
+                    J += u[t, j, i] @ at(p, "R", t)[j, i] @ u[t, j, i]
     return 0.5 * J
 
 
@@ -87,10 +94,30 @@ def test_riccati_special_case(seed, n, m, T, qt, w):
     assert np.abs(xs - R["delta"]).max() <= 1e-9 * max(1, np.abs(R["delta"]).max())
 
 
-@pytest.mark.parametrize("seed,w,bnd", [(s, "identity", False) for s in range(5)]
-                         + [(5, "spd", False), (6, "spd", False),
-                            (7, "identity", True), (8, "spd", True)])
-def test_kkt_solution_is_feasible_and_optimal(seed, w, bnd):
+@pytest.mark.parametrize("seed,n,m,T", [(0, 2, 1, 10), (1, 4, 2, 25), (2, 3, 3, 6)])
+def test_time_varying_riccati_special_case(seed, n, m, T):
+    """K = N = 1 with time-varying A_t, B_t, Q_t, R_t: the KKT solution and the
+    matrix-free slab CG equal the time-varying Riccati recursion."""
+    p = make_problem(1, 1, T, n, m, rho=1.1, seed=seed, weights="spd", qt_scale=2.0,
+                     time_varying=True)
+    R = riccati.lqr_of_tv_problem(p)
+    sol = kkt.solve_kkt(p)
+    x, u = shapes(p, sol)
+    assert np.abs(x[:, 0, 0] - R["x"]).max() <= 1e-11 * max(1, np.abs(R["x"]).max())
+    assert np.abs(u[:, 0, 0] - R["u"]).max() <= 1e-11 * max(1, np.abs(R["u"]).max())
+    assert np.abs(sol["delta"].reshape(T + 1, n) - R["delta"]).max() <= \
+        1e-10 * max(1, np.abs(R["delta"]).max())
+    assert abs(cost(p, x, u) - R["cost"]) <= 1e-11 * R["cost"]
+    ops = slab.SlabOperators(p)
+    xs, _, _ = pcg.cg(ops.delta, ops.r_delta(), tol=1e-13, max_iter=5000)
+    assert np.abs(xs - R["delta"]).max() <= 1e-9 * max(1, np.abs(R["delta"]).max())
+
+
+@pytest.mark.parametrize("seed,w,bnd,tv", [(s, "identity", False, False) for s in range(5)]
+                         + [(5, "spd", False, False), (6, "spd", False, False),
+                            (7, "identity", True, False), (8, "spd", True, False),
+                            (9, "spd", False, True), (10, "spd", True, True)])
+def test_kkt_solution_is_feasible_and_optimal(seed, w, bnd, tv):
     """Brute force on the tiny configuration: the LDL' KKT solution obeys the
     node-level dynamics (with the boundary states as the neighbours outside
     the grid), and no random feasible perturbation lowers the cost (the cost
@@ -99,7 +126,7 @@ def test_kkt_solution_is_feasible_and_optimal(seed, w, bnd):
         p, _ = config_problem("tiny", seed)
     else:
         p = make_problem(4, 4, 20, 2, 1, rho=0.9, seed=seed, qt_scale=1.7, weights=w,
-                         boundary=bnd)
+                         boundary=bnd, time_varying=tv)
     sol = kkt.solve_kkt(p)
     x, u = shapes(p, sol)
     xs = simulate(p, u)
@@ -111,11 +138,13 @@ def test_kkt_solution_is_feasible_and_optimal(seed, w, bnd):
         u2 = u + du
         J2 = cost(p, simulate(p, u2), u2)
         assert J2 > J
-    # first-order optimality: J(u + e du) - J(u) = O(e^2)
+    # first-order optimality: the directional derivative of J vanishes, i.e.
+    # the central difference J(u + e du) - J(u - e du) = 2 e J'(u) du + O(e^3)
     du = rng.standard_normal(u.shape)
     e = 1e-4
-    d1 = cost(p, simulate(p, u + e * du), u + e * du) - J
-    assert abs(d1) < 1e-5 * abs(J) + 1e-12
+    d1 = cost(p, simulate(p, u + e * du), u + e * du) - cost(p, simulate(p, u - e * du),
+                                                             u - e * du)
+    assert abs(d1) < 1e-7 * abs(J) + 1e-12
 
 
 @pytest.mark.parametrize("K,N,T,n,m", [(4, 4, 20, 2, 1), (3, 5, 6, 3, 2),
@@ -135,9 +164,12 @@ def test_schur_solve_equals_kkt_ldl(K, N, T, n, m):
                                             (2, 7, 4, 2, 1, 0.3, "identity"),
                                             (1, 1, 3, 2, 2, 1.0, "identity"),
                                             (4, 5, 6, 3, 2, 1.0, "spd"),
-                                            (5, 3, 4, 4, 2, 0.6, "spd")])
+                                            (5, 3, 4, 4, 2, 0.6, "spd"),
+                                            (4, 5, 6, 3, 2, 1.2, "tv"),
+                                            (3, 3, 2, 2, 2, 1.0, "tv")])
 def test_slab_operators_match_full_matrices(K, N, T, n, m, qt, w):
-    p = make_problem(K, N, T, n, m, seed=11, qt_scale=qt, weights=w)
+    p = make_problem(K, N, T, n, m, seed=11, qt_scale=qt,
+                     weights="spd" if w == "tv" else w, time_varying=w == "tv")
     ops = slab.SlabOperators(p)
     spl = splitting.splittings(p)
     rng = np.random.default_rng(5)
@@ -151,51 +183,53 @@ def test_slab_operators_match_full_matrices(K, N, T, n, m, qt, w):
     assert np.linalg.norm(spl["Phi"] @ tau.ravel() - d.ravel()) <= 1e-12 * np.linalg.norm(d)
 
 
-@pytest.mark.parametrize("w", ["identity", "spd"])
+@pytest.mark.parametrize("w", ["identity", "spd", "tv"])
 def test_delta_from_node_level_definition(w):
     """Delta d equals A~(Q~^-1 A~' d) + B~(R~^-1 B~' d) evaluated with
     node-level loops (no stacked matrices); with per-node SPD weights a weight
-    taken from the wrong node changes the result."""
-    p = make_problem(3, 4, 5, 2, 2, seed=4, weights=w, qt_scale=1.0 if w == "identity" else 1.4)
+    taken from the wrong node changes the result, and with time-varying data
+    a block taken at the wrong time does."""
+    p = make_problem(3, 4, 5, 2, 2, seed=4, weights="spd" if w == "tv" else w,
+                     qt_scale=1.0 if w == "identity" else 1.4, time_varying=w == "tv")
     rng = np.random.default_rng(0)
     d = rng.standard_normal((p.T + 1, p.N, p.K, p.n))
-    Qi = np.linalg.inv(p.Q)
-    QTi = np.linalg.inv(p.QT)
-    Ri = np.linalg.inv(p.R)
+    T = p.T
+    Qi = [np.linalg.inv(at(p, "Q", t)) for t in range(T)] + [np.linalg.inv(p.QT)]
+    Ri = [np.linalg.inv(at(p, "R", t)) for t in range(T)]
 
-    def nbrs(i, j):   # (coupling block of node (i,j), neighbour position)
-        out = [(p.A[j, i], (i, j))]
+    def nbrs(i, j, t):   # (coupling block of node (i,j) at t, neighbour position)
+        A, An = at(p, "A", t), at(p, "A_nbr", t)
+        out = [(A[j, i], (i, j))]
         if j - 1 >= 0:
-            out.append((p.A_nbr[j, i, 0], (i, j - 1)))
+            out.append((An[j, i, 0], (i, j - 1)))
         if j + 1 < p.N:
-            out.append((p.A_nbr[j, i, 1], (i, j + 1)))
+            out.append((An[j, i, 1], (i, j + 1)))
         if i - 1 >= 0:
-            out.append((p.A_nbr[j, i, 2], (i - 1, j)))
+            out.append((An[j, i, 2], (i - 1, j)))
         if i + 1 < p.K:
-            out.append((p.A_nbr[j, i, 3], (i + 1, j)))
+            out.append((An[j, i, 3], (i + 1, j)))
         return out
 
-    T = p.T
-    # a = A~' d : a_t = -d_t + A_hat' d_{t+1}
+    # a = A~' d : a_t = -d_t + A_hat_t' d_{t+1}
     a = -d.copy()
     for t in range(T):
         for j in range(p.N):
             for i in range(p.K):
-                for M, (ii, jj) in nbrs(i, j):
+                for M, (ii, jj) in nbrs(i, j, t):
                     a[t, jj, ii] += M.T @ d[t + 1, j, i]
     w = np.zeros_like(a)
     for t in range(T + 1):
         for j in range(p.N):
             for i in range(p.K):
-                w[t, j, i] = (QTi if t == T else Qi)[j, i] @ a[t, j, i]
+                w[t, j, i] = Qi[t][j, i] @ a[t, j, i]
     y = -w.copy()
     for t in range(1, T + 1):
         for j in range(p.N):
             for i in range(p.K):
-                for M, (ii, jj) in nbrs(i, j):
+                for M, (ii, jj) in nbrs(i, j, t - 1):
                     y[t, j, i] += M @ w[t - 1, jj, ii]
-                Bm = p.B[j, i]
-                y[t, j, i] += Bm @ Ri[j, i] @ Bm.T @ d[t, j, i]
+                Bm = at(p, "B", t - 1)[j, i]
+                y[t, j, i] += Bm @ Ri[t - 1][j, i] @ Bm.T @ d[t, j, i]
     ops = slab.SlabOperators(p)
     got = ops.delta(d.reshape(T + 1, -1)).reshape(y.shape)
     assert np.abs(got - y).max() <= 1e-13 * np.abs(y).max()
