@@ -28,8 +28,8 @@
  *           delta_hat_T).
  * Sign.     delta~ follows the Schur-complement convention of Sec. II-B:
  *           Q~ x~ = A~' delta~, R~ u~ = B~' delta~, Delta delta~ = r_delta.
- * Data.     Time-invariant A, B, Q, R (the paper allows time variation; this
- *           library does not yet).  Spatial boundary states: zero, or given
+ * Data.     Time-invariant A, B, Q, R, or time-varying ones (desc
+ *           time_varying).  Spatial boundary states: zero, or given
  *           per solve to lqgrid_pcg_solve_bc.  Per-node sizes: optional
  *           (lqgrid_problem_desc n_node / m_node).
  * Errors.   Every call returns an lqgrid_status; none aborts.
@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define LQGRID_ABI_VERSION 2
+#define LQGRID_ABI_VERSION 3
 
 #if defined(__GNUC__) || defined(__clang__)
 #define LQGRID_API __attribute__((visibility("default")))
@@ -96,6 +96,16 @@ typedef struct {
    * outside its range makes lqgrid_factor return LQGRID_EINVAL.  (ABI 2.)  */
   const int *n_node;
   const int *m_node;
+  /* Time-varying data (Sec. II: A_{i,j,t}, B_{i,j,t}, E..H_{i,j,t},
+   * Q_{i,j,t}, R_{i,j,t}).  0: the arrays above are time invariant.  1: A,
+   * A_nbr, B, Q and R carry a leading time index t = 0..T-1 ([T][N][K][n][n]
+   * etc.), A_t coupling x_t to x_{t+1}, Q_t and R_t weighting stage t; QT
+   * keeps its shape (NULL: Q_{T-1}).  Every Phi_bar_{v,t} is then factored
+   * (V (T+1) systems) and the operators read per-time blocks; the workspace
+   * grows accordingly (about 30 n^2 doubles per node and time step).  Not
+   * supported with boundary states, by the batched form or by the warm
+   * start (EUNSUPPORTED).  (ABI 3.) */
+  int time_varying;
 } lqgrid_problem_desc;
 
 typedef struct {

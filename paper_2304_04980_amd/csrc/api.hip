@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "api_common.h"
+#include "tv.h"
 
 using namespace lqg;
 
@@ -42,6 +43,10 @@ struct Plan {
   size_t outer[kNumOuter], p64[kNumPcg], p32[kNumPcg];
   size_t psum, pmax, scal, scal_outer, hist;
   size_t inA, inAnbr, inB, inQ, inQT, inR, nsz;  // ingested (size-masked) arrays
+  // time-varying data (tv.hip layouts), FP64 and FP32 copies
+  size_t tG13, tQi, tCdn, tCup, tAT5, tRiBT, tFw, tBw, tW;
+  size_t tG13f, tQif, tCdnf, tCupf, tFwf, tBwf, tWf;
+  bool tv;
   int npartial;
   size_t total;
 };
@@ -49,8 +54,9 @@ struct Plan {
 // PCG iterations whose coefficients lqgrid_condition_estimate can record.
 constexpr int kHistCap = 8192;
 
-Plan make_plan(const Dims& D) {
+Plan make_plan(const Dims& D, bool tv) {
   Plan P{};
+  P.tv = tv;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -95,6 +101,28 @@ Plan make_plan(const Dims& D) {
   P.Xwf = take(xw * 4);
   const int apply_blocks = padded_grid(((D.real_nodes + 3) / 4) * ((D.Tt + 63) / 64));
   P.npartial = std::max(apply_blocks, kFlatBlocks);
+  if (tv) {
+    const size_t L = (size_t)D.nodes * D.ldt;
+    const size_t fwt = (size_t)D.V * fw_rows(D.K) * kFwRow * D.ldt * 8;
+    const size_t bwt = (size_t)D.V * D.K * kBwRow * D.ldt * 8;
+    P.tG13 = take(L * 13 * nn * 8);
+    P.tQi = take(L * nn * 8);
+    P.tCdn = take(L * 5 * nn * 8);
+    P.tCup = take(L * 5 * nn * 8);
+    P.tAT5 = take(L * 5 * nn * 8);
+    P.tRiBT = take(L * D.m * D.n * 8);
+    P.tFw = take(fwt * 8);
+    P.tBw = take(bwt * 8);
+    P.tW = take((size_t)D.vlen * 8);
+    P.tG13f = take(L * 13 * nn * 4);
+    P.tQif = take(L * nn * 4);
+    P.tCdnf = take(L * 5 * nn * 4);
+    P.tCupf = take(L * 5 * nn * 4);
+    P.tFwf = take(fwt * 4);
+    P.tBwf = take(bwt * 4);
+    P.tWf = take((size_t)D.vlen * 4);
+    P.npartial = std::max<int>(P.npartial, (int)(((long long)D.real_nodes * D.ldt + 255) / 256));
+  }
   P.psum = take((size_t)P.npartial * 8);
   P.pmax = take((size_t)P.npartial * 8);
   for (int v = 0; v < kNumOuter; ++v) P.outer[v] = take((size_t)D.vlen * 8);
@@ -132,6 +160,9 @@ struct lqgrid_ctx {
   bool rd_dirty = false;  // r_delta holds boundary terms of an earlier solve
   const int* nsz = nullptr;       // per-node state sizes (workspace copy)
   const double* Anbr = nullptr;   // ingested coupling blocks (boundary terms)
+  bool tv = false;                // time-varying data
+  TvCoef<double> tv64{};
+  TvCoef<float> tv32{};
   int host_iter[2];   // staging for resetting the device iteration counters
   // profiling
   bool prof = false;
@@ -274,6 +305,42 @@ PcgBufs<double>& pcg_bufs<double>(lqgrid_ctx* c) { return c->b64; }
 template <>
 PcgBufs<float>& pcg_bufs<float>(lqgrid_ctx* c) { return c->b32; }
 
+template <typename T>
+const TvCoef<T>& tv_coef(const lqgrid_ctx* c);
+template <>
+const TvCoef<double>& tv_coef<double>(const lqgrid_ctx* c) { return c->tv64; }
+template <>
+const TvCoef<float>& tv_coef<float>(const lqgrid_ctx* c) { return c->tv32; }
+
+// The operators of the path on the context's data: the time-invariant
+// kernels, or the time-varying ones (tv.hip).
+template <typename T>
+int op_delta(lqgrid_ctx* c, const T* d, T* y, double* partial, const Scalars* sc,
+             int check) {
+  if (c->tv) return tv_delta_apply<T>(c->D, tv_coef<T>(c), d, y, partial, sc, check, c->stream);
+  return delta_apply<T>(c->D, op_coef<T>(c), d, y, partial, sc, check, c->stream);
+}
+template <typename T>
+void op_xi(lqgrid_ctx* c, const T* r, const T* dl, T* rho, int check) {
+  if (c->tv) tv_xi_rhs<T>(c->D, tv_coef<T>(c), r, dl, rho, c->sc, check, c->stream);
+  else xi_rhs<T>(c->D, op_coef<T>(c), r, dl, rho, c->sc, check, c->stream);
+}
+template <typename T>
+void op_omega(lqgrid_ctx* c, const T* rho, const T* th, T* tau, int check) {
+  if (c->tv) tv_omega_rhs<T>(c->D, tv_coef<T>(c), rho, th, tau, c->sc, check, c->stream);
+  else omega_rhs<T>(c->D, op_coef<T>(c), rho, th, tau, c->sc, check, c->stream);
+}
+template <typename T>
+void op_phi(lqgrid_ctx* c, const T* tau, T* out, int check) {
+  if (c->tv) tv_phi_solve<T>(c->D, tv_coef<T>(c), tau, out, c->sc, check, c->stream);
+  else phi_solve<T>(c->D, op_coef<T>(c), tau, out, c->sc, check, c->qt_distinct ? 1 : 0,
+                    c->stream);
+}
+void op_recover(lqgrid_ctx* c, const double* dl, double* x, double* u) {
+  if (c->tv) tv_recover(c->D, c->tv64, dl, x, u, c->stream);
+  else recover(c->D, c->C, dl, x, u, c->stream);
+}
+
 // q = P_S^-1 r by S outer x L inner NBJM sweeps (Alg. 2 with a fixed number
 // of sweeps, Theorem 2).  Returns the buffer holding the result (one of the
 // two theta buffers of the PCG instance).
@@ -291,7 +358,7 @@ T* precondition(lqgrid_ctx* c, const T* r, int S, int L, int check) {
     const T* rs = r;
     if (s > 0) {  // r_theta^(s) = r + Xi~ delta^(s)
       ProfScope ps(c, 2);
-      xi_rhs<T>(D, C, r, dprev, rho, c->sc, check, c->stream);
+      op_xi<T>(c, r, dprev, rho, check);
       rs = rho;
     }
     T* th = (dprev == thx) ? thy : thx;
@@ -299,12 +366,11 @@ T* precondition(lqgrid_ctx* c, const T* r, int S, int L, int check) {
       const T* rhs = rs;
       if (l > 0) {  // tau = r_theta + Omega~ theta^(l)
         ProfScope ps(c, 2);
-        omega_rhs<T>(D, C, rs, th, tau, c->sc, check, c->stream);
+        op_omega<T>(c, rs, th, tau, check);
         rhs = tau;
       }
       ProfScope ps(c, 1);
-      phi_solve<T>(D, C, rhs, th, c->sc, check, c->qt_distinct ? 1 : 0,
-                   c->stream);
+      op_phi<T>(c, rhs, th, check);
     }
     dprev = th;
   }
@@ -346,7 +412,7 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
       vec_dir<T>(D, q, d, sc, s);  // d = q + beta d (beta = 0 after init)
       {
         ProfScope ps(c, 0);
-        np = delta_apply<T>(D, C, d, y, c->psum, sc, 1, s);
+        np = op_delta<T>(c, d, y, c->psum, sc, 1);
       }
       scalar_step(kModeYd, c->psum, nullptr, np, sc, 0.0, s);
       {
@@ -387,8 +453,7 @@ void rhs_of(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc) {
 // r = r_delta - Delta dl (FP64), true residual norms into the outer scalars.
 void true_residual(lqgrid_ctx* c, const double* dl = nullptr) {
   const Dims& D = c->D;
-  delta_apply<double>(D, c->op64, dl ? dl : c->outer[kDl], c->outer[kYt], nullptr,
-                      c->sco, 0, c->stream);
+  op_delta<double>(c, dl ? dl : c->outer[kDl], c->outer[kYt], nullptr, c->sco, 0);
   const int np = vec_sub_norm(D, c->outer[kRd], c->outer[kYt], c->outer[kRt],
                               c->psum, c->pmax, c->stream);
   scalar_step(kModeTrue, c->psum, c->pmax, np, c->sco, 0.0, c->stream);
@@ -506,11 +571,13 @@ int check_problem(const lqgrid_problem_desc* desc, Dims* D) {
 // enqueues ingest and assembly into c (a fresh context).
 int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
                void* workspace, size_t workspace_bytes, void* hip_stream) {
-  const Plan P = make_plan(D);
+  const bool tv = desc->time_varying != 0;
+  const Plan P = make_plan(D, tv);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 ||
       workspace_bytes < P.total)
     return LQGRID_EWORKSPACE;
   c->D = D;
+  c->tv = tv;
   c->P = P;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ws = static_cast<char*>(workspace);
@@ -548,12 +615,39 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
   ProblemIn in{D.K, D.N, D.n, D.m, dp(P.inA), dp(P.inAnbr), dp(P.inB),
                dp(P.inQ), dp(P.inR), dp(P.inQT)};
   int* nsz = reinterpret_cast<int*>(w + P.nsz);
-  launch_ingest(D, user, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
   c->sized = desc->n_node != nullptr;
   c->nsz = nsz;
   c->Anbr = in.A_nbr;
-  launch_setup(D, in, c->C, c->sc, c->stream);
-  make_f32_blocks(c, false);
+  if (!tv) {
+    launch_ingest(D, user, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
+    launch_setup(D, in, c->C, c->sc, c->stream);
+    make_f32_blocks(c, false);
+  } else {
+    // time-varying data: each time slice s is ingested and assembled by the
+    // time-invariant kernels into the (scratch) blocks of c->C, then
+    // scattered into the time-fastest arrays: blocks of slice s at t = s
+    // (Cdn, Cup, AT5, R^-1 B', Q^-1) and t = s + 1 (the 13-point G); the
+    // terminal weight Q_T gives Q^-1 at t = T
+    c->tv64 = TvCoef<double>{dp(P.tG13), dp(P.tQi), dp(P.tCdn), dp(P.tCup), dp(P.tFw),
+                             dp(P.tBw), dp(P.tAT5), dp(P.tRiBT), dp(P.tW)};
+    c->tv32 = TvCoef<float>{fp(P.tG13f), fp(P.tQif), fp(P.tCdnf), fp(P.tCupf), fp(P.tFwf),
+                            fp(P.tBwf), nullptr, nullptr, fp(P.tWf)};
+    vec_zero<double>(dp(P.tG13), (long long)(P.tFw - P.tG13) / 8, c->stream);
+    vec_zero<double>(dp(P.tW), D.vlen, c->stream);
+    vec_zero<float>(fp(P.tWf), D.vlen, c->stream);
+    const size_t rn = (size_t)D.real_nodes, nn = (size_t)D.n * D.n;
+    const size_t sA = rn * nn, sN = rn * 4 * nn, sB = rn * D.n * D.m, sR = rn * D.m * D.m;
+    for (int s = 0; s <= D.T; ++s) {
+      const int sl = s < D.T ? s : D.T - 1;  // data slice (the terminal step: Q_T)
+      const double* Qs = desc->Q + sl * sA;
+      if (s == D.T && desc->QT) Qs = desc->QT;
+      ProblemIn us{D.K, D.N, D.n, D.m, desc->A + sl * sA, desc->A_nbr + sl * sN,
+                   desc->B + sl * sB, Qs, desc->R + sl * sR, Qs};
+      launch_ingest(D, us, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
+      launch_setup(D, in, c->C, c->sc, c->stream);
+      tv_scatter(D, c->C, c->tv64, s, s == D.T ? 1 : 0, c->stream);
+    }
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "lqgrid_setup launch");
   return LQGRID_OK;
@@ -596,7 +690,7 @@ size_t lqgrid_workspace_bytes(const lqgrid_problem_desc* desc,
   (void)opts;
   Dims D;
   if (!make_dims(desc, &D)) return 0;
-  return make_plan(D).total;
+  return make_plan(D, desc->time_varying != 0).total;
 }
 
 int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
@@ -623,11 +717,39 @@ int lqgrid_factor(lqgrid_ctx* c) {
   // entries never written by the factorisation (padding, N1/N2 of the last
   // block rows) must read as zero
   const long long NB = 2 * c->D.n;
-  vec_zero<double>(c->C.Fw, 2LL * c->D.V * fw_rows(c->D.K) * NB * kFwRow, c->stream);
-  vec_zero<double>(c->C.Bw, 2LL * c->D.V * c->D.K * NB * kBwRow, c->stream);
-  vec_zero<double>(c->C.Xw, 2LL * c->D.V * NB * kFwRow, c->stream);
-  launch_factor(c->D, c->C, c->sc, c->stream);
-  make_f32_blocks(c, true);
+  if (c->tv) {
+    // one-chain factorisation of every Phi_bar_{v,t}, t = 0..T, written in
+    // the time-fastest table layout; FP32 copies for the precision form
+    const Dims& D = c->D;
+    const Plan& P = c->P;
+    char* w = c->ws;
+    auto dp = [&](size_t off) { return reinterpret_cast<double*>(w + off); };
+    auto fp = [&](size_t off) { return reinterpret_cast<float*>(w + off); };
+    const long long L = (long long)D.nodes * D.ldt, nn = (long long)D.n * D.n;
+    const long long fwt = (long long)D.V * fw_rows(D.K) * kFwRow * D.ldt * 8;
+    const long long bwt = (long long)D.V * D.K * kBwRow * D.ldt * 8;
+    vec_zero<double>(dp(P.tFw), fwt, c->stream);
+    vec_zero<double>(dp(P.tBw), bwt, c->stream);
+    Coef F{};
+    F.G13 = dp(P.tG13);
+    F.Qi = dp(P.tQi);
+    F.Fw = dp(P.tFw);
+    F.Bw = dp(P.tBw);
+    F.tv_ld = D.ldt;
+    tv_factor(D, F, c->sc, c->stream);
+    copy_to_float(dp(P.tG13), fp(P.tG13f), L * 13 * nn, c->stream);
+    copy_to_float(dp(P.tQi), fp(P.tQif), L * nn, c->stream);
+    copy_to_float(dp(P.tCdn), fp(P.tCdnf), L * 5 * nn, c->stream);
+    copy_to_float(dp(P.tCup), fp(P.tCupf), L * 5 * nn, c->stream);
+    copy_to_float(dp(P.tFw), fp(P.tFwf), fwt, c->stream);
+    copy_to_float(dp(P.tBw), fp(P.tBwf), bwt, c->stream);
+  } else {
+    vec_zero<double>(c->C.Fw, 2LL * c->D.V * fw_rows(c->D.K) * NB * kFwRow, c->stream);
+    vec_zero<double>(c->C.Bw, 2LL * c->D.V * c->D.K * NB * kBwRow, c->stream);
+    vec_zero<double>(c->C.Xw, 2LL * c->D.V * NB * kFwRow, c->stream);
+    launch_factor(c->D, c->C, c->sc, c->stream);
+    make_f32_blocks(c, true);
+  }
   HIPCHECK(hipGetLastError());
   Scalars h;
   int st = read_scalars(c, c->sc, &h);
@@ -672,6 +794,8 @@ int pcg_solve_impl(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc,
   }
 
   // r_delta, ||r_delta||, tol^2 ||r_delta||^2 (outer scalars)
+  if (c->tv && bc && (bc->alpha_lo || bc->alpha_hi || bc->beta_lo || bc->beta_hi))
+    return LQGRID_EUNSUPPORTED;  // boundary couplings are kept for one time slice only
   rhs_of(c, x0, bc);
   int np = vec_norms<double>(D, c->outer[kRd], c->psum, c->pmax, s);
   scalar_step(kModeRd2, c->psum, c->pmax, np, c->sco, o.tol, s);
@@ -721,7 +845,7 @@ int pcg_solve_impl(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc,
     }
   }
   to_abi(D, c->outer[kDl], delta, s);
-  if (x || u) recover(D, c->C, c->outer[kDl], x, u, s);
+  if (x || u) op_recover(c, c->outer[kDl], x, u);
   float ms = 0.f;
   if (timed_events) {
     HIPCHECK(hipEventRecord(ev.b, s));
@@ -784,11 +908,11 @@ int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
     T* y = b.v[kY];
     vec_scale_to<T>(D, vin, 1.0, x, s);
     switch (op) {
-      case LQGRID_OP_DELTA: delta_apply<T>(D, C, x, y, nullptr, c->sc, 0, s); break;
-      case LQGRID_OP_XI: xi_rhs<T>(D, C, (const T*)nullptr, x, y, c->sc, 0, s); break;
-      case LQGRID_OP_OMEGA: omega_rhs<T>(D, C, (const T*)nullptr, x, y, c->sc, 0, s); break;
+      case LQGRID_OP_DELTA: op_delta<T>(c, x, y, nullptr, c->sc, 0); break;
+      case LQGRID_OP_XI: op_xi<T>(c, (const T*)nullptr, x, y, 0); break;
+      case LQGRID_OP_OMEGA: op_omega<T>(c, (const T*)nullptr, x, y, 0); break;
       case LQGRID_OP_PHI_SOLVE:
-        phi_solve<T>(D, C, x, y, c->sc, 0, c->qt_distinct ? 1 : 0, s);
+        op_phi<T>(c, x, y, 0);
         break;
       default: y = precondition<T>(c, x, S, L, 0); break;
     }
@@ -851,18 +975,16 @@ int lqgrid_nbjm_solve(lqgrid_ctx* c, const double* x0, const lqgrid_solve_opts* 
   double* rho = c->b64.v[kBufA];
   double* tau = c->b64.v[kBufB];
   vec_zero<double>(dcur, D.vlen, s);
-  const OpCoef<double>& C = c->op64;
-  const int qtd = c->qt_distinct ? 1 : 0;
   int sweeps = 0, status = LQGRID_OK;
   Scalars h{};
   for (;;) {
     // delta^(s+1): rho = r_delta + Xi~ delta^(s); the inner iteration starts
     // from theta^(0) = delta^(s), theta^(l+1) = Phi~^-1 (rho + Omega~ theta^(l))
-    xi_rhs<double>(D, C, rd, dcur, rho, c->sc, 0, s);
+    op_xi<double>(c, rd, dcur, rho, 0);
     const double* th = dcur;
     for (int l = 0; l < o.inner_L; ++l) {
-      omega_rhs<double>(D, C, rho, th, tau, c->sc, 0, s);
-      phi_solve<double>(D, C, tau, dnext, c->sc, 0, qtd, s);
+      op_omega<double>(c, rho, th, tau, 0);
+      op_phi<double>(c, tau, dnext, 0);
       th = dnext;
     }
     std::swap(dcur, dnext);
@@ -884,7 +1006,7 @@ int lqgrid_nbjm_solve(lqgrid_ctx* c, const double* x0, const lqgrid_solve_opts* 
     }
   }
   to_abi(D, dcur, delta, s);
-  if (x || u) recover(D, c->C, dcur, x, u, s);
+  if (x || u) op_recover(c, dcur, x, u);
   HIPCHECK(hipStreamSynchronize(s));
   HIPCHECK(hipGetLastError());
   if (info) {
@@ -964,7 +1086,7 @@ int lqgrid_solve_noalloc(const lqgrid_problem_desc* desc, const double* x0,
   Dims D;
   const int chk = check_problem(desc, &D);
   if (chk != LQGRID_OK) return chk;
-  const size_t need = make_plan(D).total;
+  const size_t need = make_plan(D, desc->time_varying != 0).total;
   if (need > kNoAllocBytes) {
     std::snprintf(g_last_error, sizeof(g_last_error),
                   "lqgrid_solve_noalloc: the problem needs %zu bytes of scratch, "

@@ -449,7 +449,8 @@ int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
     const lqgrid_problem_desc& d = descs[p];
     if (!d.A || !d.A_nbr || !d.B || !d.Q || !d.R || !x0s[p] || !deltas[p])
       return LQGRID_EINVAL;
-    if (d.n_node || d.m_node) return LQGRID_EUNSUPPORTED;  // uniform sizes only
+    if (d.n_node || d.m_node || d.time_varying)  // uniform, time-invariant only
+      return LQGRID_EUNSUPPORTED;
     if (Ds[p].n != Ds[0].n) return LQGRID_EUNSUPPORTED;
     if (Ds[p].n > kMaxN || Ds[p].m > kMaxM) return LQGRID_EUNSUPPORTED;
     if (Ds[p].vlen * 8 >= (1LL << 31)) return LQGRID_EUNSUPPORTED;

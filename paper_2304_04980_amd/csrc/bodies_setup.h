@@ -233,10 +233,37 @@ __device__ inline double phi_entry(const Dims& D, const Coef& C, int cls, int v,
   if (k < 0) return 0.0;
   const size_t p = (size_t)j * K + i;
   const size_t nn = (size_t)n * n;
+  if (C.tv_ld) {  // time-varying data: class cls is the time t, t fastest
+    const size_t ld = (size_t)C.tv_ld;
+    double val = C.G13[((p * 13 + k) * nn + a * n + b) * ld + cls];
+    if (di == 0 && h == h2) val += C.Qi[(p * nn + a * n + b) * ld + cls];
+    return val;
+  }
   double val = C.G13[(p * 13 + k) * nn + a * n + b];
   if (di == 0 && h == h2)
     val += (cls == 0 ? C.Qi : C.QTi)[p * nn + a * n + b];
   return val;
+}
+
+// Addresses of entry (row r, column k) of block row `row` of the forward
+// (kFwRow columns) and backward (kBwRow columns) factor tables of class cls,
+// super-column v: [cls][v][row][r][k] for time-invariant data, and for
+// time-varying data [v][row][k][t][r8] (t = cls, 8 rows per time step)
+// so that the eight row threads of eight time steps read one coalesced
+// segment per column.
+__device__ inline double* fw_at(const Dims& D, const Coef& C, int cls, int v, int row,
+                                int r, int k) {
+  if (C.tv_ld)
+    return C.Fw + ((((size_t)v * fw_rows(D.K) + row) * kFwRow + k) * C.tv_ld + cls) * 8 + r;
+  const size_t frows = ((size_t)cls * D.V + v) * fw_rows(D.K);
+  return C.Fw + ((frows + row) * (2 * D.n) + r) * kFwRow + k;
+}
+__device__ inline double* bw_at(const Dims& D, const Coef& C, int cls, int v, int row,
+                                int r, int k) {
+  if (C.tv_ld)
+    return C.Bw + ((((size_t)v * D.K + row) * kBwRow + k) * C.tv_ld + cls) * 8 + r;
+  const size_t rows = ((size_t)cls * D.V + v) * D.K;
+  return C.Bw + ((rows + row) * (2 * D.n) + r) * kBwRow + k;
 }
 
 // Cholesky factor L of the SPD NB x NB block Dm (shared memory, row-major)
@@ -357,16 +384,13 @@ __device__ inline void factor(const Dims& D, const Coef& C, Scalars* sc, int v,
         n1 += Lp1[k * NB + r] * L1[c * NB + k];   // Linv_{i-1}' L_{i,i-1}'
         n2 += Lp2[k * NB + r] * L2[c * NB + k];   // Linv_{i-2}' L_{i,i-2}'
       }
-      const size_t rows = ((size_t)cls * D.V + v) * K;         // Bw rows of (cls, v)
-      const size_t frows = ((size_t)cls * D.V + v) * fw_rows(K);  // Fw rows of (cls, v)
-      double* fw = C.Fw + ((frows + i) * NB + r) * kFwRow;
-      fw[c] = m1;
-      fw[8 + c] = m2;
-      fw[16 + c] = Li[r * NB + c];
+      *fw_at(D, C, cls, v, i, r, c) = m1;
+      *fw_at(D, C, cls, v, i, r, 8 + c) = m2;
+      *fw_at(D, C, cls, v, i, r, 16 + c) = Li[r * NB + c];
       // Linv_i' is used one block row later (w_i needs all of z_i)
-      C.Fw[((frows + i + 1) * NB + r) * kFwRow + 24 + c] = Li[c * NB + r];
-      if (i >= 1) C.Bw[((rows + i - 1) * NB + r) * kBwRow + c] = n1;
-      if (i >= 2) C.Bw[((rows + i - 2) * NB + r) * kBwRow + 8 + c] = n2;
+      *fw_at(D, C, cls, v, i + 1, r, 24 + c) = Li[c * NB + r];
+      if (i >= 1) *bw_at(D, C, cls, v, i - 1, r, c) = n1;
+      if (i >= 2) *bw_at(D, C, cls, v, i - 2, r, 8 + c) = n2;
     }
     __syncthreads();
     if (act) {

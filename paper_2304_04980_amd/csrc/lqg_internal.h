@@ -71,6 +71,11 @@ struct Coef {
   double *Qi, *QTi, *QTd, *Qm, *RiBT;
   double *Fw, *Bw;  // factors in the substitution layout
   double* Xw;       // middle-row couplings of the twisted factorisation
+  // Time-varying data (0: the layouts above).  Otherwise the class of a
+  // factorisation is the time t = 0..T and the one-chain factorisation reads
+  // G13 / Qi and writes Fw / Bw in the time-fastest layouts of the
+  // time-varying operator (see tv.hip), with this leading dimension (ldt).
+  long long tv_ld = 0;
 };
 
 // The operator blocks the hot kernels read, in the element type of the

@@ -588,6 +588,7 @@ int lqgrid_wsnet_features(const lqgrid_wsnet_desc* d, const lqgrid_problem_desc*
     return LQGRID_EINVAL;
   if (prob->K != s.K || prob->N != s.N || prob->n != s.n || prob->m != s.m)
     return LQGRID_EINVAL;
+  if (prob->time_varying || prob->n_node || prob->m_node) return LQGRID_EUNSUPPORTED;
   clear_stale_error();
   hipLaunchKernelGGL(k_features, dim3((s.P + 255) / 256), dim3(256), 0,
                      reinterpret_cast<hipStream_t>(stream), s.P, s.n, s.m, prob->A,

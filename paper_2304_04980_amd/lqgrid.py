@@ -25,7 +25,8 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("K", c_int), ("N", c_int), ("T", c_int), ("n", c_int),
                 ("m", c_int), ("A", c_void_p), ("A_nbr", c_void_p),
                 ("B", c_void_p), ("Q", c_void_p), ("R", c_void_p),
-                ("QT", c_void_p), ("n_node", c_void_p), ("m_node", c_void_p)]
+                ("QT", c_void_p), ("n_node", c_void_p), ("m_node", c_void_p),
+                ("time_varying", c_int)]
 
 
 class Boundary(ctypes.Structure):
@@ -198,17 +199,19 @@ def _stream():
     return c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def workspace_bytes(K, N, T, n, m) -> int:
-    d = ProblemDesc(K, N, T, n, m, None, None, None, None, None, None)
+def workspace_bytes(K, N, T, n, m, time_varying=False) -> int:
+    d = ProblemDesc(K, N, T, n, m, None, None, None, None, None, None, None, None,
+                    1 if time_varying else 0)
     return load().lqgrid_workspace_bytes(byref(d), None)
 
 
 def problem_desc(K, N, T, n, m, A, A_nbr, B, Q, R, QT=None, n_node=None,
-                 m_node=None) -> ProblemDesc:
+                 m_node=None, time_varying=False) -> ProblemDesc:
     """Tensors must be contiguous float64 (sizes: int32) CUDA tensors in the
     header's layouts; the caller keeps them alive while the setup work runs."""
     return ProblemDesc(K, N, T, n, m, _ptr(A), _ptr(A_nbr), _ptr(B), _ptr(Q),
-                       _ptr(R), _ptr(QT), _ptr(n_node), _ptr(m_node))
+                       _ptr(R), _ptr(QT), _ptr(n_node), _ptr(m_node),
+                       1 if time_varying else 0)
 
 
 class Context:
@@ -236,7 +239,8 @@ class Context:
         self.arrays = arrays
         a = self.arrays
         self.desc = problem_desc(*self.dims, a["A"], a["A_nbr"], a["B"], a["Q"],
-                                 a["R"], a["QT"], a.get("n_node"), a.get("m_node"))
+                                 a["R"], a["QT"], a.get("n_node"), a.get("m_node"),
+                                 getattr(p, "time_varying", False))
         nbytes = self.L.lqgrid_workspace_bytes(byref(self.desc), None)
         if nbytes == 0:
             raise LqgridError(EINVAL, "lqgrid_workspace_bytes")

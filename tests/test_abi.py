@@ -30,7 +30,7 @@ def test_library_exports_every_header_symbol():
     L = lqgrid.load()
     for name in header_symbols():
         assert hasattr(L, name), name
-    assert L.lqgrid_abi_version() == 2
+    assert L.lqgrid_abi_version() == 3
 
 
 def _desc(K=4, N=4, T=5, n=2, m=1, ptr=8):
