@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblqgrid.so")
 SOURCES = ["setup.hip", "ops.hip", "vec.hip", "batch.hip", "api.hip", "batch_api.hip", "warm.hip",
-           "tv.hip"]
+           "tv.hip", "nt.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -548,3 +548,40 @@ def test_heterogeneous_sizes(seed):
         assert np.abs(got - h[key]).max() <= 1e-11 * np.abs(h[key]).max()
     gotu = padded["u"].reshape(T, N, K, p.m)
     assert np.abs(gotu - h["u"]).max() <= 1e-11 * np.abs(h["u"]).max()
+
+
+# ------------------------------------------------ node-temporal nesting
+@pytest.mark.parametrize("case", [("tiny", False), ("spd", False), ("tv", True)])
+def test_node_temporal_preconditioner(case):
+    """The node-temporal block Jacobi preconditioner (oracle/nodetemporal.py,
+    per-node banded Cholesky in t) equals the inverse of the node-diagonal
+    part of the explicit Delta, which is symmetric positive definite; PCG with
+    it converges to the dense solution in fewer iterations than plain CG; for
+    a single node it is Delta itself, so PCG takes one step."""
+    from oracle import nodetemporal
+    import scipy.sparse.linalg as spla
+    kind, tv = case
+    if kind == "tiny":
+        p, _ = config_problem("tiny", 1)
+    else:
+        p = make_problem(3, 5, 8, 3, 2, seed=4, weights="spd", qt_scale=1.5, time_varying=tv)
+    ops = slab.SlabOperators(p)
+    D = stack.delta_matrix(p)
+    Dn = nodetemporal.node_blocks_dense(p, D)
+    Dd = Dn.toarray()
+    assert np.abs(Dd - Dd.T).max() <= 1e-14 * np.abs(Dd).max()
+    assert np.linalg.eigvalsh(Dd).min() > 0
+    P = nodetemporal.NodeTemporal(ops)
+    r = np.random.default_rng(3).standard_normal((p.T + 1, p.K * p.N * p.n))
+    ref = spla.spsolve(Dn.tocsc(), r.ravel())
+    assert np.abs(P(r).ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+    rd = ops.r_delta()
+    x, it, _ = pcg.pcg(ops.delta, P, rd, tol=1e-10)
+    _, itc, _ = pcg.cg(ops.delta, rd, tol=1e-10)
+    ds = kkt.solve_schur_dense(p).reshape(rd.shape)
+    assert np.linalg.norm(x - ds) <= 1e-7 * np.linalg.norm(ds)
+    assert it < itc
+    q = make_problem(1, 1, 25, 3, 2, seed=2, weights="spd", time_varying=tv)
+    oq = slab.SlabOperators(q)
+    _, it1, _ = pcg.pcg(oq.delta, nodetemporal.NodeTemporal(oq), oq.r_delta(), tol=1e-12)
+    assert it1 == 1
