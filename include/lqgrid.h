@@ -70,6 +70,22 @@ typedef enum {
   LQGRID_FP32_REFINE = 1  /* FP32 operator/sweeps inside FP64 iterative refinement */
 } lqgrid_precision;
 
+/* Preconditioner of Algorithm 1. */
+typedef enum {
+  /* The paper's: S outer x L inner nested block Jacobi sweeps of Algorithm 2
+   * (time split first, then column pairs; per (v, t) solves along the rows). */
+  LQGRID_PRECOND_NBJM = 0,
+  /* The alternative nesting: one block Jacobi sweep over the grid nodes with
+   * each node's whole temporal block of Delta (block tridiagonal in t, its
+   * blocks Psi_hat_t[p,p] and Delta_{t+1,t}[p,p] = -A_hat_t[p,p] Q_{t,p}^-1),
+   * solved exactly by a block Cholesky in t.  That part of Delta is positive
+   * definite, so P is too.  Needs the workspace sized with this choice in
+   * opts (lqgrid_workspace_bytes), else the solve returns LQGRID_EWORKSPACE. */
+  LQGRID_PRECOND_NODE_TEMPORAL = 1,
+  /* P = I: plain conjugate gradients. */
+  LQGRID_PRECOND_NONE = 2
+} lqgrid_preconditioner;
+
 /* One problem (Sec. II, eq. "2d_graph_dynamics" and the LQ problem):
  *   x_{i,j,t+1} = A x_{i,j,t} + B u_{i,j,t} + E x_{i,j-1,t} + F x_{i,j+1,t}
  *                 + G x_{i-1,j,t} + H x_{i+1,j,t}
@@ -118,9 +134,16 @@ typedef struct {
   double inner_tol;   /* FP32_REFINE: relative tolerance of each inner solve
                          (<= 0: 1e-5)                                            */
   int check_every;    /* iterations between host convergence reads (<= 0: 8)    */
-  int warm_fallback;  /* with delta_init: if ||r_delta - Delta delta_init|| >=
-                         ||r_delta|| start from zero instead (the warm start
-                         is then no better than none)                        */
+  int warm_fallback;  /* with delta_init: 0 use it as given; 1 start from zero
+                         instead if ||r_delta - Delta delta_init|| >= ||r_delta||
+                         (the warm start is then no better than none); 2
+                         energy line search: start from alpha delta_init,
+                         alpha = delta_init' r_delta / (delta_init' Delta
+                         delta_init), which minimises the Delta-norm of the
+                         error along delta_init (so it is never larger than
+                         the zero start's), or from zero if alpha <= 0       */
+  int preconditioner; /* lqgrid_preconditioner (default NBJM); S and L apply to
+                         NBJM only (ABI 3)                                     */
 } lqgrid_solve_opts;
 
 typedef struct {
@@ -139,7 +162,10 @@ LQGRID_API void lqgrid_default_opts(lqgrid_solve_opts *opts);
 
 /* Bytes of device workspace that lqgrid_setup needs for this problem (0 if
  * the description is invalid); it covers both precisions.  Workspace must be
- * 256-byte aligned.  opts is unused and may be NULL. */
+ * 256-byte aligned.  opts may be NULL; with opts->preconditioner ==
+ * LQGRID_PRECOND_NODE_TEMPORAL the size includes that preconditioner's
+ * factor tables (a setup given at least that much workspace factors them in
+ * lqgrid_factor and can use either preconditioner). */
 LQGRID_API size_t lqgrid_workspace_bytes(const lqgrid_problem_desc *desc,
                               const lqgrid_solve_opts *opts);
 
@@ -236,6 +262,7 @@ typedef enum {
   LQGRID_OP_OMEGA = 2,
   LQGRID_OP_PHI_SOLVE = 3,
   LQGRID_OP_PRECOND = 4,
+  LQGRID_OP_NODE_PRECOND = 5, /* out = D_node^-1 in (LQGRID_PRECOND_NODE_TEMPORAL) */
   LQGRID_OP_F32 = 16
 } lqgrid_op;
 LQGRID_API int lqgrid_apply_operator(lqgrid_ctx *ctx, int op, int outer_S, int inner_L,
@@ -307,6 +334,16 @@ LQGRID_API int lqgrid_wsnet_gradient(const lqgrid_wsnet_desc *desc, int batch,
                                      const int *index, const float *params, float *grad,
                                      double *loss, void *workspace,
                                      size_t workspace_bytes, void *hip_stream);
+/* Gradient with respect to params of a loss whose gradient with respect to
+ * the network output is dout (FP32 [batch][K N][64], rounded to BF16 like
+ * the back-propagated gradients): the backward pass of lqgrid_wsnet_gradient
+ * from a given output gradient, for losses formed outside the network (e.g.
+ * from operator products) and for exact tests. */
+LQGRID_API int lqgrid_wsnet_backward(const lqgrid_wsnet_desc *desc, int batch,
+                                     const void *feats, const int *index,
+                                     const float *params, const float *dout, float *grad,
+                                     void *workspace, size_t workspace_bytes,
+                                     void *hip_stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8); moments: 2 x param_count
  * FP32, zero before step 1. */
 LQGRID_API int lqgrid_wsnet_adam(const lqgrid_wsnet_desc *desc, float *params,
@@ -340,7 +377,8 @@ LQGRID_API int lqgrid_nbjm_solve(lqgrid_ctx *ctx, const double *x0,
  * compares kappa(Delta) with kappa(P_S^-1/2 Delta P_S^-1/2)).  Runs one FP64
  * Algorithm 1 from zero on Delta delta = r_delta(x0) to the relative
  * tolerance tol (at most max_iter <= 8192 iterations; <= 0: 8192) with the
- * S x L NBJM preconditioner (preconditioned != 0) or P = I (plain CG), and
+ * S x L NBJM preconditioner (preconditioned = 1), the node-temporal one
+ * (preconditioned = 2) or P = I (preconditioned = 0, plain CG), and
  * returns the extreme eigenvalues of the Lanczos matrix built from its step
  * lengths theta_k and direction coefficients beta_k (diagonal 1/theta_k +
  * beta_{k-1}/theta_{k-1}, off-diagonal sqrt(beta_k)/theta_k), which converge

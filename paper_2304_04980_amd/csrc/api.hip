@@ -26,6 +26,7 @@
 
 #include "api_common.h"
 #include "tv.h"
+#include "nt.h"
 
 using namespace lqg;
 
@@ -40,6 +41,7 @@ enum PcgVec { kX, kR, kD, kY, kBufA, kBufB, kBufC, kBufD, kNumPcg };
 struct Plan {
   size_t G13, Cdn, Cup, AT5, Qi, QTi, QTd, Qm, RiBT, Fw, Bw, Xw;
   size_t G13f, Cdnf, Cupf, Qif, QTdf, Qmf, Fwf, Bwf, Xwf;
+  size_t A5, BRB, A5f, BRBf, W64, W32;  // the factored Delta apply
   size_t outer[kNumOuter], p64[kNumPcg], p32[kNumPcg];
   size_t psum, pmax, scal, scal_outer, hist;
   size_t inA, inAnbr, inB, inQ, inQT, inR, nsz;  // ingested (size-masked) arrays
@@ -47,6 +49,7 @@ struct Plan {
   size_t tG13, tQi, tCdn, tCup, tAT5, tRiBT, tFw, tBw, tW;
   size_t tG13f, tQif, tCdnf, tCupf, tFwf, tBwf, tWf;
   bool tv;
+  size_t nt64, nt32, total_nt;  // node-temporal tables, past `total` (opt-in)
   int npartial;
   size_t total;
 };
@@ -99,6 +102,12 @@ Plan make_plan(const Dims& D, bool tv) {
   P.Fwf = take(fw * 4);
   P.Bwf = take(bw * 4);
   P.Xwf = take(xw * 4);
+  P.A5 = take(nodes * 5 * nn * 8);
+  P.BRB = take(nodes * nn * 8);
+  P.A5f = take(nodes * 5 * nn * 4);
+  P.BRBf = take(nodes * nn * 4);
+  P.W64 = take((size_t)D.vlen * 8);
+  P.W32 = take((size_t)D.vlen * 4);
   const int apply_blocks = padded_grid(((D.real_nodes + 3) / 4) * ((D.Tt + 63) / 64));
   P.npartial = std::max(apply_blocks, kFlatBlocks);
   if (tv) {
@@ -129,6 +138,9 @@ Plan make_plan(const Dims& D, bool tv) {
   for (int v = 0; v < kNumPcg; ++v) P.p64[v] = take((size_t)D.vlen * 8);
   for (int v = 0; v < kNumPcg; ++v) P.p32[v] = take((size_t)D.vlen * 4);
   P.total = off;
+  P.nt64 = take(nt_table_doubles(D) * 8);
+  P.nt32 = take(nt_table_doubles(D) * 4);
+  P.total_nt = off;
   return P;
 }
 
@@ -155,7 +167,9 @@ struct lqgrid_ctx {
   double *psum, *pmax;
   bool factored = false;
   bool qt_distinct = false;
-  bool precond_identity = false;  // P = I in Algorithm 1 (plain CG)
+  int pmode = LQGRID_PRECOND_NBJM;  // preconditioner of the running solve
+  bool nt_ok = false;   // the workspace holds the node-temporal tables
+  bool nt_factored = false;
   bool sized = false;     // per-node sizes given: x0 is masked by nsz
   bool rd_dirty = false;  // r_delta holds boundary terms of an earlier solve
   const int* nsz = nullptr;       // per-node state sizes (workspace copy)
@@ -275,7 +289,8 @@ void opts_fill(const lqgrid_solve_opts* in, lqgrid_solve_opts* o) {
 bool opts_valid(const lqgrid_solve_opts& o) {
   return o.outer_S >= 1 && o.inner_L >= 2 && (o.inner_L % 2) == 0 &&
          o.tol > 0 && std::isfinite(o.tol) &&
-         (o.precision == LQGRID_FP64 || o.precision == LQGRID_FP32_REFINE);
+         (o.precision == LQGRID_FP64 || o.precision == LQGRID_FP32_REFINE) &&
+         o.preconditioner >= LQGRID_PRECOND_NBJM && o.preconditioner <= LQGRID_PRECOND_NONE;
 }
 
 }  // namespace lqg
@@ -345,8 +360,25 @@ void op_recover(lqgrid_ctx* c, const double* dl, double* x, double* u) {
 // of sweeps, Theorem 2).  Returns the buffer holding the result (one of the
 // two theta buffers of the PCG instance).
 template <typename T>
+const T* nt_tab(const lqgrid_ctx* c);
+template <>
+const double* nt_tab<double>(const lqgrid_ctx* c) {
+  return reinterpret_cast<const double*>(c->ws + c->P.nt64);
+}
+template <>
+const float* nt_tab<float>(const lqgrid_ctx* c) {
+  return reinterpret_cast<const float*>(c->ws + c->P.nt32);
+}
+
+template <typename T>
 T* precondition(lqgrid_ctx* c, const T* r, int S, int L, int check) {
   const Dims& D = c->D;
+  if (c->pmode == LQGRID_PRECOND_NODE_TEMPORAL) {  // one node-temporal Jacobi sweep
+    T* q = pcg_bufs<T>(c).v[kBufC];
+    ProfScope ps(c, 1);
+    nt_solve<T>(D, nt_tab<T>(c), r, q, c->sc, check, c->stream);
+    return q;
+  }
   const OpCoef<T>& C = op_coef<T>(c);
   PcgBufs<T>& b = pcg_bufs<T>(c);
   T* rho = b.v[kBufA];
@@ -401,7 +433,8 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
   HIPCHECK(hipMemcpyAsync(&sc->iter, c->host_iter, 2 * sizeof(int),
                           hipMemcpyHostToDevice, s));
   // P = I (plain CG): q aliases r, every read of q sees the current residual
-  T* q = c->precond_identity ? r : precondition<T>(c, r, S, L, 0);
+  const bool ident = c->pmode == LQGRID_PRECOND_NONE;
+  T* q = ident ? r : precondition<T>(c, r, S, L, 0);
   np = vec_dot<T>(D, q, r, c->psum, sc, 0, s);
   scalar_step(kModeMuInit, c->psum, nullptr, np, sc, 0.0, s);
   vec_zero<T>(d, D.vlen, s);
@@ -420,7 +453,7 @@ int pcg_core(lqgrid_ctx* c, double tol_rel, int max_iter, int check_every,
         np = vec_update<T>(D, d, y, x, r, c->psum, sc, s);
       }
       scalar_step(kModeRr, c->psum, nullptr, np, sc, 0.0, s);
-      if (!c->precond_identity) q = precondition<T>(c, r, S, L, 1);
+      if (!ident) q = precondition<T>(c, r, S, L, 1);
       np = vec_dot<T>(D, q, r, c->psum, sc, 1, s);
       scalar_step(kModeMu, c->psum, nullptr, np, sc, 0.0, s);
     }
@@ -488,6 +521,8 @@ void make_f32_blocks(lqgrid_ctx* c, bool factors) {
     copy_to_float(c->C.Qi, fp(P.Qif), nodes * nn, c->stream);
     copy_to_float(c->C.QTd, fp(P.QTdf), nodes * nn, c->stream);
     copy_to_float(c->C.Qm, fp(P.Qmf), nodes * nn, c->stream);
+    copy_to_float(c->C.A5, fp(P.A5f), nodes * 5 * nn, c->stream);
+    copy_to_float(c->C.BRB, fp(P.BRBf), nodes * nn, c->stream);
   } else {
     copy_to_float(c->C.Fw, fp(P.Fwf), 2LL * D.V * fw_rows(D.K) * NB * kFwRow, c->stream);
     copy_to_float(c->C.Bw, fp(P.Bwf), 2LL * D.V * D.K * NB * kBwRow, c->stream);
@@ -578,6 +613,7 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
     return LQGRID_EWORKSPACE;
   c->D = D;
   c->tv = tv;
+  c->nt_ok = workspace_bytes >= P.total_nt;
   c->P = P;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ws = static_cast<char*>(workspace);
@@ -588,10 +624,14 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
   c->sco = reinterpret_cast<Scalars*>(w + P.scal_outer);
   c->C = Coef{dp(P.G13), dp(P.Cdn), dp(P.Cup), dp(P.AT5), dp(P.Qi), dp(P.QTi),
               dp(P.QTd), dp(P.Qm), dp(P.RiBT), dp(P.Fw), dp(P.Bw), dp(P.Xw)};
+  c->C.A5 = dp(P.A5);
+  c->C.BRB = dp(P.BRB);
   c->op64 = OpCoef<double>{c->C.G13, c->C.Cdn, c->C.Cup, c->C.Qi, c->C.QTd,
-                           c->C.Qm, c->C.Fw, c->C.Bw, c->C.Xw};
+                           c->C.Qm, c->C.Fw, c->C.Bw, c->C.Xw,
+                           c->C.A5, c->C.BRB, dp(P.W64)};
   c->op32 = OpCoef<float>{fp(P.G13f), fp(P.Cdnf), fp(P.Cupf), fp(P.Qif),
-                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf), fp(P.Xwf)};
+                          fp(P.QTdf), fp(P.Qmf), fp(P.Fwf), fp(P.Bwf), fp(P.Xwf),
+                          fp(P.A5f), fp(P.BRBf), fp(P.W32)};
   for (int v = 0; v < kNumOuter; ++v) c->outer[v] = dp(P.outer[v]);
   for (int v = 0; v < kNumPcg; ++v) {
     c->b64.v[v] = dp(P.p64[v]);
@@ -607,6 +647,8 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
     vec_zero<double>(c->b64.v[v], D.vlen, c->stream);
     vec_zero<float>(c->b32.v[v], D.vlen, c->stream);
   }
+  vec_zero<double>(dp(P.W64), D.vlen, c->stream);
+  vec_zero<float>(fp(P.W32), D.vlen, c->stream);
   // ingest: copies of the problem arrays, padded where a node is smaller than
   // n, m (a plain copy for uniform sizes); the setup reads only the copies,
   // and the coupling blocks stay for the boundary terms of later solves
@@ -667,6 +709,7 @@ void lqgrid_default_opts(lqgrid_solve_opts* o) {
   o->inner_tol = 1e-5;
   o->check_every = 8;
   o->warm_fallback = 1;
+  o->preconditioner = LQGRID_PRECOND_NBJM;
 }
 
 int lqgrid_abi_version(void) { return LQGRID_ABI_VERSION; }
@@ -687,10 +730,10 @@ const char* lqgrid_status_string(int s) {
 
 size_t lqgrid_workspace_bytes(const lqgrid_problem_desc* desc,
                               const lqgrid_solve_opts* opts) {
-  (void)opts;
   Dims D;
   if (!make_dims(desc, &D)) return 0;
-  return make_plan(D, desc->time_varying != 0).total;
+  const Plan P = make_plan(D, desc->time_varying != 0);
+  return (opts && opts->preconditioner == LQGRID_PRECOND_NODE_TEMPORAL) ? P.total_nt : P.total;
 }
 
 int lqgrid_setup(const lqgrid_problem_desc* desc, void* workspace,
@@ -750,6 +793,13 @@ int lqgrid_factor(lqgrid_ctx* c) {
     launch_factor(c->D, c->C, c->sc, c->stream);
     make_f32_blocks(c, true);
   }
+  if (c->nt_ok) {  // node-temporal tables (workspace sized for them)
+    double* t64 = reinterpret_cast<double*>(c->ws + c->P.nt64);
+    nt_factor(c->D, c->C, c->tv64, c->tv ? 1 : 0, t64, c->sc, c->stream);
+    copy_to_float(t64, reinterpret_cast<float*>(c->ws + c->P.nt32),
+                  (long long)nt_table_doubles(c->D), c->stream);
+    c->nt_factored = true;
+  }
   HIPCHECK(hipGetLastError());
   Scalars h;
   int st = read_scalars(c, c->sc, &h);
@@ -775,6 +825,9 @@ int pcg_solve_impl(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc,
   lqgrid_solve_opts o;
   opts_fill(opts_in, &o);
   if (!opts_valid(o) || !c->factored) return LQGRID_EINVAL;
+  if (o.preconditioner == LQGRID_PRECOND_NODE_TEMPORAL && !c->nt_factored)
+    return LQGRID_EWORKSPACE;
+  c->pmode = o.preconditioner;
   const Dims& D = c->D;
   hipStream_t s = c->stream;
   clear_stale_error();
@@ -805,11 +858,32 @@ int pcg_solve_impl(lqgrid_ctx* c, const double* x0, const lqgrid_boundary* bc,
   int status = LQGRID_OK, total_it = 0, passes = 0;
   bool warm = delta_init != nullptr;
   Scalars h{};
+  if (warm && o.warm_fallback == 2) {
+    // energy line search along the warm start: delta^(0) = alpha delta_init
+    // with alpha = delta_init' r_delta / (delta_init' Delta delta_init), the
+    // minimiser of the Delta-norm of the error on that line (Sec. III: the
+    // norm PCG reduces), never larger than the zero start's
+    op_delta<double>(c, c->outer[kDl], c->outer[kYt], c->psum, c->sco, 0);
+    int nb = vec_dot<double>(D, c->outer[kDl], c->outer[kYt], c->psum, c->sco, 0, s);
+    scalar_step(kModeDotB, c->psum, nullptr, nb, c->sco, 0.0, s);
+    nb = vec_dot<double>(D, c->outer[kDl], c->outer[kRd], c->psum, c->sco, 0, s);
+    scalar_step(kModeDotA, c->psum, nullptr, nb, c->sco, 0.0, s);
+    const int st = read_scalars(c, c->sco, &h);
+    if (st != LQGRID_OK) return st;
+    const double alpha = h.mu / h.yd;
+    if (h.yd > 0.0 && std::isfinite(alpha) && alpha > 0.0) {
+      vec_scale_to<double>(D, c->outer[kDl], alpha, c->outer[kRt], s);
+      vec_scale_to<double>(D, c->outer[kRt], 1.0, c->outer[kDl], s);
+    } else {
+      vec_zero<double>(c->outer[kDl], D.vlen, s);
+      warm = false;
+    }
+  }
   for (;;) {
     true_residual(c);
     int st = read_scalars(c, c->sco, &h);
     if (st != LQGRID_OK) return st;
-    if (warm && passes == 0 && o.warm_fallback && !(h.rr < h.rd2)) {
+    if (warm && passes == 0 && o.warm_fallback == 1 && !(h.rr < h.rd2)) {
       // the warm start does not lower the residual: start from zero
       vec_zero<double>(c->outer[kDl], D.vlen, s);
       warm = false;
@@ -893,9 +967,9 @@ int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
   clear_stale_error();
   const bool f32 = (op & kOpF32) != 0;
   op &= ~kOpF32;
-  if (op < LQGRID_OP_DELTA || op > LQGRID_OP_PRECOND) return LQGRID_EINVAL;
-  if ((op == LQGRID_OP_PHI_SOLVE || op == LQGRID_OP_PRECOND) && !c->factored)
-    return LQGRID_EINVAL;
+  if (op < LQGRID_OP_DELTA || op > LQGRID_OP_NODE_PRECOND) return LQGRID_EINVAL;
+  if (op >= LQGRID_OP_PHI_SOLVE && !c->factored) return LQGRID_EINVAL;
+  if (op == LQGRID_OP_NODE_PRECOND && !c->nt_factored) return LQGRID_EWORKSPACE;
   if (op == LQGRID_OP_PRECOND && (S < 1 || L < 1)) return LQGRID_EINVAL;
   double* vin = c->outer[kRt];
   double* vout = c->outer[kYt];
@@ -914,7 +988,13 @@ int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
       case LQGRID_OP_PHI_SOLVE:
         op_phi<T>(c, x, y, 0);
         break;
-      default: y = precondition<T>(c, x, S, L, 0); break;
+      case LQGRID_OP_NODE_PRECOND:
+        nt_solve<T>(D, nt_tab<T>(c), x, y, c->sc, 0, s);
+        break;
+      default:
+        c->pmode = LQGRID_PRECOND_NBJM;
+        y = precondition<T>(c, x, S, L, 0);
+        break;
     }
     vec_zero<double>(vout, D.vlen, s);
     vec_axpy_from<T>(D, 1.0, y, vout, s);
@@ -1030,7 +1110,9 @@ int lqgrid_condition_estimate(lqgrid_ctx* c, const double* x0, int preconditione
   o.inner_L = inner_L;
   o.tol = tol;
   o.max_iter = max_iter > 0 ? max_iter : kHistCap;
-  if (!opts_valid(o) || o.max_iter > kHistCap) return LQGRID_EINVAL;
+  if (!opts_valid(o) || o.max_iter > kHistCap || preconditioned < 0 || preconditioned > 2)
+    return LQGRID_EINVAL;
+  if (preconditioned == 2 && !c->nt_factored) return LQGRID_EWORKSPACE;
   const Dims& D = c->D;
   hipStream_t s = c->stream;
   clear_stale_error();
@@ -1047,10 +1129,11 @@ int lqgrid_condition_estimate(lqgrid_ctx* c, const double* x0, int preconditione
   struct { double* p; int cap; } stage{reinterpret_cast<double*>(c->ws + c->P.hist), kHistCap};
   HIPCHECK(hipMemcpyAsync(&c->sc->hist, &stage, sizeof(double*) + sizeof(int),
                           hipMemcpyHostToDevice, s));
-  c->precond_identity = preconditioned == 0;
+  c->pmode = preconditioned == 0 ? LQGRID_PRECOND_NONE
+            : preconditioned == 2 ? LQGRID_PRECOND_NODE_TEMPORAL : LQGRID_PRECOND_NBJM;
   int it = 0, done = kRunning;
   st = refine_pass<double>(c, std::sqrt(h.rr), o.tol, o.max_iter, o, &it, &done);
-  c->precond_identity = false;
+  c->pmode = LQGRID_PRECOND_NBJM;
   const decltype(stage) none{nullptr, 0};
   HIPCHECK(hipMemcpyAsync(&c->sc->hist, &none, sizeof(double*) + sizeof(int),
                           hipMemcpyHostToDevice, s));
@@ -1086,7 +1169,7 @@ int lqgrid_solve_noalloc(const lqgrid_problem_desc* desc, const double* x0,
   Dims D;
   const int chk = check_problem(desc, &D);
   if (chk != LQGRID_OK) return chk;
-  const size_t need = make_plan(D, desc->time_varying != 0).total;
+  const size_t need = lqgrid_workspace_bytes(desc, opts);
   if (need > kNoAllocBytes) {
     std::snprintf(g_last_error, sizeof(g_last_error),
                   "lqgrid_solve_noalloc: the problem needs %zu bytes of scratch, "

@@ -81,7 +81,7 @@ Coef coef_at(char* base, const Dims& D) {
     off += align_up(bytes);
     return p;
   };
-  Coef C;
+  Coef C{};
   C.G13 = take(nodes * 13 * nn * 8);
   C.Cdn = take(nodes * 5 * nn * 8);
   C.Cup = take(nodes * 5 * nn * 8);
@@ -445,6 +445,7 @@ int lqgrid_batch_solve(int P, const lqgrid_problem_desc* descs,
   opts_fill(opts_in, &o);
   if (!opts_valid(o)) return LQGRID_EINVAL;
   if (o.precision != LQGRID_FP64) return LQGRID_EUNSUPPORTED;
+  if (o.preconditioner != LQGRID_PRECOND_NBJM) return LQGRID_EUNSUPPORTED;
   for (int p = 0; p < P; ++p) {
     const lqgrid_problem_desc& d = descs[p];
     if (!d.A || !d.A_nbr || !d.B || !d.Q || !d.R || !x0s[p] || !deltas[p])

@@ -681,6 +681,156 @@ __device__ __forceinline__ void delta_rows(const Dims& D, const OpCoef<T>& C,
   if (partial && threadIdx.x == 0) *partial = dot;
 }
 
+// The factored Delta apply, Delta = A~ Q~^-1 A~' + B~ R~^-1 B~' (Sec. II-B),
+// as two passes over the nodes (12 block products per node and step instead
+// of the 25 of the assembled 13-point form):
+//   w_t(p) = Q_t^-1 (A~'d)_t(p) = -Q_t^-1 d_t(p) + [t<T] sum_5 Cup[p][k] d_{t+1}(q_k)
+//   y_t(p) = -w_t(p) + [t>=1] ( sum_5 A5[p][k] w_{t-1}(q_k) + BRB[p] d_t(p) )
+// with Cup[p][k] = Q_p^-1 A_hat[q_k,p]' and A5[p][k] = A_hat[p,q_k]; the
+// t+1 / t-1 terms are formed at t from aligned reads and moved one lane
+// (the chunk boundaries from the neighbouring chunks), as in delta_rows.
+// One wavefront per node over all its time chunks.
+template <typename T, int NS>
+__device__ __forceinline__ void delta_w_rows(const Dims& D, const OpCoef<T>& C,
+                                             const T* __restrict__ d, T* __restrict__ w,
+                                             int group) {
+  constexpr int nn = NS * NS;
+  const int p = tile_node(group);
+  if (p >= D.real_nodes) return;  // wave-uniform
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+  const long long nodes = D.nodes;
+  TileBlocks<T, 5 * nn> Cu;
+  TileBlocks<T, nn> Qi, Qd;
+  Cu.load(C.Cup, nodes * 5 * nn, (long long)p * 5 * nn, lane);
+  Qi.load(C.Qi, nodes * nn, (long long)p * nn, lane);
+  Qd.load(C.QTd, nodes * nn, (long long)p * nn, lane);
+  const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), rw = vec_rsrc(D, w);
+  const int nc = time_chunks(D);
+  struct Prod {
+    T self[NS], v[NS];
+  };
+  auto prod = [&](int c, Prod& P) {
+    const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) P.v[a] = T(0);
+    load_nb<NS>(rd, off, p, ldt, P.self);
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+      T nb[NS];
+      if constexpr (k == 0) {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) nb[a] = P.self[a];
+      } else {
+        load_nb<NS>(rd, off, jq * K + iq, ldt, nb);
+      }
+      Cu.template mv<k * nn, false>(nb, P.v);
+    });
+  };
+  Prod cur, nxt;
+  prod(0, cur);
+  for (int c = 0; c < nc; ++c) {
+    if (c + 1 < nc) {
+      prod(c + 1, nxt);
+    } else {
+#pragma unroll
+      for (int a = 0; a < NS; ++a) nxt.self[a] = nxt.v[a] = T(0);
+    }
+    const TileTime tt = tile_time<T>(D, c);
+    T acc[NS], sq[NS], a2[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      acc[a] = T(0);
+      sq[a] = cur.self[a];
+      a2[a] = from_next_lane(cur.v[a], nxt.v[a]);
+    }
+    Qi.template mv<0, true>(cur.self, acc);
+    zero_unless<NS>(tt.t == T_, sq);
+    Qd.template mv<0, true>(sq, acc);      // -Q_T^-1 d_T at t = T
+    zero_unless<NS>(tt.t < T_, a2);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] += a2[a];
+    store_nb<NS>(rw, tt.valid ? tt.off : kOob, p, ldt, acc);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      cur.self[a] = nxt.self[a];
+      cur.v[a] = nxt.v[a];
+    }
+  }
+}
+
+// Second pass: y from w and d; the workgroup's FP64 partial of y'd to
+// *partial.  Every thread of the workgroup must call this.
+template <typename T, int NS>
+__device__ __forceinline__ void delta_y_rows(const Dims& D, const OpCoef<T>& C,
+                                             const T* __restrict__ d,
+                                             const T* __restrict__ w, T* __restrict__ y,
+                                             double* __restrict__ partial, int group) {
+  constexpr int nn = NS * NS;
+  const int p = tile_node(group);
+  const int T_ = D.T, ldt = D.ldt, K = D.K, N = D.N;
+  const int lane = threadIdx.x & (kWave - 1);
+  double dot = 0.0;
+  if (p < D.real_nodes) {  // wave-uniform
+    const int j = uniform(p / K), i = uniform(p - (p / K) * K);
+    const long long nodes = D.nodes;
+    TileBlocks<T, 5 * nn> A5;
+    TileBlocks<T, nn> Bb;
+    A5.load(C.A5, nodes * 5 * nn, (long long)p * 5 * nn, lane);
+    Bb.load(C.BRB, nodes * nn, (long long)p * nn, lane);
+    const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), rw = vec_rsrc(D, w),
+                                 ry = vec_rsrc(D, y);
+    const int nc = time_chunks(D);
+    T xp[NS];  // the previous chunk's sum_5 A5 w
+#pragma unroll
+    for (int a = 0; a < NS; ++a) xp[a] = T(0);
+    for (int c = 0; c < nc; ++c) {
+      const TileTime tt = tile_time<T>(D, c);
+      T self[NS], ws[NS], x[NS], acc[NS];
+      load_nb<NS>(rd, tt.off, p, ldt, self);
+      load_nb<NS>(rw, tt.off, p, ldt, ws);
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        x[a] = T(0);
+        acc[a] = T(0);
+      }
+      sfor<0, 5>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
+        T nb[NS];
+        if constexpr (k == 0) {
+#pragma unroll
+          for (int a = 0; a < NS; ++a) nb[a] = ws[a];
+        } else {
+          load_nb<NS>(rw, tt.off, jq * K + iq, ldt, nb);
+        }
+        A5.template mv<k * nn, false>(nb, x);
+      });
+      Bb.template mv<0, false>(self, acc);
+      T a1[NS];
+#pragma unroll
+      for (int a = 0; a < NS; ++a) a1[a] = from_prev_lane(x[a], xp[a]) + acc[a];
+      zero_unless<NS>(tt.t >= 1, a1);
+#pragma unroll
+      for (int a = 0; a < NS; ++a) {
+        acc[a] = a1[a] - ws[a];
+        xp[a] = x[a];
+      }
+      store_nb<NS>(ry, tt.valid ? tt.off : kOob, p, ldt, acc);
+      if (tt.valid) {
+#pragma unroll
+        for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
+      }
+    }
+  }
+  dot = block_sum<256>(dot);
+  if (partial && threadIdx.x == 0) *partial = dot;
+}
+
 // One row of NW factor coefficients of a block row, as the sweeps read it:
 // lane l holds coefficient 16 g + (l mod 16) in register g, i.e. every 16-lane
 // row of the wavefront holds the same 16 coefficients.  The product with

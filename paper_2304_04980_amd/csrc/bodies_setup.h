@@ -99,6 +99,8 @@ __device__ inline void node_prep(const Dims& D, const ProblemIn& P, const Coef& 
   if (p >= D.real_nodes) {  // dummy column: all zero
     for (size_t k = 0; k < nn; ++k) Qi[k] = QTi[k] = QTd[k] = Qm[k] = 0.0;
     for (int k = 0; k < m * n; ++k) RiBT[k] = 0.0;
+    if (C.BRB)
+      for (size_t k = 0; k < nn; ++k) C.BRB[p * nn + k] = 0.0;
     return;
   }
   double q[kMaxM * kMaxM], qt[kMaxM * kMaxM], r[kMaxM * kMaxM];
@@ -126,6 +128,15 @@ __device__ inline void node_prep(const Dims& D, const ProblemIn& P, const Coef& 
       for (int k = 0; k < m; ++k) s += r[a * m + k] * Bp[b * m + k];
       RiBT[a * n + b] = s;
     }
+  if (C.BRB) {  // B R^-1 B' = B (R^-1 B')
+    double* BRB = C.BRB + p * nn;
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += Bp[a * m + k] * RiBT[k * n + b];
+        BRB[a * n + b] = s;
+      }
+  }
   if (differs) atomicOr(&sc->qt_differs, 1);
   if (!ok) atomicOr(&sc->flag_notspd, 1);
 }
@@ -214,6 +225,12 @@ __device__ inline void stencil(const Dims& D, const ProblemIn& P, const Coef& C,
     Cd[e] = out[e];
     At[e] = out2[e];
     Cu[e] = out3[e];
+  }
+  if (C.A5) {  // A_hat[p, q] itself (the factored Delta apply)
+    double* A5 = C.A5 + ((size_t)p * 5 + k5) * nn;
+    const double* Apq = (real && iq >= 0 && iq < K && jq >= 0 && jq < N)
+                            ? ahat_block(P, i, j, iq, jq) : nullptr;
+    for (size_t e = 0; e < nn; ++e) A5[e] = Apq ? Apq[e] : 0.0;
   }
 }
 

@@ -79,9 +79,11 @@ enum ScalarMode {
   kModeMu = 3,    // mu' = sum; beta = mu'/mu; mu = mu'
   kModeMuInit = 4,// mu = sum; beta = 0; done = 0
   kModeTrue = 5,  // rr = sum, rinf = max (true residual), no state change
-  kModeRd2Rel = 6 // as kModeRd2 with the relative target of a refinement
+  kModeRd2Rel = 6,// as kModeRd2 with the relative target of a refinement
                   // pass, tol_rel = min(tol ||r_delta|| / ||r||, 1/2), taken
                   // from the outer scalars
+  kModeDotA = 7,  // mu = sum (a dot product for the host, no state change)
+  kModeDotB = 8   // yd = sum (likewise)
 };
 
 // The scalar update of Algorithm 1 selected by mode, given the reduced sum s
@@ -138,6 +140,12 @@ __device__ inline void scalar_apply(int mode, double s, double m, Scalars* sc,
     case kModeTrue:
       sc->rr = s;
       sc->rinf = m;
+      break;
+    case kModeDotA:
+      sc->mu = s;
+      break;
+    case kModeDotB:
+      sc->yd = s;
       break;
   }
 }

@@ -71,6 +71,10 @@ struct Coef {
   double *Qi, *QTi, *QTd, *Qm, *RiBT;
   double *Fw, *Bw;  // factors in the substitution layout
   double* Xw;       // middle-row couplings of the twisted factorisation
+  // A5[p][k] = A_hat[p, p + o5_k] and BRB[p] = B_p R_p^-1 B_p' for the
+  // factored Delta apply (null: not assembled)
+  double* A5 = nullptr;
+  double* BRB = nullptr;
   // Time-varying data (0: the layouts above).  Otherwise the class of a
   // factorisation is the time t = 0..T and the one-chain factorisation reads
   // G13 / Qi and writes Fw / Bw in the time-fastest layouts of the
@@ -83,6 +87,11 @@ struct Coef {
 template <typename T>
 struct OpCoef {
   const T *G13, *Cdn, *Cup, *Qi, *QTd, *Qm, *Fw, *Bw, *Xw;
+  // the factored form of the Delta apply: A5[p][k] = A_hat[p, p + o5_k],
+  // BRB[p] = B_p R_p^-1 B_p', and its intermediate vector W (single-problem
+  // path; null in the batched form)
+  const T *A5 = nullptr, *BRB = nullptr;
+  T* W = nullptr;
 };
 
 // Rows of the forward factor table per (class, super-column): the one-chain

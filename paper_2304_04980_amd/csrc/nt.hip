@@ -128,7 +128,16 @@ __device__ __forceinline__ T quad_read(T v, int src) {
 
 // theta = D_node^-1 tau: four lanes per node (lane r of a quad owns state
 // component r; components past n idle), sixteen nodes per wavefront.  The
-// loads of kNtBatch steps are issued before their (sequential) products.
+// recurrence is sequential in t, so the loads are software-pipelined: the
+// coefficients and right-hand sides of the next kNtBatch steps are issued
+// before the products of the current ones (two register buffers).
+template <typename T, int NS>
+struct NtBuf {
+  T v[kNtBatch];             // tau_t (forward) or z_t (backward)
+  T a[kNtBatch][NS];         // Linv_t row (forward) / Linv_t' row (backward)
+  T b[kNtBatch][NS];         // M_t row (forward) / N_t row (backward)
+};
+
 template <typename T, int NS>
 __global__ __launch_bounds__(256) void k_nt_solve(Dims D, const T* __restrict__ tab,
                                                   const T* __restrict__ tau,
@@ -145,63 +154,84 @@ __global__ __launch_bounds__(256) void k_nt_solve(Dims D, const T* __restrict__ 
   const int rc = r < NS ? r : 0;
   const size_t nodes = D.nodes, ldt = D.ldt;
   const size_t vrow = ((size_t)pc * NS + rc) * ldt;
+  const int Tt = D.Tt;
+  const int nb = (Tt + kNtBatch - 1) / kNtBatch;
   auto coef = [&](int t, int k, int row, int col) {
     return tab[(((size_t)t * 3 + k) * nn + row * NS + col) * nodes + pc];
   };
-  const int Tt = D.Tt;
-  // forward
-  T zp = T(0);
-  for (int t0 = 0; t0 < Tt; t0 += kNtBatch) {
-    T tv[kNtBatch], li[kNtBatch][NS], mm[kNtBatch][NS];
+  // forward: batch i covers t = i kNtBatch + b
+  auto fload = [&](int i, NtBuf<T, NS>& B) {
 #pragma unroll
     for (int b = 0; b < kNtBatch; ++b) {
-      const int t = min(t0 + b, Tt - 1);
-      tv[b] = tau[vrow + t];
+      const int t = min(i * kNtBatch + b, Tt - 1);
+      B.v[b] = tau[vrow + t];
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
-        li[b][c] = coef(t, 0, rc, c);
-        mm[b][c] = coef(t, 1, rc, c);
+        B.a[b][c] = coef(t, 0, rc, c);
+        B.b[b][c] = coef(t, 1, rc, c);
       }
     }
+  };
+  T zp = T(0);
+  auto fcomp = [&](int i, const NtBuf<T, NS>& B) {
 #pragma unroll
     for (int b = 0; b < kNtBatch; ++b) {
-      if (t0 + b >= Tt) break;
+      const int t = i * kNtBatch + b;
+      if (t >= Tt) break;
       T z = T(0);
 #pragma unroll
-      for (int c = 0; c < NS; ++c) {
-        z = fma(li[b][c], quad_read(tv[b], q0 + c), z);
-        z = fma(-mm[b][c], quad_read(zp, q0 + c), z);
-      }
-      if (act) out[vrow + t0 + b] = z;
+      for (int c = 0; c < NS; ++c) z = fma(B.a[b][c], quad_read(B.v[b], q0 + c), z);
+#pragma unroll
+      for (int c = 0; c < NS; ++c) z = fma(-B.b[b][c], quad_read(zp, q0 + c), z);
+      if (act) out[vrow + t] = z;
       zp = z;
     }
+  };
+  NtBuf<T, NS> B0, B1;
+  fload(0, B0);
+  for (int i = 0; i < nb; i += 2) {
+    if (i + 1 < nb) fload(i + 1, B1);
+    fcomp(i, B0);
+    if (i + 1 >= nb) break;
+    if (i + 2 < nb) fload(i + 2, B0);
+    fcomp(i + 1, B1);
   }
-  // backward
-  T th = T(0);
-  for (int t1 = Tt - 1; t1 >= 0; t1 -= kNtBatch) {
-    T zv[kNtBatch], lt[kNtBatch][NS], nv[kNtBatch][NS];
+  // backward: batch i covers t = Tt - 1 - (i kNtBatch + b); z_t is read back
+  // from `out` (this thread's own forward stores)
+  auto bload = [&](int i, NtBuf<T, NS>& B) {
 #pragma unroll
     for (int b = 0; b < kNtBatch; ++b) {
-      const int t = max(t1 - b, 0);
-      zv[b] = act ? out[vrow + t] : T(0);
+      const int t = max(Tt - 1 - (i * kNtBatch + b), 0);
+      B.v[b] = act ? out[vrow + t] : T(0);
 #pragma unroll
       for (int c = 0; c < NS; ++c) {
-        lt[b][c] = coef(t, 0, c, rc);  // Linv_t' row r
-        nv[b][c] = coef(t, 2, rc, c);
+        B.a[b][c] = coef(t, 0, c, rc);  // Linv_t' row r
+        B.b[b][c] = coef(t, 2, rc, c);
       }
     }
+  };
+  T th = T(0);
+  auto bcomp = [&](int i, const NtBuf<T, NS>& B) {
 #pragma unroll
     for (int b = 0; b < kNtBatch; ++b) {
-      if (t1 - b < 0) break;
+      const int t = Tt - 1 - (i * kNtBatch + b);
+      if (t < 0) break;
       T v = T(0);
 #pragma unroll
-      for (int c = 0; c < NS; ++c) {
-        v = fma(lt[b][c], quad_read(zv[b], q0 + c), v);
-        v = fma(-nv[b][c], quad_read(th, q0 + c), v);
-      }
-      if (act) out[vrow + t1 - b] = v;
+      for (int c = 0; c < NS; ++c) v = fma(B.a[b][c], quad_read(B.v[b], q0 + c), v);
+#pragma unroll
+      for (int c = 0; c < NS; ++c) v = fma(-B.b[b][c], quad_read(th, q0 + c), v);
+      if (act) out[vrow + t] = v;
       th = v;
     }
+  };
+  bload(0, B0);
+  for (int i = 0; i < nb; i += 2) {
+    if (i + 1 < nb) bload(i + 1, B1);
+    bcomp(i, B0);
+    if (i + 1 >= nb) break;
+    if (i + 2 < nb) bload(i + 2, B0);
+    bcomp(i + 1, B1);
   }
 }
 

@@ -37,6 +37,28 @@ __global__ __launch_bounds__(256) void k_delta(Dims D, OpCoef<T> C,
   delta_rows<T, NS>(D, C, d, y, partial ? partial + lb : nullptr, lb);
 }
 
+// The factored Delta apply (delta_w_rows / delta_y_rows): two passes.
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_delta_w(Dims D, OpCoef<T> C,
+                                                 const T* __restrict__ d,
+                                                 const Scalars* sc, int check) {
+  if (is_done(sc, check)) return;
+  const int lb = xcd_block();
+  if (lb >= node_groups(D)) return;
+  delta_w_rows<T, NS>(D, C, d, C.W, lb);
+}
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_delta_y(Dims D, OpCoef<T> C,
+                                                 const T* __restrict__ d,
+                                                 T* __restrict__ y,
+                                                 double* __restrict__ partial,
+                                                 const Scalars* sc, int check) {
+  if (is_done(sc, check)) return;
+  const int lb = xcd_block();
+  if (lb >= node_groups(D)) return;
+  delta_y_rows<T, NS>(D, C, d, C.W, y, partial ? partial + lb : nullptr, lb);
+}
+
 template <typename T, int NS>
 __global__ __launch_bounds__(256) void k_omega(Dims D, OpCoef<T> C,
                                                const T* __restrict__ rho,
@@ -159,6 +181,15 @@ int delta_apply(const Dims& D, const OpCoef<T>& C, const T* d, T* y,
                 hipStream_t s) {
   const int nb = node_groups(D);  // one partial of y'd per workgroup
   const dim3 g(padded_grid(nb));
+  if (C.A5 && C.BRB && C.W) {  // the factored form, two passes
+#define CALL(NS)                                                                     \
+  hipLaunchKernelGGL((k_delta_w<T, NS>), g, dim3(256), 0, s, D, C, d, sc, check_done); \
+  hipLaunchKernelGGL((k_delta_y<T, NS>), g, dim3(256), 0, s, D, C, d, y, partial, sc,  \
+                     check_done)
+    LQG_DISPATCH_N(D.n, CALL)
+#undef CALL
+    return nb;
+  }
 #define CALL(NS)                                                              \
   hipLaunchKernelGGL((k_delta<T, NS>), g, dim3(256), 0, s, D, C, d, y, partial, \
                      sc, check_done)

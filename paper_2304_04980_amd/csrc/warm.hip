@@ -298,6 +298,21 @@ __global__ __launch_bounds__(256) void k_loss(int P, int B, const float* __restr
   if (threadIdx.x == 0) part[blockIdx.x] = lp;
 }
 
+// A given output gradient dout (FP32 [B][P][64]) rounded to BF16 (nearest
+// even) into both layouts of the first gradient buffer.
+__global__ __launch_bounds__(256) void k_dout_bf16(int P, int B, const float* __restrict__ dout,
+                                                   bf16* __restrict__ dy_nhwc,
+                                                   bf16* __restrict__ dy_chw) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long long)B * P * kWidth) return;
+  const int ch = (int)(g % kWidth);
+  const long long bp = g / kWidth;
+  const int b = (int)(bp / P), p = (int)(bp % P);
+  const bf16 v = (bf16)dout[g];
+  dy_nhwc[g] = v;
+  dy_chw[((long long)b * kWidth + ch) * P + p] = v;
+}
+
 // out[0] = sum of n partials (fixed order).
 __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ part, int n,
                                              double* __restrict__ out) {
@@ -529,6 +544,8 @@ void launch_conv(const Net& net, int B, int cin, int mode, const ConvArgs& a) {
 
 // Forward pass of B samples (features of sample idx[b]); the output lands in
 // the workspace's FP32 buffer.
+void backward_layers(Net& net, int batch, const bf16* fb, const int* index, float* grad);
+
 void forward(const Net& net, int B, const bf16* feats, const int* idx,
              const float* params) {
   prep_weights(net, params);
@@ -658,7 +675,47 @@ int lqgrid_wsnet_gradient(const lqgrid_wsnet_desc* d, int batch, const void* fea
                      lpart);
   double* lsum = net.at<double>(net.w.scal);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, net.st, lpart, net.w.nloss, lsum);
-  // backward through the layers
+  backward_layers(net, batch, fb, index, grad);
+  HIPCHECK(hipGetLastError());
+  if (loss) {
+    double h = 0.0;
+    HIPCHECK(hipMemcpyAsync(&h, lsum, sizeof(double), hipMemcpyDeviceToHost, net.st));
+    HIPCHECK(hipStreamSynchronize(net.st));
+    *loss = h / batch + 1.0;  // + |delta*|^2 / |delta*|^2 per sample
+  }
+  return LQGRID_OK;
+}
+
+int lqgrid_wsnet_backward(const lqgrid_wsnet_desc* d, int batch, const void* feats,
+                          const int* index, const float* params, const float* dout,
+                          float* grad, void* workspace, size_t ws_bytes, void* stream) {
+  NetShape s;
+  if (!make_shape(d, &s) || batch < 1 || !feats || !params || !dout || !grad)
+    return LQGRID_EINVAL;
+  Net net{s, make_ws(s, batch), static_cast<char*>(workspace),
+          reinterpret_cast<hipStream_t>(stream)};
+  int st = check_ws(net, ws_bytes);
+  if (st != LQGRID_OK) return st;
+  clear_stale_error();
+  const bf16* fb = static_cast<const bf16*>(feats);
+  forward(net, batch, fb, index, params);
+  const long long cnt = (long long)batch * s.P * kWidth;
+  hipLaunchKernelGGL(k_dout_bf16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, net.st,
+                     s.P, batch, dout, net.at<bf16>(net.w.dy_nhwc[0]),
+                     net.at<bf16>(net.w.dy_chw[0]));
+  backward_layers(net, batch, fb, index, grad);
+  HIPCHECK(hipGetLastError());
+  return LQGRID_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Gradients of every layer's weights and biases from the output gradient in
+// slot 0 of the gradient buffers (BF16, both layouts), into grad.
+void backward_layers(Net& net, int batch, const bf16* fb, const int* index, float* grad) {
+  const NetShape& s = net.s;
   int cur = 0;
   for (int l = s.L - 1; l >= 0; --l) {
     const int cin = s.cin[l];
@@ -702,15 +759,11 @@ int lqgrid_wsnet_gradient(const lqgrid_wsnet_desc* d, int batch, const void* fea
       cur = 1 - cur;
     }
   }
-  HIPCHECK(hipGetLastError());
-  if (loss) {
-    double h = 0.0;
-    HIPCHECK(hipMemcpyAsync(&h, lsum, sizeof(double), hipMemcpyDeviceToHost, net.st));
-    HIPCHECK(hipStreamSynchronize(net.st));
-    *loss = h / batch + 1.0;  // + |delta*|^2 / |delta*|^2 per sample
-  }
-  return LQGRID_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int lqgrid_wsnet_adam(const lqgrid_wsnet_desc* d, float* params, const float* grad,
                       float* moments, int step, float lr, void* stream) {

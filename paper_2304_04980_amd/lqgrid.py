@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "liblqgrid.so")
 
 OK, EINVAL, ENOTSPD, EBREAKDOWN, ENOCONV, EWORKSPACE, EHIP, EUNSUPPORTED = range(8)
 FP64, FP32_REFINE = 0, 1
-OP_DELTA, OP_XI, OP_OMEGA, OP_PHI_SOLVE, OP_PRECOND = range(5)
+OP_DELTA, OP_XI, OP_OMEGA, OP_PHI_SOLVE, OP_PRECOND, OP_NODE_PRECOND = range(6)
+PRECOND_NBJM, PRECOND_NODE_TEMPORAL, PRECOND_NONE = range(3)
 OP_F32 = 16   # or-ed into an operator code: run the FP32 kernels
 PROF_DELTA, PROF_PHI_SOLVE, PROF_RHS, PROF_UPDATE = range(4)
 
@@ -38,7 +39,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("outer_S", c_int), ("inner_L", c_int), ("tol", c_double),
                 ("max_iter", c_int), ("precision", c_int),
                 ("inner_tol", c_double), ("check_every", c_int),
-                ("warm_fallback", c_int)]
+                ("warm_fallback", c_int), ("preconditioner", c_int)]
 
 
 class WsNetDesc(ctypes.Structure):
@@ -135,6 +136,9 @@ def load(path: str = LIB_PATH):
                                         c_void_p, c_void_p, POINTER(c_double),
                                         c_void_p, c_size_t, c_void_p]
     L.lqgrid_wsnet_gradient.restype = c_int
+    L.lqgrid_wsnet_backward.argtypes = [W, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_size_t, c_void_p]
+    L.lqgrid_wsnet_backward.restype = c_int
     L.lqgrid_wsnet_adam.argtypes = [W, c_void_p, c_void_p, c_void_p, c_int,
                                     ctypes.c_float, c_void_p]
     L.lqgrid_wsnet_adam.restype = c_int
@@ -169,7 +173,7 @@ EXPORTED = ["lqgrid_default_opts", "lqgrid_workspace_bytes", "lqgrid_setup",
             "lqgrid_wsnet_targets", "lqgrid_wsnet_forward", "lqgrid_wsnet_gradient",
             "lqgrid_wsnet_adam", "lqgrid_wsnet_predict", "lqgrid_noalloc_capacity",
             "lqgrid_solve_noalloc", "lqgrid_nbjm_solve", "lqgrid_condition_estimate",
-            "lqgrid_pcg_solve_bc"]
+            "lqgrid_pcg_solve_bc", "lqgrid_wsnet_backward"]
 
 
 class LqgridError(RuntimeError):
@@ -199,10 +203,11 @@ def _stream():
     return c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def workspace_bytes(K, N, T, n, m, time_varying=False) -> int:
+def workspace_bytes(K, N, T, n, m, time_varying=False, node_temporal=False) -> int:
     d = ProblemDesc(K, N, T, n, m, None, None, None, None, None, None, None, None,
                     1 if time_varying else 0)
-    return load().lqgrid_workspace_bytes(byref(d), None)
+    o = default_opts(preconditioner=PRECOND_NODE_TEMPORAL) if node_temporal else None
+    return load().lqgrid_workspace_bytes(byref(d), byref(o) if o is not None else None)
 
 
 def problem_desc(K, N, T, n, m, A, A_nbr, B, Q, R, QT=None, n_node=None,
@@ -219,10 +224,12 @@ class Context:
     lqgrid_pcg_solve calls (e.g. for different initial states)."""
 
     def __init__(self, problem, device="cuda", factor=True, workspace=None,
-                 arrays=None):
+                 arrays=None, node_temporal=False):
         """problem: an lqgrid_synth.Problem (numpy arrays, copied to the
         device) or, with ``arrays``, just the dims of device-resident tensors.
-        workspace: optional preallocated uint8 CUDA tensor, reused as is."""
+        workspace: optional preallocated uint8 CUDA tensor, reused as is.
+        node_temporal: size the workspace for the node-temporal preconditioner
+        too (PRECOND_NODE_TEMPORAL)."""
         import torch
         self.L = load()
         p = problem
@@ -241,7 +248,9 @@ class Context:
         self.desc = problem_desc(*self.dims, a["A"], a["A_nbr"], a["B"], a["Q"],
                                  a["R"], a["QT"], a.get("n_node"), a.get("m_node"),
                                  getattr(p, "time_varying", False))
-        nbytes = self.L.lqgrid_workspace_bytes(byref(self.desc), None)
+        wo = default_opts(preconditioner=PRECOND_NODE_TEMPORAL) if node_temporal else None
+        nbytes = self.L.lqgrid_workspace_bytes(byref(self.desc),
+                                               byref(wo) if wo is not None else None)
         if nbytes == 0:
             raise LqgridError(EINVAL, "lqgrid_workspace_bytes")
         # 256-byte alignment: torch's caching allocator returns 512-byte
@@ -335,12 +344,14 @@ class Context:
     def condition_estimate(self, x0, preconditioned=True, S=2, L=2, tol=1e-10,
                            max_iter=0):
         """lqgrid_condition_estimate: dict with kappa, lambda_min, lambda_max,
-        iterations of the Lanczos estimate from one run of Algorithm 1."""
+        iterations of the Lanczos estimate from one run of Algorithm 1.
+        preconditioned: True / 1 (NBJM), 2 (node temporal), False / 0 (none)."""
         import torch
         dev = self.arrays["A"].device
         x0 = torch.as_tensor(x0).to(dtype=torch.float64, device=dev).contiguous()
         k, lo, hi, it = c_double(), c_double(), c_double(), c_int()
-        st = self.L.lqgrid_condition_estimate(self.ctx, _ptr(x0), 1 if preconditioned else 0,
+        mode = int(preconditioned) if not isinstance(preconditioned, bool) else int(preconditioned)
+        st = self.L.lqgrid_condition_estimate(self.ctx, _ptr(x0), mode,
                                               S, L, tol, max_iter, byref(k), byref(lo),
                                               byref(hi), byref(it))
         if st != OK:
@@ -561,6 +572,22 @@ class WarmNet:
         if st != OK:
             raise LqgridError(st, "lqgrid_wsnet_gradient")
         return loss.value, grad
+
+    def backward(self, feats, index, dout, grad=None, params=None):
+        """Parameter gradient for a given output gradient dout
+        ([batch][K N][64] FP32 device tensor)."""
+        import torch
+        batch = index.numel()
+        wp, nb = self.workspace(batch)
+        if grad is None:
+            grad = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        p = self.params if params is None else params
+        st = self.L.lqgrid_wsnet_backward(byref(self.desc), batch, _ptr(feats), _ptr(index),
+                                          _ptr(p), _ptr(dout), _ptr(grad), c_void_p(wp), nb,
+                                          _stream())
+        if st != OK:
+            raise LqgridError(st, "lqgrid_wsnet_backward")
+        return grad
 
     def adam(self, grad, lr):
         self.step += 1

@@ -9,8 +9,9 @@ gradients), so the remaining differences come from FP32 accumulation in the
 kernels (relative error about 576 terms x 6e-8 ~ 3.5e-5 of a layer's sums)
 and from the BF16 values that this rounding difference moves across a
 rounding boundary (one BF16 ulp, 2^-8 relative, on a small fraction of the
-stored values).  Bounds used: forward output 2e-3 x max|ref|, loss 1e-3
-relative, weight and bias gradients 2e-2 x max|ref| of each layer's tensor.
+stored values).  Bounds used: forward output 2e-2 x max|ref| and 1e-3 of
+its RMS (2e-3 for six layers), loss 1e-3 relative, weight and bias gradients
+2e-2 x max|ref| of each layer's tensor.
 A value moved across a boundary perturbs every output it reaches, and the
 perturbations compound with depth (measured on random data: 1.5e-3 of the
 output scale after 2 layers, 8e-3 after 6, on a few outputs only), so the
@@ -150,6 +151,46 @@ def test_forward_is_exact_on_dyadic_data(lib, torch, layers):
             say(f"  layers {layers} order {order} entry {bi}: max err {err:.3e} "
                 f"(scale {np.abs(refs[s]).max():.3e})")
             assert err <= (0.0 if layers == 2 else 1e-6 * np.abs(refs[s]).max())
+
+
+@pytest.mark.parametrize("layers", [2, 3])
+def test_backward_is_exact_on_dyadic_data(lib, torch, layers):
+    """The input-gradient and weight-gradient kernels from a given output
+    gradient (lqgrid_wsnet_backward) on dyadic data: weights multiples of
+    1/64 in [-3/64, 3/64], inputs multiples of 1/4, output gradients in
+    {-1, 0, 1}/16.  Every product and partial sum is then exact in FP32 for
+    two layers (at most 24 significant bits), so both sides take the same
+    BF16 rounding decisions and the gradients agree exactly; with three
+    layers the hidden sums can exceed 24 bits and the bound is the FP32
+    rounding of the sums, 1e-6 of each tensor's largest entry."""
+    from paper_2304_04980_amd import lqgrid
+    net = lqgrid.WarmNet(K, N, n, m, T, layers=layers, seed=2)
+    rng = np.random.default_rng(11)
+    params = (rng.integers(-3, 4, net.count) / 64.0).astype(np.float32)
+    net.params.copy_(torch.as_tensor(params))
+    feats, probs = dyadic_set(torch, net, [31, 32, 33])
+    order = [2, 0, 1]
+    idx = torch.tensor(order, dtype=torch.int32, device="cuda")
+    P = K * N
+    dout = (rng.integers(-1, 2, (len(order), P, 64)) / 16.0).astype(np.float32)
+    grad = net.backward(feats, idx, torch.as_tensor(dout).cuda()).cpu().numpy()
+    pw = net.unflatten(params)
+    gsum = [(np.zeros_like(W), np.zeros_like(b)) for W, b in pw]
+    for bi, s in enumerate(order):
+        x = ows.bf16(ows.features(probs[s], 32))
+        acts = ows.forward(pw, x, round_bf16=True)
+        grads = ows.backward(pw, x, acts, to_img(dout[bi]), round_bf16=True)
+        for li, (dW, db) in enumerate(grads):
+            gsum[li][0][...] += dW
+            gsum[li][1][...] += db
+    for li, ((dWg, dbg), (dWr, dbr)) in enumerate(zip(net.unflatten(grad), gsum)):
+        ew = np.abs(dWg - dWr).max()
+        eb = np.abs(dbg - dbr).max()
+        say(f"  layers {layers}, layer {li}: dW max err {ew:.3e} (max {np.abs(dWr).max():.3e}), "
+            f"db max err {eb:.3e}")
+        tol_w = 0.0 if layers == 2 else 1e-6 * np.abs(dWr).max()
+        tol_b = 0.0 if layers == 2 else 1e-6 * np.abs(dbr).max()
+        assert ew <= tol_w and eb <= tol_b
 
 
 @pytest.mark.parametrize("layers", [2, 3, 6])
