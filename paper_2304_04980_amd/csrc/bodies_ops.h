@@ -394,23 +394,37 @@ __device__ __forceinline__ void omega_tile(const Dims& D, const OpCoef<T>& C,
   G.load(C.G13, (long long)D.nodes * 13 * nn, (long long)p * 13 * nn, lane);
   const __amdgpu_buffer_rsrc_t rth = vec_rsrc(D, th), rtau = vec_rsrc(D, tau);
   const __amdgpu_buffer_rsrc_t rrho = vec_rsrc(D, rho ? rho : th);
+  // the five 13-point offsets that leave the super-column: (0, -2) and
+  // (0, +2) always, and the three of dj = -1 (left column of its pair) or
+  // dj = +1 (right column)
+  const bool left = (j & 1) == 0;
   for (int chunk = c0; chunk < c1; ++chunk) {
     const TileTime tt = tile_time<T>(D, chunk);
-    T acc[NS], a1[NS], nb[NS];
+    T acc[NS], a1[NS];
     if (rho) load_nb<NS>(rrho, tt.off, p, ldt, acc);
     else
 #pragma unroll
       for (int a = 0; a < NS; ++a) acc[a] = T(0);
 #pragma unroll
     for (int a = 0; a < NS; ++a) a1[a] = T(0);
-    sfor<0, 13>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
-      if ((jq >> 1) == (j >> 1)) return;  // same super-column: inside Phi~
-      load_nb<NS>(rth, tt.off, jq * K + iq, ldt, nb);
-      G.template mv<k * nn, true>(nb, a1);
-    });
+    auto apply = [&](auto side) {
+      constexpr int sgn = decltype(side)::value;  // -1: left column, +1: right
+      constexpr int ks[5] = {off13_index(0, -2), off13_index(0, 2), off13_index(-1, sgn),
+                             off13_index(0, sgn), off13_index(1, sgn)};
+      T nb[5][NS];
+      sfor<0, 5>([&](auto uc) {  // every neighbour's loads first
+        constexpr int k = ks[decltype(uc)::value];
+        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+        const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
+        load_nb<NS>(rth, in ? tt.off : kOob, in ? jq * K + iq : 0, ldt, nb[decltype(uc)::value]);
+      });
+      sfor<0, 5>([&](auto uc) {
+        constexpr int k = ks[decltype(uc)::value];
+        G.template mv<k * nn, true>(nb[decltype(uc)::value], a1);
+      });
+    };
+    if (left) apply(std::integral_constant<int, -1>{});
+    else apply(std::integral_constant<int, 1>{});
     zero_unless<NS>(tt.t >= 1, a1);
 #pragma unroll
     for (int a = 0; a < NS; ++a) acc[a] += a1[a];
@@ -521,14 +535,19 @@ __device__ __forceinline__ void xi_rows(const Dims& D, const OpCoef<T>& C,
     const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
 #pragma unroll
     for (int a = 0; a < NS; ++a) W[a] = V[a] = T(0);
+    // every neighbour's loads first (out-of-grid ones read as zero through an
+    // out-of-range offset; their blocks are zero), then the products
+    T nb[5][NS];
     sfor<0, 5>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
-      T nb[NS];
-      load_nb<NS>(rdl, off, jq * K + iq, ldt, nb);
-      Cd.template mv<k * nn, false>(nb, W);
-      Cu.template mv<k * nn, false>(nb, V);
+      const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
+      load_nb<NS>(rdl, in ? off : kOob, in ? jq * K + iq : 0, ldt, nb[k]);
+    });
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      Cd.template mv<k * nn, false>(nb[k], W);
+      Cu.template mv<k * nn, false>(nb[k], V);
     });
   };
   T Wp[NS], W[NS], V[NS], Wn[NS], Vn[NS];
@@ -715,19 +734,21 @@ __device__ __forceinline__ void delta_w_rows(const Dims& D, const OpCoef<T>& C,
     const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
 #pragma unroll
     for (int a = 0; a < NS; ++a) P.v[a] = T(0);
+    // every neighbour's loads first (out-of-grid neighbours read as zero
+    // through an out-of-range offset), then the products
+    T nb[5][NS];
     load_nb<NS>(rd, off, p, ldt, P.self);
-    sfor<0, 5>([&](auto kc) {
+    sfor<1, 5>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-      if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
-      T nb[NS];
-      if constexpr (k == 0) {
+      const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
+      load_nb<NS>(rd, in ? off : kOob, in ? jq * K + iq : 0, ldt, nb[k]);
+    });
 #pragma unroll
-        for (int a = 0; a < NS; ++a) nb[a] = P.self[a];
-      } else {
-        load_nb<NS>(rd, off, jq * K + iq, ldt, nb);
-      }
-      Cu.template mv<k * nn, false>(nb, P.v);
+    for (int a = 0; a < NS; ++a) nb[0][a] = P.self[a];
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      Cu.template mv<k * nn, false>(nb[k], P.v);
     });
   };
   Prod cur, nxt;
@@ -797,18 +818,18 @@ __device__ __forceinline__ void delta_y_rows(const Dims& D, const OpCoef<T>& C,
         x[a] = T(0);
         acc[a] = T(0);
       }
-      sfor<0, 5>([&](auto kc) {
+      T nb[5][NS];
+      sfor<1, 5>([&](auto kc) {  // every neighbour's loads first
         constexpr int k = decltype(kc)::value;
         const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= N) return;
-        T nb[NS];
-        if constexpr (k == 0) {
+        const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
+        load_nb<NS>(rw, in ? tt.off : kOob, in ? jq * K + iq : 0, ldt, nb[k]);
+      });
 #pragma unroll
-          for (int a = 0; a < NS; ++a) nb[a] = ws[a];
-        } else {
-          load_nb<NS>(rw, tt.off, jq * K + iq, ldt, nb);
-        }
-        A5.template mv<k * nn, false>(nb, x);
+      for (int a = 0; a < NS; ++a) nb[0][a] = ws[a];
+      sfor<0, 5>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        A5.template mv<k * nn, false>(nb[k], x);
       });
       Bb.template mv<0, false>(self, acc);
       T a1[NS];
