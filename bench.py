@@ -20,7 +20,6 @@ Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -32,79 +31,20 @@ sys.path.insert(0, ROOT)
 METRIC = ("solves/s to 1e-8 rel. KKT residual, K=N=128 T=200 (plain vs chosen); "
           "HBM %")
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
-TWIST_MIN = 8                # block rows from which Phi_bar is solved in the twisted order
 # Kernel durations come from HIP events around every PROFILE_STRIDE-th launch
 # of each hot kernel inside the timed steps: an event pair serialises the
 # dispatch of the launches around it (timing every launch costs ~11% of the
 # solve rate), so only a sample is timed.
 PROFILE_STRIDE = 16
 PROFILE_DIR = os.path.join(ROOT, "profiles")
+TRAFFIC = os.path.join(PROFILE_DIR, "traffic.json")
+
+from paper_2304_04980_amd.roofline import (  # noqa: E402
+    KERNEL_NAMES, iteration_bytes, kernel_bytes, traffic_from_record)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def kernel_bytes(p, w=8, qt_distinct=False):
-    """Algorithmic HBM bytes of one launch of each hot kernel.
-
-    U = K N n (T+1) unknowns, w = bytes per element of the vectors and of the
-    operator / factor copies the kernels read (8: FP64, 4: FP32 sweeps).
-      Delta apply: read d, write y (2 U w) + the operator blocks read once:
-                   per node 13 (G) + 5 (A_hat Q^-1) + 5 (Q^-1 A_hat') + 2
-                   (Q^-1, Q_T^-1 - Q^-1) n x n blocks.
-      Phi solve:   read tau, write theta (2 U w) + the factor rows of one
-                   class: per super-column and block row, 2n forward rows of
-                   32 entries and 2n backward rows of 16 entries (K block
-                   rows), + Q per node (the t = 0 solve).  The forward table
-                   has K+1 block rows in the one-chain order, K+2 plus one
-                   row of middle couplings in the twisted order (K >= 8).
-    The parked forward-sweep result w (one write and one read of U) is not
-    algorithmic and shows up as measured traffic above these figures.
-    """
-    K, N, T, n = p.K, p.N, p.T, p.n
-    U = K * N * n * (T + 1)
-    V = (N + 1) // 2
-    nodes = K * N
-    ncls = 2 if qt_distinct else 1
-    fw_rows = K + 3 if K >= TWIST_MIN else K + 1
-    factors = ncls * V * 2 * n * (32 * fw_rows + 16 * K) * w
-    return {
-        "delta": 2 * U * w + nodes * 25 * n * n * w,
-        "phi_solve": 2 * U * w + factors + nodes * n * n * w,
-    }
-
-
-def src_hash():
-    h = hashlib.sha256()
-    for f in ("ops.hip", "bodies_ops.h", "lqg_internal.h"):
-        with open(os.path.join(ROOT, "paper_2304_04980_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-KERNEL_NAMES = {  # rocprofv3 names of the two hot kernels per element type
-    ("delta", 8): "k_delta<double, 4>", ("delta", 4): "k_delta<float, 4>",
-    ("phi_solve", 8): "k_phi_solve_twisted<double, 4>",
-    ("phi_solve", 4): "k_phi_solve_twisted<float, 4>",
-}
-
-
-def traffic_from_profiles(kernel, w):
-    """HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and
-    WRITE_SIZE (profiles/traffic.json), only if taken on the current kernel
-    source; else None."""
-    path = os.path.join(PROFILE_DIR, "traffic.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        rec = json.load(open(path))
-    except Exception:
-        return None
-    if rec.get("src_sha") != src_hash():
-        return None
-    k = rec.get("kernels", {}).get(KERNEL_NAMES.get((kernel, w), ""))
-    return None if k is None else k.get("bytes_per_launch")
 
 
 def cpu_model():
@@ -164,38 +104,32 @@ def cpu_baseline(p, tol, gpu_iters):
     }
 
 
-def iteration_bytes(p, w, qt_distinct=False):
-    """Algorithmic HBM bytes of one PCG iteration (S = L = 2) over the whole
-    path: 21 full vector passes (Delta apply 2, update + first solve 7,
-    second and third solves 3 each, fourth solve with the dot product 4 --
-    the count of a fully fused iteration) plus the factor rows of four block
-    solves and the operator blocks of the Delta apply, the two Omega~ and
-    the Xi~ right-hand sides."""
-    kb = kernel_bytes(p, w, qt_distinct)
-    U = p.K * p.N * p.n * (p.T + 1)
-    nodes = p.K * p.N
-    factors = kb["phi_solve"] - 2 * U * w - nodes * p.n * p.n * w
-    return 21 * U * w + 4 * factors + nodes * (25 + 2 * 10 + 10) * p.n * p.n * w
-
-
 def make_inputs(p, torch, dev):
     f64 = dict(dtype=torch.float64, device=dev)
     arrays = {k: torch.as_tensor(getattr(p, k)).to(**f64).contiguous()
               for k in ("A", "A_nbr", "B", "Q", "R", "QT")}
+    for k in ("n_node", "m_node"):
+        v = getattr(p, k, None)
+        if v is not None:
+            arrays[k] = torch.as_tensor(v).to(dtype=torch.int32, device=dev).contiguous()
     x0 = torch.as_tensor(p.x0).to(**f64).contiguous()
     return arrays, x0
 
 
 def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
-            lqgrid):
+            lqgrid, path="ti", opts_kw=None, ctx_kw=None, boundary=None):
     """Time `steps` full passes (setup + factor + solve) of one form after
     `warmup` untimed ones; per-kernel averages from the library's HIP events
-    on its stream over the timed steps."""
+    on its stream over the timed steps.  path: "ti" (time-invariant data),
+    "tv" (time-varying data) or "nt" (node-temporal preconditioner), for the
+    kernel names and byte models; opts_kw / ctx_kw: extra solve options and
+    Context arguments; boundary: known boundary states for the solve."""
+    extra = dict(opts_kw or {})
     if precision == "fp32r":
         opts = lqgrid.default_opts(tol=tol, precision=lqgrid.FP32_REFINE,
-                                   inner_tol=inner_tol)
+                                   inner_tol=inner_tol, **extra)
     else:
-        opts = lqgrid.default_opts(tol=tol)
+        opts = lqgrid.default_opts(tol=tol, **extra)
     w = 4 if precision == "fp32r" else 8
     f64 = dict(dtype=torch.float64, device=x0.device)
     delta = torch.empty((p.T + 1, p.N, p.K, p.n), **f64)
@@ -203,11 +137,13 @@ def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
     us = torch.empty((p.T, p.N, p.K, p.m), **f64)
 
     def step(profile):
-        ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=False)
+        ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=False,
+                             **(ctx_kw or {}))
         if profile:
             ctx.profile_enable(True, stride=PROFILE_STRIDE)
         ctx.factor()
-        _, _, _, info = ctx.solve(x0, opts, out=delta, out_x=xs, out_u=us)
+        _, _, _, info = ctx.solve(x0, opts, out=delta, out_x=xs, out_u=us,
+                                  boundary=boundary)
         prof = {k: ctx.profile_read(k) for k in range(4)} if profile else None
         ctx.close()
         return info, prof
@@ -233,14 +169,19 @@ def measure(p, tol, arrays, x0, ws, precision, inner_tol, steps, warmup, torch,
         ms = sum(r[1][k][1] for r in runs)
         kern[nm] = {"timed_launches": launches, "timed_ms": round(ms, 3),
                     "avg_ms": ms / launches if launches else None}
-    kb = kernel_bytes(p, w)
+    kb = kernel_bytes(p, w, path=path)
+    if path == "nt":  # the Delta apply of the time-invariant path
+        kb["delta"] = kernel_bytes(p, w)["delta"]
     per_kernel = {}
     for nm in ("delta", "phi_solve"):
         if kern[nm]["avg_ms"]:
+            names = KERNEL_NAMES.get(("ti" if nm == "delta" and path == "nt" else path,
+                                      nm, w), [])
             per_kernel[nm] = {
+                "kernels": names,
                 "achieved": round(kb[nm] / (kern[nm]["avg_ms"] * 1e-3) / 1e9, 1),
                 "avg_launch_ms": kern[nm]["avg_ms"], "algorithmic_bytes": kb[nm],
-                "traffic": traffic_from_profiles(nm, w)}
+                "traffic": traffic_from_record(TRAFFIC, names)}
     dom = max(per_kernel, key=lambda k: kern[k]["timed_ms"])
     iters = sum(i["iterations"] for i in infos) / len(infos)
     return {
@@ -386,13 +327,119 @@ def bench_learned(args, torch, lqgrid):
     return result
 
 
+# Problem classes beyond the headline's, on the headline's dimensions
+# (K = N = 128, T = 200, n = 4, m = 2, tol 1e-8): each runs both forms like
+# the headline (the device FP64 KKT residual decides convergence; the oracle's
+# parity on these classes is covered by the GPU tests at smaller sizes).
+ROWS = {
+    "tv": {"desc": "time-varying data (A_t, A_nbr_t, B_t, Q_t, R_t per step)",
+           "path": "tv", "make": {"time_varying": True}},
+    "nodetemporal": {"desc": "node-temporal block Jacobi preconditioner",
+                     "path": "nt", "make": {}},
+    "boundary": {"desc": "known boundary states, per-node sizes n_ij in 1..4, "
+                         "m_ij in 1..2", "path": "ti",
+                 "make": {"boundary": True, "sizes": True}},
+}
+
+
+def row_problem(name, seed):
+    from lqgrid_synth import CONFIGS, make_problem
+    c = dict(CONFIGS["headline"])
+    tol = c.pop("tol")
+    return make_problem(seed=seed, **c, **ROWS[name]["make"]), tol
+
+
+def bench_nbjm(args, torch, lqgrid):
+    """Algorithm 2 run as a solver (S = 1 outer sweep per step, L = 2 inner,
+    outer sweeps to the tolerance; FP64) on the headline problem, beside
+    Algorithm 1 with the same sweeps as preconditioner, and the Lanczos
+    estimates of kappa(Delta) and kappa(P^-1 Delta) from one CG and one PCG
+    run.  A step is one standalone NBJM solve (setup + factor + sweeps)."""
+    from lqgrid_synth import config_problem
+    p, tol = config_problem("headline", args.seed)
+    arrays, x0 = make_inputs(p, torch, "cuda")
+    ws = torch.empty(lqgrid.workspace_bytes(p.K, p.N, p.T, p.n, p.m) + 256,
+                     dtype=torch.uint8, device="cuda")
+    opts = lqgrid.default_opts(tol=tol, check_every=32)
+    torch.cuda.synchronize()
+
+    def step(profile):
+        ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=False)
+        if profile:
+            ctx.profile_enable(True, stride=PROFILE_STRIDE)
+        ctx.factor()
+        _, _, _, info = ctx.nbjm_solve(x0, opts)
+        prof = {k: ctx.profile_read(k) for k in range(4)} if profile else None
+        ctx.close()
+        return info, prof
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    infos = [r[0] for r in runs]
+    sweeps = sum(i["iterations"] for i in infos) / len(infos)
+    log(f"[nbjm] {sweeps:.0f} sweeps, res {infos[-1]['rel_kkt_residual']:.2e}, "
+        f"{elapsed / args.steps:.3f} s per solve")
+    kern = {}
+    for k, nm in {1: "phi_solve", 2: "rhs"}.items():
+        launches = sum(r[1][k][0] for r in runs)
+        ms = sum(r[1][k][1] for r in runs)
+        kern[nm] = {"timed_launches": launches, "timed_ms": round(ms, 3),
+                    "avg_ms": ms / launches if launches else None}
+    kb = kernel_bytes(p, 8)["phi_solve"]
+    names = KERNEL_NAMES[("ti", "phi_solve", 8)]
+    avg = kern["phi_solve"]["avg_ms"]
+    achieved = kb / (avg * 1e-3) / 1e9
+    # Algorithm 1 with the same sweeps, and the conditioning estimates
+    ctx = lqgrid.Context(p, workspace=ws, arrays=arrays, factor=True)
+    t1 = time.perf_counter()
+    _, _, _, pinfo = ctx.solve(x0, lqgrid.default_opts(tol=tol))
+    t_pcg = time.perf_counter() - t1
+    kap = {}
+    for key, mode in (("cg", 0), ("pcg", 1)):
+        kap[key] = ctx.condition_estimate(x0, preconditioned=mode, tol=tol)
+    ctx.close()
+    return {
+        "metric": "standalone NBJM solves/s to 1e-8 rel. KKT residual, K=N=128 T=200 "
+                  "(vs Algorithm 1 with the same preconditioner); HBM %",
+        "value": args.steps / elapsed, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"nbjm: K={p.K} N={p.N} T={p.T} n={p.n} m={p.m}, FP64 "
+                               f"Algorithm 2 to convergence (L=2, inner start from the "
+                               f"outer iterate), tol={tol}",
+                   "check_every": 32},
+        "converged": all(i["status"] == lqgrid.OK and i["rel_kkt_residual"] <= tol
+                         for i in infos),
+        "sweeps": sweeps, "rel_kkt_residual": max(i["rel_kkt_residual"] for i in infos),
+        "kernels": kern,
+        "pcg": {"iterations": pinfo["iterations"], "seconds": t_pcg,
+                "solves_per_s": 1.0 / t_pcg, "rel_kkt_residual": pinfo["rel_kkt_residual"]},
+        "speedup_pcg_vs_nbjm": (elapsed / args.steps) / t_pcg,
+        "condition": {k: {kk: v[kk] for kk in ("kappa", "lambda_min", "lambda_max",
+                                               "iterations")} for k, v in kap.items()},
+        "roofline": {"bound": "hbm", "kernel": "phi_solve", "kernels": names,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_record(TRAFFIC, names),
+                     "algorithmic_bytes": kb, "avg_launch_ms": avg},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "plain", "tiny", "learned", "batched"])
+                    choices=["headline", "plain", "tiny", "learned", "batched", "nbjm"]
+                    + list(ROWS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="fp32r", choices=["fp64", "fp32r"],
                     help="form reported as value (fp32r: FP32 sweeps inside FP64 "
@@ -424,25 +471,43 @@ def main():
     if args.workload == "learned":
         print(json.dumps(bench_learned(args, torch, lqgrid)), flush=True)
         return
-    p, tol = config_problem(args.workload, args.seed)
+    if args.workload == "nbjm":
+        print(json.dumps(bench_nbjm(args, torch, lqgrid)), flush=True)
+        return
+    row = ROWS.get(args.workload)
+    if row is None:
+        p, tol = config_problem(args.workload, args.seed)
+    else:
+        p, tol = row_problem(args.workload, args.seed)
+    path = row["path"] if row else "ti"
     dev = "cuda"
     arrays, x0 = make_inputs(p, torch, dev)
-    nbytes = lqgrid.workspace_bytes(p.K, p.N, p.T, p.n, p.m)
+    nbytes = lqgrid.workspace_bytes(p.K, p.N, p.T, p.n, p.m,
+                                    time_varying=path == "tv", node_temporal=path == "nt")
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    mkw = {}
+    if path == "nt":
+        mkw = dict(opts_kw={"preconditioner": lqgrid.PRECOND_NODE_TEMPORAL},
+                   ctx_kw={"node_temporal": True})
+    if row is not None and p.has_boundary:
+        mkw["boundary"] = {k: torch.as_tensor(getattr(p, k)).to(
+            dtype=torch.float64, device=dev).contiguous()
+            for k in ("alpha_lo", "alpha_hi", "beta_lo", "beta_hi")}
     torch.cuda.synchronize()
     log(f"workload {args.workload}: K={p.K} N={p.N} T={p.T} n={p.n} m={p.m} "
-        f"U={p.unknowns} tol={tol}")
+        f"U={p.unknowns} tol={tol} workspace {nbytes / 2**30:.1f} GiB")
 
     plain = None
     if not args.no_plain and args.precision != "fp64":
         plain = measure(p, tol, arrays, x0, ws, "fp64", args.inner_tol,
-                        args.steps, args.warmup, torch, lqgrid)
+                        args.steps, args.warmup, torch, lqgrid, path=path, **mkw)
     chosen = measure(p, tol, arrays, x0, ws, args.precision, args.inner_tol,
-                     args.steps, args.warmup, torch, lqgrid)
+                     args.steps, args.warmup, torch, lqgrid, path=path, **mkw)
 
     dom = chosen["dominant"]
     hot = chosen["hot"][dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": hot["achieved"],
+    roofline = {"bound": "hbm", "kernel": dom, "kernels": hot["kernels"],
+                "achieved": hot["achieved"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hot["achieved"] / HBM_PEAK_GBS, 4),
                 "traffic": hot["traffic"], "algorithmic_bytes": hot["algorithmic_bytes"],
@@ -459,8 +524,12 @@ def main():
 
     form = ("FP32 stencil apply and sweeps, FP64 scalars, factors and outer "
             "refinement" if args.precision == "fp32r" else "plain FP64 PCG")
+    metric = METRIC if row is None else (
+        f"solves/s to {tol:g} rel. KKT residual, K={p.K} N={p.N} T={p.T}, "
+        f"{row['desc']} (plain vs chosen); HBM %")
+    wname = args.workload if row is None else f"{args.workload} ({row['desc']})"
     result = {
-        "metric": METRIC,
+        "metric": metric,
         "value": chosen["value"],
         "unit": "solves/s",
         "n_gpus": 1,
@@ -472,7 +541,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: K={p.K} N={p.N} T={p.T} n={p.n} "
+        "config": {"workload": f"{wname}: K={p.K} N={p.N} T={p.T} n={p.n} "
                                f"m={p.m}, {form}, S=L=2, tol={tol}",
                    "K": p.K, "N": p.N, "T": p.T, "n": p.n, "m": p.m,
                    "S": 2, "L": 2, "tol": tol, "precision": args.precision,
@@ -496,7 +565,7 @@ def main():
         "speedup_vs_plain": None if plain is None else chosen["value"] / plain["value"],
         "cpu_baseline": None,
     }
-    if not args.no_oracle_check:
+    if not args.no_oracle_check and row is None:
         # the oracle's FP64 KKT residual of the last timed step's delta~, x~, u~
         # (all three blocks of the KKT system), for each form
         from oracle import slab, residual
@@ -513,7 +582,7 @@ def main():
             target["converged"] = bool(target["converged"] and g["rel2"] <= tol)
             log(f"  {name}: oracle relative KKT residual {g['rel2']:.3e}")
         del ops
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and row is None:
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(p, tol, int(round(
             plain["pcg_iterations"] if plain else chosen["pcg_iterations"])))

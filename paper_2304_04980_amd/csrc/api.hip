@@ -1060,10 +1060,17 @@ int lqgrid_nbjm_solve(lqgrid_ctx* c, const double* x0, const lqgrid_solve_opts* 
   for (;;) {
     // delta^(s+1): rho = r_delta + Xi~ delta^(s); the inner iteration starts
     // from theta^(0) = delta^(s), theta^(l+1) = Phi~^-1 (rho + Omega~ theta^(l))
-    op_xi<double>(c, rd, dcur, rho, 0);
+    {
+      ProfScope ps(c, 2);
+      op_xi<double>(c, rd, dcur, rho, 0);
+    }
     const double* th = dcur;
     for (int l = 0; l < o.inner_L; ++l) {
-      op_omega<double>(c, rho, th, tau, 0);
+      {
+        ProfScope ps(c, 2);
+        op_omega<double>(c, rho, th, tau, 0);
+      }
+      ProfScope ps(c, 1);
       op_phi<double>(c, tau, dnext, 0);
       th = dnext;
     }
