@@ -727,58 +727,95 @@ __device__ __forceinline__ void delta_w_rows(const Dims& D, const OpCoef<T>& C,
   Qd.load(C.QTd, nodes * nn, (long long)p * nn, lane);
   const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), rw = vec_rsrc(D, w);
   const int nc = time_chunks(D);
-  struct Prod {
-    T self[NS], v[NS];
-  };
-  auto prod = [&](int c, Prod& P) {
-    const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
-#pragma unroll
-    for (int a = 0; a < NS; ++a) P.v[a] = T(0);
-    // every neighbour's loads first (out-of-grid neighbours read as zero
-    // through an out-of-range offset), then the products
+  // One chunk's reads: d at the node (nb[0]) and at its four neighbours
+  // (out-of-grid neighbours read as zero through an out-of-range offset).
+  struct Ld {
     T nb[5][NS];
-    load_nb<NS>(rd, off, p, ldt, P.self);
+  };
+  auto issue = [&](int c, Ld& L) {
+    const unsigned off = (unsigned)min(c * kWave + lane, D.Tt - 1) * sizeof(T);
+    load_nb<NS>(rd, off, p, ldt, L.nb[0]);
     sfor<1, 5>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
       const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
-      load_nb<NS>(rd, in ? off : kOob, in ? jq * K + iq : 0, ldt, nb[k]);
-    });
-#pragma unroll
-    for (int a = 0; a < NS; ++a) nb[0][a] = P.self[a];
-    sfor<0, 5>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      Cu.template mv<k * nn, false>(nb[k], P.v);
+      load_nb<NS>(rd, in ? off : kOob, in ? jq * K + iq : 0, ldt, L.nb[k]);
     });
   };
-  Prod cur, nxt;
-  prod(0, cur);
-  for (int c = 0; c < nc; ++c) {
-    if (c + 1 < nc) {
-      prod(c + 1, nxt);
-    } else {
+  struct Prod {
+    T self[NS], v[NS];
+  };
+  auto cup = [&](const Ld& L, Prod& P) {  // V_t = sum_k Cup_k d_t(q_k)
 #pragma unroll
-      for (int a = 0; a < NS; ++a) nxt.self[a] = nxt.v[a] = T(0);
+    for (int a = 0; a < NS; ++a) {
+      P.v[a] = T(0);
+      P.self[a] = L.nb[0][a];
     }
+    sfor<0, 5>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      Cu.template mv<k * nn, false>(L.nb[k], P.v);
+    });
+  };
+  // w_t = -Q^-1 d_t (- Q_T^-1 d_T at t = T) + V_{t+1}; V_{t+1} of lane 63
+  // comes from the next chunk's products (lane move)
+  auto finish = [&](int c, const Prod& cur, const Prod& nxt) {
     const TileTime tt = tile_time<T>(D, c);
-    T acc[NS], sq[NS], a2[NS];
+    T acc[NS], a2[NS];
 #pragma unroll
     for (int a = 0; a < NS; ++a) {
       acc[a] = T(0);
-      sq[a] = cur.self[a];
       a2[a] = from_next_lane(cur.v[a], nxt.v[a]);
     }
     Qi.template mv<0, true>(cur.self, acc);
-    zero_unless<NS>(tt.t == T_, sq);
-    Qd.template mv<0, true>(sq, acc);      // -Q_T^-1 d_T at t = T
+    if (c == nc - 1) {  // wave-uniform: the chunk holding t = T
+      T sq[NS];
+#pragma unroll
+      for (int a = 0; a < NS; ++a) sq[a] = cur.self[a];
+      zero_unless<NS>(tt.t == T_, sq);
+      Qd.template mv<0, true>(sq, acc);
+    }
     zero_unless<NS>(tt.t < T_, a2);
 #pragma unroll
     for (int a = 0; a < NS; ++a) acc[a] += a2[a];
     store_nb<NS>(rw, tt.valid ? tt.off : kOob, p, ldt, acc);
+  };
+  Prod zero;
 #pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      cur.self[a] = nxt.self[a];
-      cur.v[a] = nxt.v[a];
+  for (int a = 0; a < NS; ++a) zero.self[a] = zero.v[a] = T(0);
+  if constexpr (sizeof(T) == 4) {
+    // software pipeline over chunks: the reads of chunk c + 2 are issued
+    // before the products of chunk c + 1 (whose reads were issued one chunk
+    // earlier) and the output of chunk c; two read buffers alternate
+    Ld LA, LB;
+    Prod P0, P1;
+    issue(0, LA);
+    if (nc > 1) issue(1, LB);
+    cup(LA, P0);
+    // on entry Pc holds chunk c's products and X chunk c + 1's reads; Y is free
+    auto step = [&](int c, Ld& X, Ld& Y, Prod& Pc, Prod& Pn) {
+      if (c + 2 < nc) issue(c + 2, Y);
+      if (c + 1 < nc) cup(X, Pn);
+      finish(c, Pc, c + 1 < nc ? Pn : zero);
+    };
+    for (int c = 0; c < nc; c += 2) {
+      step(c, LB, LA, P0, P1);
+      if (c + 1 >= nc) break;
+      step(c + 1, LA, LB, P1, P0);
+    }
+  } else {
+    Ld L;
+    Prod cur, nxt;
+    issue(0, L);
+    cup(L, cur);
+    for (int c = 0; c < nc; ++c) {
+      if (c + 1 < nc) {
+        issue(c + 1, L);
+        cup(L, nxt);
+      } else {
+        nxt = zero;
+      }
+      finish(c, cur, nxt);
+      cur = nxt;
     }
   }
 }
@@ -805,46 +842,70 @@ __device__ __forceinline__ void delta_y_rows(const Dims& D, const OpCoef<T>& C,
     const __amdgpu_buffer_rsrc_t rd = vec_rsrc(D, d), rw = vec_rsrc(D, w),
                                  ry = vec_rsrc(D, y);
     const int nc = time_chunks(D);
+    // One chunk's reads: d at the node, w at the node (nb[0]) and at its four
+    // neighbours (out-of-grid neighbours read as zero).
+    struct Ld {
+      T self[NS], nb[5][NS];
+    };
+    auto issue = [&](int c, Ld& L) {
+      const TileTime tt = tile_time<T>(D, c);
+      load_nb<NS>(rd, tt.off, p, ldt, L.self);
+      load_nb<NS>(rw, tt.off, p, ldt, L.nb[0]);
+      sfor<1, 5>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
+        load_nb<NS>(rw, in ? tt.off : kOob, in ? jq * K + iq : 0, ldt, L.nb[k]);
+      });
+    };
     T xp[NS];  // the previous chunk's sum_5 A5 w
 #pragma unroll
     for (int a = 0; a < NS; ++a) xp[a] = T(0);
-    for (int c = 0; c < nc; ++c) {
+    // y_t = (sum_5 A5 w)_{t-1} + B R^-1 B' d_t - w_t  (t >= 1), y_0 = -w_0
+    auto body = [&](int c, const Ld& L) {
       const TileTime tt = tile_time<T>(D, c);
-      T self[NS], ws[NS], x[NS], acc[NS];
-      load_nb<NS>(rd, tt.off, p, ldt, self);
-      load_nb<NS>(rw, tt.off, p, ldt, ws);
+      T x[NS], acc[NS], a1[NS];
 #pragma unroll
       for (int a = 0; a < NS; ++a) {
         x[a] = T(0);
         acc[a] = T(0);
       }
-      T nb[5][NS];
-      sfor<1, 5>([&](auto kc) {  // every neighbour's loads first
-        constexpr int k = decltype(kc)::value;
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        const bool in = iq >= 0 && iq < K && jq >= 0 && jq < N;
-        load_nb<NS>(rw, in ? tt.off : kOob, in ? jq * K + iq : 0, ldt, nb[k]);
-      });
-#pragma unroll
-      for (int a = 0; a < NS; ++a) nb[0][a] = ws[a];
       sfor<0, 5>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        A5.template mv<k * nn, false>(nb[k], x);
+        A5.template mv<k * nn, false>(L.nb[k], x);
       });
-      Bb.template mv<0, false>(self, acc);
-      T a1[NS];
+      Bb.template mv<0, false>(L.self, acc);
 #pragma unroll
       for (int a = 0; a < NS; ++a) a1[a] = from_prev_lane(x[a], xp[a]) + acc[a];
       zero_unless<NS>(tt.t >= 1, a1);
 #pragma unroll
       for (int a = 0; a < NS; ++a) {
-        acc[a] = a1[a] - ws[a];
+        acc[a] = a1[a] - L.nb[0][a];
         xp[a] = x[a];
       }
       store_nb<NS>(ry, tt.valid ? tt.off : kOob, p, ldt, acc);
       if (tt.valid) {
 #pragma unroll
-        for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)self[a], dot);
+        for (int a = 0; a < NS; ++a) dot = fma((double)acc[a], (double)L.self[a], dot);
+      }
+    };
+    if constexpr (sizeof(T) == 4) {
+      // the reads of chunk c + 1 are issued before the products of chunk c;
+      // two read buffers alternate
+      Ld LA, LB;
+      issue(0, LA);
+      for (int c = 0; c < nc; c += 2) {
+        if (c + 1 < nc) issue(c + 1, LB);
+        body(c, LA);
+        if (c + 1 >= nc) break;
+        if (c + 2 < nc) issue(c + 2, LA);
+        body(c + 1, LB);
+      }
+    } else {
+      Ld L;
+      for (int c = 0; c < nc; ++c) {
+        issue(c, L);
+        body(c, L);
       }
     }
   }
