@@ -376,7 +376,7 @@ T* precondition(lqgrid_ctx* c, const T* r, int S, int L, int check) {
   if (c->pmode == LQGRID_PRECOND_NODE_TEMPORAL) {  // one node-temporal Jacobi sweep
     T* q = pcg_bufs<T>(c).v[kBufC];
     ProfScope ps(c, 1);
-    nt_solve<T>(D, nt_tab<T>(c), r, q, c->sc, check, c->stream);
+    nt_solve<T>(D, nt_tab<T>(c), r, pcg_bufs<T>(c).v[kBufD], q, c->sc, check, c->stream);
     return q;
   }
   const OpCoef<T>& C = op_coef<T>(c);
@@ -989,7 +989,7 @@ int lqgrid_apply_operator(lqgrid_ctx* c, int op, int S, int L,
         op_phi<T>(c, x, y, 0);
         break;
       case LQGRID_OP_NODE_PRECOND:
-        nt_solve<T>(D, nt_tab<T>(c), x, y, c->sc, 0, s);
+        nt_solve<T>(D, nt_tab<T>(c), x, b.v[kBufD], y, c->sc, 0, s);
         break;
       default:
         c->pmode = LQGRID_PRECOND_NBJM;

@@ -40,8 +40,8 @@ KERNEL_NAMES = {
     ("tv", "delta", 4): ["k_tv_stencil<float, 4, 0>"],
     ("tv", "phi_solve", 8): ["k_tv_phi_solve<double, 4>"],
     ("tv", "phi_solve", 4): ["k_tv_phi_solve<float, 4>"],
-    ("nt", "phi_solve", 8): ["k_nt_solve<double, 4>"],
-    ("nt", "phi_solve", 4): ["k_nt_solve<float, 4>"],
+    ("nt", "phi_solve", 8): ["k_nt_solve<double, 4, 8>"],
+    ("nt", "phi_solve", 4): ["k_nt_solve<float, 4, 16>"],
 }
 
 
