@@ -1359,15 +1359,27 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
       buf_sts(rout, in_lds ? kOob : ro[j], roff(k), val);
     }
   };
-  auto get_w = [&](int k, int j) {
-    if constexpr (kKeep == 0) {
-      return buf_lds<T>(rout, ro[j], roff(k));
-    } else {
-      const bool in_lds = k >= kl;
-      const T a = wl[in_lds ? k - kl : kKeep][R0 + j][lane];
-      const T b = buf_lds<T>(rout, in_lds ? kOob : ro[j], roff(k));
-      return in_lds ? a : b;
+  // The backward sweep's ring of parked w: slot s holds the HBM read (whead)
+  // and, with LDS parking, the LDS read (wlds) of its position; the two are
+  // selected where the value is used, not where it is fetched, so the select
+  // does not wait for the HBM read at once.
+  constexpr int kWL = kKeep > 0 ? kP : 1;
+  T whead[kP][NR], wlds[kWL][NR];
+  auto fetch_w = [&](int s, int k) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      if constexpr (kKeep == 0) {
+        whead[s][j] = buf_lds<T>(rout, ro[j], roff(k));
+      } else {
+        const bool in_lds = k >= kl;
+        wlds[s][j] = wl[in_lds ? k - kl : kKeep][R0 + j][lane];
+        whead[s][j] = buf_lds<T>(rout, in_lds ? kOob : ro[j], roff(k));
+      }
     }
+  };
+  auto wval = [&](int s, int k, int j) {  // parked w of position k, row R0+j, from slot s
+    if constexpr (kKeep == 0) return whead[s][j];
+    else return k >= kl ? wlds[s][j] : whead[s][j];
   };
 
   // ---------------------------------------------------------- forward
@@ -1397,13 +1409,16 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
   }
   lds_barrier();
   // Standard position i >= 1 (sp, s, sn: ring slots of rows i-1, i, i+1).
-  auto fstep_body = [&](int i, int sp, int s, int sn) {
+  // park: i >= 2 (w_{i-2} exists), a compile-time flag so that the steps of
+  // the unrolled loop have no branch (a branch would make the compiler's
+  // wait counts on the prefetched loads conservative).
+  auto fstep_body = [&](int i, int sp, int s, int sn, auto park) {
     read_all(zn, zo[(i - 1 + fso) & 1]);  // z_{i-1}
     T pre[NR], an[NR];
     sfor<0, NR>([&](auto jc) {  // independent of z_{i-1}
       constexpr int j = decltype(jc)::value;
       pre[j] = a[j] - dot8(cring[s][j], I8{}, z2, T(0));
-      if (i >= 2) put_w(i - 2, j, w_of(jc, cring[sp][j], z2));
+      if constexpr (decltype(park)::value) put_w(i - 2, j, w_of(jc, cring[sp][j], z2));
       an[j] = linv_tau(jc, cring[sn][j], tring[sn]);
     });
     sfor<0, NR>([&](auto jc) {  // z_i = Linv_i tau_i - M2_i z_{i-2} - M1_i z_{i-1}
@@ -1419,14 +1434,19 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     for (int c = 0; c < NT; ++c) tring[sn][c] = buf_lds<T>(rtau, rb[c], roff(it));
     lds_barrier();
   };
-  int i = 1;
+  using Park = std::true_type;
+  // position 1 (len - 1 >= 3 with the twisted order, K >= 8), then positions
+  // 2 .. len - 2 in groups of kP (slots of position i: (i - 1) mod kP ...)
+  fstep_body(1, 0, 1 % kP, 2 % kP, std::false_type{});
+  int i = 2;
   for (; i + kP <= len - 1; i += kP) {
 #pragma unroll
-    for (int u = 0; u < kP; ++u) fstep_body(i + u, u % kP, (1 + u) % kP, (2 + u) % kP);
+    for (int u = 0; u < kP; ++u)
+      fstep_body(i + u, (1 + u) % kP, (2 + u) % kP, (3 + u) % kP, Park{});
   }
 #pragma unroll
   for (int u = 0; u < kP - 1; ++u)
-    if (i + u < len - 1) fstep_body(i + u, u % kP, (1 + u) % kP, (2 + u) % kP);
+    if (i + u < len - 1) fstep_body(i + u, (1 + u) % kP, (2 + u) % kP, (3 + u) % kP, Park{});
 
   // the backward sweep's first coefficient rows, fetched a few steps early
   const int bs = top ? len - 1 : len - 2, cnt = bs + 1;
@@ -1488,11 +1508,8 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
   // with theta_{p+1} from the exchange and theta_{p+2} in registers (t2).
   T t2[NB], tn[NB];
   const int bso = top ? sm + 3 : sm + 4;  // step of backward step 0
-  T wring[kP][NR];
 #pragma unroll
-  for (int u = 0; u < kP; ++u)
-#pragma unroll
-    for (int j = 0; j < NR; ++j) wring[u][j] = get_w(max(bs - u, 0), j);
+  for (int u = 0; u < kP; ++u) fetch_w(u, max(bs - u, 0));
   // theta_p = q - N1_p theta_{p+1} for the rows of this wavefront; refill
   auto bfinish = [&](int kk, int p, int s, const T* q) {
     sfor<0, NR>([&](auto jc) {
@@ -1502,15 +1519,14 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
       buf_sts(rout, ro[j], roff(p), th);
     });
     load_b(bring[s], bw + (size_t)max(p - kP, 0) * bstep);
-#pragma unroll
-    for (int j = 0; j < NR; ++j) wring[s][j] = get_w(max(p - kP, 0), j);
+    fetch_w(s, max(p - kP, 0));
     lds_barrier();
   };
   if (top) {  // step sm + 3: theta_m = w_m - N1_m theta_{m+1}
     read_all(tn, zx[(sm + 2) & 1]);
     T q[NR];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) q[j] = wring[0][j];
+    for (int j = 0; j < NR; ++j) q[j] = wval(0, bs, j);
     bfinish(0, bs, 0, q);
 #pragma unroll
     for (int b = 0; b < NB; ++b) t2[b] = tn[b];
@@ -1522,14 +1538,13 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     T q[NR];
     sfor<0, NR>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      q[j] = wring[0][j] - dot8x2(bring[0][j], I0{}, t2);
+      q[j] = wval(0, bs, j) - dot8x2(bring[0][j], I0{}, t2);
       const T th = q[j] - dot8x2(bring[0][j], I8{}, tn);
       zo[bso & 1][R0 + j][lane] = th;
       buf_sts(rout, ro[j], roff(bs), th);
     });
     load_b(bring[0], bw + (size_t)max(bs - kP, 0) * bstep);
-#pragma unroll
-    for (int j = 0; j < NR; ++j) wring[0][j] = get_w(max(bs - kP, 0), j);
+    fetch_w(0, max(bs - kP, 0));
     lds_barrier();
   }
   auto bstep_body = [&](int kk, int s) {
@@ -1537,12 +1552,17 @@ __device__ __forceinline__ void sweep_twisted(const Dims& D, const OpCoef<T>& C,
     T q[NR];
     sfor<0, NR>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      q[j] = wring[s][j] - dot8(bring[s][j], I8{}, t2, T(0));
+      q[j] = wval(s, bs - kk, j) - dot8(bring[s][j], I8{}, t2, T(0));
     });
     bfinish(kk, bs - kk, s, q);
 #pragma unroll
     for (int b = 0; b < NB; ++b) t2[b] = tn[b];
   };
+  // One explicit drain of the vector-memory counter before the loop: the two
+  // middle-row paths above join here, and without it the compiler's wait at
+  // the loop head (valid for both paths and for every iteration) is far more
+  // conservative than the ring's prefetch distance.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt untouched
   int kk = 1;
   for (; kk + kP <= cnt; kk += kP) {
 #pragma unroll
