@@ -46,8 +46,9 @@ struct Plan {
   size_t psum, pmax, scal, scal_outer, hist;
   size_t inA, inAnbr, inB, inQ, inQT, inR, nsz;  // ingested (size-masked) arrays
   // time-varying data (tv.hip layouts), FP64 and FP32 copies
-  size_t tG13, tQi, tCdn, tCup, tAT5, tRiBT, tFw, tBw, tW;
-  size_t tG13f, tQif, tCdnf, tCupf, tFwf, tBwf, tWf;
+  size_t tG13, tQi, tCdn, tCup, tAT5, tRiBT, tA5, tBRB, tFw, tBw, tW;
+  size_t tG13f, tQif, tCdnf, tCupf, tA5f, tBRBf, tFwf, tBwf, tWf;
+  size_t tsG13, tsQi, tsCdn, tsCup, tsAT5, tsRiBT, tsA5, tsBRB;  // kTvBatch assembly slices
   bool tv;
   size_t nt64, nt32, total_nt;  // node-temporal tables, past `total` (opt-in)
   int npartial;
@@ -120,6 +121,8 @@ Plan make_plan(const Dims& D, bool tv) {
     P.tCup = take(L * 5 * nn * 8);
     P.tAT5 = take(L * 5 * nn * 8);
     P.tRiBT = take(L * D.m * D.n * 8);
+    P.tA5 = take(L * 5 * nn * 8);
+    P.tBRB = take(L * nn * 8);
     P.tFw = take(fwt * 8);
     P.tBw = take(bwt * 8);
     P.tW = take((size_t)D.vlen * 8);
@@ -127,9 +130,20 @@ Plan make_plan(const Dims& D, bool tv) {
     P.tQif = take(L * nn * 4);
     P.tCdnf = take(L * 5 * nn * 4);
     P.tCupf = take(L * 5 * nn * 4);
+    P.tA5f = take(L * 5 * nn * 4);
+    P.tBRBf = take(L * nn * 4);
     P.tFwf = take(fwt * 4);
     P.tBwf = take(bwt * 4);
     P.tWf = take((size_t)D.vlen * 4);
+    const size_t B = kTvBatch, nd = D.nodes;
+    P.tsG13 = take(B * nd * 13 * nn * 8);
+    P.tsQi = take(B * nd * nn * 8);
+    P.tsCdn = take(B * nd * 5 * nn * 8);
+    P.tsCup = take(B * nd * 5 * nn * 8);
+    P.tsAT5 = take(B * nd * 5 * nn * 8);
+    P.tsRiBT = take(B * nd * D.m * D.n * 8);
+    P.tsA5 = take(B * nd * 5 * nn * 8);
+    P.tsBRB = take(B * nd * nn * 8);
     P.npartial = std::max<int>(P.npartial, (int)(((long long)D.real_nodes * D.ldt + 255) / 256));
   }
   P.psum = take((size_t)P.npartial * 8);
@@ -671,23 +685,48 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
     // (Cdn, Cup, AT5, R^-1 B', Q^-1) and t = s + 1 (the 13-point G); the
     // terminal weight Q_T gives Q^-1 at t = T
     c->tv64 = TvCoef<double>{dp(P.tG13), dp(P.tQi), dp(P.tCdn), dp(P.tCup), dp(P.tFw),
-                             dp(P.tBw), dp(P.tAT5), dp(P.tRiBT), dp(P.tW)};
+                             dp(P.tBw), dp(P.tAT5), dp(P.tRiBT), dp(P.tW),
+                             dp(P.tA5), dp(P.tBRB), dp(P.W64)};
     c->tv32 = TvCoef<float>{fp(P.tG13f), fp(P.tQif), fp(P.tCdnf), fp(P.tCupf), fp(P.tFwf),
-                            fp(P.tBwf), nullptr, nullptr, fp(P.tWf)};
+                            fp(P.tBwf), nullptr, nullptr, fp(P.tWf),
+                            fp(P.tA5f), fp(P.tBRBf), fp(P.W32)};
     vec_zero<double>(dp(P.tG13), (long long)(P.tFw - P.tG13) / 8, c->stream);
     vec_zero<double>(dp(P.tW), D.vlen, c->stream);
     vec_zero<float>(fp(P.tWf), D.vlen, c->stream);
     const size_t rn = (size_t)D.real_nodes, nn = (size_t)D.n * D.n;
     const size_t sA = rn * nn, sN = rn * 4 * nn, sB = rn * D.n * D.m, sR = rn * D.m * D.m;
-    for (int s = 0; s <= D.T; ++s) {
-      const int sl = s < D.T ? s : D.T - 1;  // data slice (the terminal step: Q_T)
-      const double* Qs = desc->Q + sl * sA;
-      if (s == D.T && desc->QT) Qs = desc->QT;
-      ProblemIn us{D.K, D.N, D.n, D.m, desc->A + sl * sA, desc->A_nbr + sl * sN,
-                   desc->B + sl * sB, Qs, desc->R + sl * sR, Qs};
-      launch_ingest(D, us, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
-      launch_setup(D, in, c->C, c->sc, c->stream);
-      tv_scatter(D, c->C, c->tv64, s, s == D.T ? 1 : 0, c->stream);
+    const size_t nd = D.nodes;
+    for (int s0 = 0; s0 <= D.T; s0 += kTvBatch) {
+      const int nsl = std::min(kTvBatch, D.T + 1 - s0);
+      for (int b = 0; b < nsl; ++b) {
+        const int s = s0 + b;
+        const int sl = s < D.T ? s : D.T - 1;  // data slice (the terminal step: Q_T)
+        const double* Qs = desc->Q + sl * sA;
+        if (s == D.T && desc->QT) Qs = desc->QT;
+        ProblemIn us{D.K, D.N, D.n, D.m, desc->A + sl * sA, desc->A_nbr + sl * sN,
+                     desc->B + sl * sB, Qs, desc->R + sl * sR, Qs};
+        launch_ingest(D, us, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
+        Coef Cs = c->C;  // slice b of the assembly scratch
+        Cs.G13 = dp(P.tsG13) + b * nd * 13 * nn;
+        Cs.Qi = dp(P.tsQi) + b * nd * nn;
+        Cs.Cdn = dp(P.tsCdn) + b * nd * 5 * nn;
+        Cs.Cup = dp(P.tsCup) + b * nd * 5 * nn;
+        Cs.AT5 = dp(P.tsAT5) + b * nd * 5 * nn;
+        Cs.RiBT = dp(P.tsRiBT) + b * nd * D.m * D.n;
+        Cs.A5 = dp(P.tsA5) + b * nd * 5 * nn;
+        Cs.BRB = dp(P.tsBRB) + b * nd * nn;
+        launch_setup(D, in, Cs, c->sc, c->stream);
+      }
+      Coef S0 = c->C;
+      S0.G13 = dp(P.tsG13);
+      S0.Qi = dp(P.tsQi);
+      S0.Cdn = dp(P.tsCdn);
+      S0.Cup = dp(P.tsCup);
+      S0.AT5 = dp(P.tsAT5);
+      S0.RiBT = dp(P.tsRiBT);
+      S0.A5 = dp(P.tsA5);
+      S0.BRB = dp(P.tsBRB);
+      tv_scatter_batch(D, S0, c->tv64, s0, nsl, c->stream);
     }
   }
   const hipError_t e = hipGetLastError();
@@ -784,6 +823,8 @@ int lqgrid_factor(lqgrid_ctx* c) {
     copy_to_float(dp(P.tQi), fp(P.tQif), L * nn, c->stream);
     copy_to_float(dp(P.tCdn), fp(P.tCdnf), L * 5 * nn, c->stream);
     copy_to_float(dp(P.tCup), fp(P.tCupf), L * 5 * nn, c->stream);
+    copy_to_float(dp(P.tA5), fp(P.tA5f), L * 5 * nn, c->stream);
+    copy_to_float(dp(P.tBRB), fp(P.tBRBf), L * nn, c->stream);
     copy_to_float(dp(P.tFw), fp(P.tFwf), fwt, c->stream);
     copy_to_float(dp(P.tBw), fp(P.tBwf), bwt, c->stream);
   } else {

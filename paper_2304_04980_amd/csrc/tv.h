@@ -11,8 +11,13 @@ struct TvCoef {
   const T *G13, *Qi, *Cdn, *Cup, *Fw, *Bw;
   const T *AT5, *RiBT;  // FP64 only (recovery)
   T* w;                 // forward-sweep result of the block solve
+  const T *A5 = nullptr, *BRB = nullptr;  // factored Delta apply (TA5, TBRB)
+  T* dw = nullptr;      // the factored Delta apply's intermediate w
 };
 
+// y = Delta d (and one FP64 partial of d'y per workgroup into partial);
+// returns the number of partials.  With C.A5, C.BRB and C.dw: the factored
+// two-pass form, else the 13-point form.
 template <typename T>
 int tv_delta_apply(const Dims& D, const TvCoef<T>& C, const T* d, T* y, double* partial,
                    const Scalars* sc, int check, hipStream_t s);
@@ -27,10 +32,14 @@ void tv_phi_solve(const Dims& D, const TvCoef<T>& C, const T* tau, T* out,
                   const Scalars* sc, int check, hipStream_t s);
 void tv_recover(const Dims& D, const TvCoef<double>& C, const double* dl, double* x,
                 double* u, hipStream_t s);
-// Blocks of one time slice s assembled in the time-invariant layouts of S
-// into the time-varying arrays of C (qi_only: the terminal Q_T^-1 only).
-void tv_scatter(const Dims& D, const Coef& S, const TvCoef<double>& C, int s_, int qi_only,
-                hipStream_t s);
+// Time slices assembled per batch before their scatter into the time-fastest
+// arrays (the assembly scratch holds this many slices).
+constexpr int kTvBatch = 16;
+// Blocks of the nsl time slices s0 .. s0 + nsl - 1 assembled in the
+// time-invariant layouts of S (each array of S holding kTvBatch slices back to
+// back) into the time-varying arrays of C; slice T contributes Q_T^-1 only.
+void tv_scatter_batch(const Dims& D, const Coef& S, const TvCoef<double>& C, int s0, int nsl,
+                      hipStream_t s);
 // One-chain factorisation of every Phi_bar_{v,t}, t = 0..T (C.tv_ld = ldt).
 void tv_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s);
 

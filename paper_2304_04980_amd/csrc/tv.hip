@@ -17,12 +17,17 @@
 //   TCup [p][5][n*n][ldt]   Q_{t,p}^-1 A_hat_t[q,p]'      (t < T)
 //   TAT5 [p][5][n*n][ldt]   A_hat_t[q,p]'                 (recovery)
 //   TRiBT[p][m*n][ldt]      R_t^-1 B_t'                   (recovery)
+//   TA5  [p][5][n*n][ldt]   A_hat_t[p,q]                  (t < T; factored Delta)
+//   TBRB [p][n*n][ldt]      B_{t-1} R_{t-1}^-1 B_{t-1}'   (t >= 1; factored Delta)
 //   TFw  [v][row][32][ldt][8], TBw [v][row][16][ldt][8]: the one-chain
 //        factor products of every Phi_bar_{v,t} (see bodies_setup.h fw_at),
 //        row r of the eight rows of a block row (2n <= 8) fastest.
 //
 // The operator kernels run one thread per (node, t); they are bound by the
-// coefficient reads (about 23 n^2 per node and step for Delta).  The block
+// coefficient reads.  Delta is applied in the factored form of Sec. II-B,
+// Delta = A~ Q~^-1 A~' + B~ R~^-1 B~', in two passes (12 n^2 coefficients
+// per node and step instead of the 24 n^2 of the 13-point form, which is
+// kept for the operator tests and as a fallback).  The block
 // solve runs eight threads per (v, t) system, one per row of a 2n-row block
 // row, exchanging the block row's values by cross-lane reads.
 #include "bodies_setup.h"
@@ -92,6 +97,98 @@ __global__ __launch_bounds__(256) void k_tv_stencil(Dims D, TvCoef<T> C,
     }
   }
   if (MODE == 0 && partial) {
+    const double s = block_sum<256>(dot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// First pass of the factored Delta apply, w = -Q~^-1 A~' d:
+//   w_t = -Q_t^-1 d_t + sum_k Q_{t,p}^-1 A_hat_t[q_k,p]' d_{t+1}(q_k)  (t < T),
+//   w_T = -Q_T^-1 d_T,
+// over the 5-point neighbours q_k of node p inside the grid.
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_tv_delta_w(Dims D, TvCoef<T> C,
+                                                    const T* __restrict__ d,
+                                                    T* __restrict__ w, const Scalars* sc,
+                                                    int check) {
+  if (check && __builtin_nontemporal_load(&sc->done) != 0) return;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ldt = D.ldt, K = D.K;
+  const int t = (int)(g % ldt), p = (int)(g / ldt);
+  constexpr int nn = NS * NS;
+  if (p >= D.real_nodes || t >= D.Tt) return;
+  const int j = p / K, i = p - j * K;
+  T acc[NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) acc[a] = T(0);
+  auto term = [&](const T* blk, int q, int tq, T sign) {
+    T xv[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) xv[b] = d[((size_t)q * NS + b) * ldt + tq];
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+      for (int b = 0; b < NS; ++b)
+        acc[a] = fma(sign * blk[(size_t)(a * NS + b) * ldt], xv[b], acc[a]);
+  };
+  term(C.Qi + (size_t)p * nn * ldt + t, p, t, T(-1));
+  if (t < D.T) {
+    for (int k = 0; k < 5; ++k) {
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= D.N) continue;
+      term(C.Cup + ((size_t)p * 5 + k) * nn * ldt + t, jq * K + iq, t + 1, T(1));
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NS; ++a) w[((size_t)p * NS + a) * ldt + t] = acc[a];
+}
+
+// Second pass, y = Delta d = -A~ w + B~ R~^-1 B~' d:
+//   y_t = sum_k A_hat_{t-1}[p,q_k] w_{t-1}(q_k) + B_{t-1} R_{t-1}^-1 B_{t-1}' d_t
+//         - w_t  (t >= 1),   y_0 = -w_0,
+// and one FP64 partial of d'y per workgroup.
+template <typename T, int NS>
+__global__ __launch_bounds__(256) void k_tv_delta_y(Dims D, TvCoef<T> C,
+                                                    const T* __restrict__ d,
+                                                    const T* __restrict__ w,
+                                                    T* __restrict__ y,
+                                                    double* __restrict__ partial,
+                                                    const Scalars* sc, int check) {
+  if (check && __builtin_nontemporal_load(&sc->done) != 0) return;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ldt = D.ldt, K = D.K;
+  const int t = (int)(g % ldt), p = (int)(g / ldt);
+  constexpr int nn = NS * NS;
+  double dot = 0.0;
+  if (p < D.real_nodes && t < D.Tt) {
+    const int j = p / K, i = p - j * K;
+    T acc[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[a] = -w[((size_t)p * NS + a) * ldt + t];
+    auto term = [&](const T* blk, const T* x, int q, int tq) {
+      T xv[NS];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) xv[b] = x[((size_t)q * NS + b) * ldt + tq];
+#pragma unroll
+      for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int b = 0; b < NS; ++b) acc[a] = fma(blk[(size_t)(a * NS + b) * ldt], xv[b], acc[a]);
+    };
+    if (t >= 1) {
+      for (int k = 0; k < 5; ++k) {
+        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+        if (iq < 0 || iq >= K || jq < 0 || jq >= D.N) continue;
+        term(C.A5 + ((size_t)p * 5 + k) * nn * ldt + (t - 1), w, jq * K + iq, t - 1);
+      }
+      term(C.BRB + (size_t)p * nn * ldt + t, d, p, t);
+    }
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      y[((size_t)p * NS + a) * ldt + t] = acc[a];
+      dot += (double)acc[a] * (double)d[((size_t)p * NS + a) * ldt + t];
+    }
+  }
+  if (partial) {
     const double s = block_sum<256>(dot);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
@@ -227,41 +324,28 @@ __global__ __launch_bounds__(256) void k_tv_recover(Dims D, TvCoef<double> C,
   }
 }
 
-// Scatter of the blocks that the time-invariant assembly wrote for one time
-// slice s (data at time s) into the time-varying layouts: G13 -> TG13 at
-// t = s + 1, Qi -> TQi at s, Cdn, Cup, AT5, RiBT -> at s.  qi_only: the
-// terminal slice (Q_T), only TQi at s.  One thread per coefficient of a node.
-__global__ void k_tv_scatter(Dims D, Coef S, TvCoef<double> C, double* TAT5, double* TRiBT,
-                             int s, int qi_only) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nn = D.n * D.n, mn = D.m * D.n;
-  const int per = 29 * nn + mn;  // 13 + 1 + 5 + 5 + 5 blocks, R^-1 B'
-  if (g >= (long long)D.nodes * per) return;
-  const int p = (int)(g / per), e = (int)(g % per);
-  const size_t ldt = D.ldt;
-  double* TG13 = const_cast<double*>(C.G13);
-  double* TQi = const_cast<double*>(C.Qi);
-  double* TCdn = const_cast<double*>(C.Cdn);
-  double* TCup = const_cast<double*>(C.Cup);
-  if (e < 13 * nn) {
-    if (!qi_only) TG13[((size_t)p * 13 * nn + e) * ldt + s + 1] = S.G13[(size_t)p * 13 * nn + e];
-  } else if (e < 14 * nn) {
-    const int f = e - 13 * nn;
-    TQi[((size_t)p * nn + f) * ldt + s] = S.Qi[(size_t)p * nn + f];
-  } else if (qi_only) {
-    return;
-  } else if (e < 19 * nn) {
-    const int f = e - 14 * nn;
-    TCdn[((size_t)p * 5 * nn + f) * ldt + s] = S.Cdn[(size_t)p * 5 * nn + f];
-  } else if (e < 24 * nn) {
-    const int f = e - 19 * nn;
-    TCup[((size_t)p * 5 * nn + f) * ldt + s] = S.Cup[(size_t)p * 5 * nn + f];
-  } else if (e < 29 * nn) {
-    const int f = e - 24 * nn;
-    TAT5[((size_t)p * 5 * nn + f) * ldt + s] = S.AT5[(size_t)p * 5 * nn + f];
-  } else {
-    const int f = e - 29 * nn;
-    TRiBT[((size_t)p * mn + f) * ldt + s] = S.RiBT[(size_t)p * mn + f];
+// Scatter of one block array that the time-invariant assembly wrote for
+// nsl consecutive time slices s0 .. s0 + nsl - 1 (slice b at src + b * stride,
+// row r = (node, coefficient) at [r]) into its time-fastest array dst[r][t]
+// at t = s + toff.  A workgroup transposes 64 rows x kTvBatch slices through
+// LDS, so that both the reads (64 consecutive rows of one slice) and the
+// writes (kTvBatch consecutive times of one row) are contiguous.
+__global__ __launch_bounds__(256) void k_tv_scatter(const double* __restrict__ src,
+                                                    long long stride, long long rows,
+                                                    double* __restrict__ dst, int ldt, int s0,
+                                                    int nsl, int toff) {
+  __shared__ double tile[64][kTvBatch + 1];
+  const long long r0 = (long long)blockIdx.x * 64;
+  for (int k = threadIdx.x; k < 64 * kTvBatch; k += 256) {
+    const int b = k / 64, rl = k % 64;  // row fastest: coalesced reads
+    const long long r = r0 + rl;
+    if (b < nsl && r < rows) tile[rl][b] = src[(long long)b * stride + r];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 64 * kTvBatch; k += 256) {
+    const int rl = k / kTvBatch, b = k % kTvBatch;  // time fastest: contiguous writes
+    const long long r = r0 + rl;
+    if (b < nsl && r < rows) dst[r * ldt + s0 + b + toff] = tile[rl][b];
   }
 }
 
@@ -288,6 +372,16 @@ template <typename T>
 int tv_delta_apply(const Dims& D, const TvCoef<T>& C, const T* d, T* y, double* partial,
                    const Scalars* sc, int check, hipStream_t s) {
   const int nb = tv_blocks(D);
+  if (C.A5 && C.BRB && C.dw) {
+#define CALL(NS)                                                                            \
+  hipLaunchKernelGGL((k_tv_delta_w<T, NS>), dim3(nb), dim3(256), 0, s, D, C, d, C.dw, sc,     \
+                     check);                                                                \
+  hipLaunchKernelGGL((k_tv_delta_y<T, NS>), dim3(nb), dim3(256), 0, s, D, C, d,             \
+                     (const T*)C.dw, y, partial, sc, check)
+    LQG_TV_DISPATCH(D.n, CALL)
+#undef CALL
+    return nb;
+  }
 #define CALL(NS)                                                                      \
   hipLaunchKernelGGL((k_tv_stencil<T, NS, 0>), dim3(nb), dim3(256), 0, s, D, C, d,    \
                      (const T*)nullptr, y, partial, sc, check)
@@ -335,12 +429,24 @@ void tv_recover(const Dims& D, const TvCoef<double>& C, const double* dl, double
 #undef CALL
 }
 
-void tv_scatter(const Dims& D, const Coef& S, const TvCoef<double>& C, int s_, int qi_only,
-                hipStream_t s) {
-  const long long work = (long long)D.nodes * (29 * D.n * D.n + D.m * D.n);
-  hipLaunchKernelGGL(k_tv_scatter, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, D,
-                     S, C, const_cast<double*>(C.AT5), const_cast<double*>(C.RiBT), s_,
-                     qi_only);
+void tv_scatter_batch(const Dims& D, const Coef& S, const TvCoef<double>& C, int s0, int nsl,
+                      hipStream_t s) {
+  const long long nodes = D.nodes, nn = (long long)D.n * D.n, mn = (long long)D.m * D.n;
+  const int nfull = s0 + nsl - 1 == D.T ? nsl - 1 : nsl;  // slice T: Q_T^-1 only
+  auto one = [&](const double* src, long long per, double* dst, int n, int toff) {
+    if (n <= 0 || !src || !dst) return;
+    const long long rows = nodes * per;
+    hipLaunchKernelGGL(k_tv_scatter, dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s, src,
+                       rows, rows, dst, D.ldt, s0, n, toff);
+  };
+  one(S.G13, 13 * nn, const_cast<double*>(C.G13), nfull, 1);
+  one(S.Qi, nn, const_cast<double*>(C.Qi), nsl, 0);
+  one(S.Cdn, 5 * nn, const_cast<double*>(C.Cdn), nfull, 0);
+  one(S.Cup, 5 * nn, const_cast<double*>(C.Cup), nfull, 0);
+  one(S.AT5, 5 * nn, const_cast<double*>(C.AT5), nfull, 0);
+  one(S.RiBT, mn, const_cast<double*>(C.RiBT), nfull, 0);
+  one(S.A5, 5 * nn, const_cast<double*>(C.A5), nfull, 0);
+  one(S.BRB, nn, const_cast<double*>(C.BRB), nfull, 1);
 }
 
 void tv_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s) {

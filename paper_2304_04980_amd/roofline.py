@@ -36,8 +36,8 @@ KERNEL_NAMES = {
     ("ti", "delta", 4): ["k_delta_w<float, 4>", "k_delta_y<float, 4>"],
     ("ti", "phi_solve", 8): ["k_phi_solve_twisted<double, 4>"],
     ("ti", "phi_solve", 4): ["k_phi_solve_twisted<float, 4>"],
-    ("tv", "delta", 8): ["k_tv_stencil<double, 4, 0>"],
-    ("tv", "delta", 4): ["k_tv_stencil<float, 4, 0>"],
+    ("tv", "delta", 8): ["k_tv_delta_w<double, 4>", "k_tv_delta_y<double, 4>"],
+    ("tv", "delta", 4): ["k_tv_delta_w<float, 4>", "k_tv_delta_y<float, 4>"],
     ("tv", "phi_solve", 8): ["k_tv_phi_solve<double, 4>"],
     ("tv", "phi_solve", 4): ["k_tv_phi_solve<float, 4>"],
     ("nt", "phi_solve", 8): ["k_nt_solve<double, 4, 8>"],
@@ -58,8 +58,9 @@ def kernel_bytes(p, w=8, qt_distinct=False, path="ti"):
                     block row; K+1 forward rows in the one-chain order, K+2
                     plus one row of middle couplings in the twisted order,
                     K >= 8) + the t = 0 block Q^-1 per node.
-    tv, delta:      2 U w + 24 n^2 w per node and step (13-point, Q_t^-1 and
-                    the 5 + 5 time-coupling blocks, all per t).
+    tv, delta:      2 U w + 12 n^2 w per node and step (the factored form's
+                    blocks, all per t: 5 Cup_t and Q_t^-1 in the w pass,
+                    5 A-hat_{t-1} and B R^-1 B'_{t-1} in the y pass).
     tv, phi_solve:  2 U w + a one-chain factor per (super-column, t).
     nt, phi_solve:  2 U w + 3 n^2 w per node and step (L_t^-1, M_t, N_t).
 
@@ -78,7 +79,7 @@ def kernel_bytes(p, w=8, qt_distinct=False, path="ti"):
                 "phi_solve": 2 * U * w + factors + nodes * n * n * w}
     if path == "tv":
         factors = V * (T + 1) * 2 * n * (FW_ROW * (K + 1) + BW_ROW * K) * w
-        return {"delta": 2 * U * w + nodes * (T + 1) * 24 * n * n * w,
+        return {"delta": 2 * U * w + nodes * (T + 1) * 12 * n * n * w,
                 "phi_solve": 2 * U * w + factors}
     if path == "nt":
         return {"phi_solve": 2 * U * w + nodes * (T + 1) * 3 * n * n * w}
