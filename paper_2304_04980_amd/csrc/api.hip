@@ -49,6 +49,7 @@ struct Plan {
   size_t tG13, tQi, tCdn, tCup, tAT5, tRiBT, tA5, tBRB, tFw, tBw, tW;
   size_t tG13f, tQif, tCdnf, tCupf, tA5f, tBRBf, tFwf, tBwf, tWf;
   size_t tsG13, tsQi, tsCdn, tsCup, tsAT5, tsRiBT, tsA5, tsBRB;  // kTvBatch assembly slices
+  size_t tsInA, tsInN, tsInB, tsInQ, tsInR;  // kTvBatch ingested slices
   bool tv;
   size_t nt64, nt32, total_nt;  // node-temporal tables, past `total` (opt-in)
   int npartial;
@@ -144,6 +145,11 @@ Plan make_plan(const Dims& D, bool tv) {
     P.tsRiBT = take(B * nd * D.m * D.n * 8);
     P.tsA5 = take(B * nd * 5 * nn * 8);
     P.tsBRB = take(B * nd * nn * 8);
+    P.tsInA = take(B * rn * nn * 8);
+    P.tsInN = take(B * rn * 4 * nn * 8);
+    P.tsInB = take(B * rn * D.n * D.m * 8);
+    P.tsInQ = take(B * rn * nn * 8);
+    P.tsInR = take(B * rn * D.m * D.m * 8);
     P.npartial = std::max<int>(P.npartial, (int)(((long long)D.real_nodes * D.ldt + 255) / 256));
   }
   P.psum = take((size_t)P.npartial * 8);
@@ -696,36 +702,43 @@ int setup_into(lqgrid_ctx* c, const lqgrid_problem_desc* desc, const Dims& D,
     const size_t rn = (size_t)D.real_nodes, nn = (size_t)D.n * D.n;
     const size_t sA = rn * nn, sN = rn * 4 * nn, sB = rn * D.n * D.m, sR = rn * D.m * D.m;
     const size_t nd = D.nodes;
+    // every slice of a batch in one launch per setup kernel (slice b reads
+    // its problem data, writes its ingested copy and assembly scratch)
+    const ProblemIn user0{D.K, D.N, D.n, D.m, desc->A, desc->A_nbr, desc->B, desc->Q,
+                          desc->R, desc->Q};
+    const ProblemIn in0{D.K, D.N, D.n, D.m, dp(P.tsInA), dp(P.tsInN), dp(P.tsInB),
+                        dp(P.tsInQ), dp(P.tsInR), dp(P.tsInQ)};
+    Coef S0 = c->C;
+    S0.G13 = dp(P.tsG13);
+    S0.Qi = dp(P.tsQi);
+    S0.Cdn = dp(P.tsCdn);
+    S0.Cup = dp(P.tsCup);
+    S0.AT5 = dp(P.tsAT5);
+    S0.RiBT = dp(P.tsRiBT);
+    S0.A5 = dp(P.tsA5);
+    S0.BRB = dp(P.tsBRB);
     for (int s0 = 0; s0 <= D.T; s0 += kTvBatch) {
       const int nsl = std::min(kTvBatch, D.T + 1 - s0);
-      for (int b = 0; b < nsl; ++b) {
-        const int s = s0 + b;
-        const int sl = s < D.T ? s : D.T - 1;  // data slice (the terminal step: Q_T)
-        const double* Qs = desc->Q + sl * sA;
-        if (s == D.T && desc->QT) Qs = desc->QT;
-        ProblemIn us{D.K, D.N, D.n, D.m, desc->A + sl * sA, desc->A_nbr + sl * sN,
-                     desc->B + sl * sB, Qs, desc->R + sl * sR, Qs};
-        launch_ingest(D, us, desc->n_node, desc->m_node, in, nsz, c->sc, c->stream);
-        Coef Cs = c->C;  // slice b of the assembly scratch
-        Cs.G13 = dp(P.tsG13) + b * nd * 13 * nn;
-        Cs.Qi = dp(P.tsQi) + b * nd * nn;
-        Cs.Cdn = dp(P.tsCdn) + b * nd * 5 * nn;
-        Cs.Cup = dp(P.tsCup) + b * nd * 5 * nn;
-        Cs.AT5 = dp(P.tsAT5) + b * nd * 5 * nn;
-        Cs.RiBT = dp(P.tsRiBT) + b * nd * D.m * D.n;
-        Cs.A5 = dp(P.tsA5) + b * nd * 5 * nn;
-        Cs.BRB = dp(P.tsBRB) + b * nd * nn;
-        launch_setup(D, in, Cs, c->sc, c->stream);
-      }
-      Coef S0 = c->C;
-      S0.G13 = dp(P.tsG13);
-      S0.Qi = dp(P.tsQi);
-      S0.Cdn = dp(P.tsCdn);
-      S0.Cup = dp(P.tsCup);
-      S0.AT5 = dp(P.tsAT5);
-      S0.RiBT = dp(P.tsRiBT);
-      S0.A5 = dp(P.tsA5);
-      S0.BRB = dp(P.tsBRB);
+      TvSlices S{};
+      S.s0 = s0;
+      S.nsl = nsl;
+      S.T = D.T;
+      S.sA = (long long)sA;
+      S.sN = (long long)sN;
+      S.sB = (long long)sB;
+      S.sR = (long long)sR;
+      S.QT = desc->QT;
+      S.iA = (long long)(rn * nn);
+      S.iN = (long long)(rn * 4 * nn);
+      S.iB = (long long)(rn * D.n * D.m);
+      S.iR = (long long)(rn * D.m * D.m);
+      S.cG13 = (long long)(nd * 13 * nn);
+      S.cQi = (long long)(nd * nn);
+      S.c5 = (long long)(nd * 5 * nn);
+      S.cRiBT = (long long)(nd * D.m * D.n);
+      S.cBRB = (long long)(nd * nn);
+      launch_ingest_setup_tv(D, user0, S, desc->n_node, desc->m_node, in0, nsz, S0, c->sc,
+                             c->stream);
       tv_scatter_batch(D, S0, c->tv64, s0, nsl, c->stream);
     }
   }

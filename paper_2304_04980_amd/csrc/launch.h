@@ -10,9 +10,30 @@ struct ProblemIn {
   const double *A, *A_nbr, *B, *Q, *R, *QT;
 };
 
+// A batch of time slices s0 .. s0 + nsl - 1 of time-varying data, handled by
+// one launch per setup kernel (blockIdx.y = slice b of the batch).  Slice s
+// reads the problem arrays of slice min(s, T - 1) at the given strides (the
+// terminal slice T: Q = Q_T, or Q_{T-1} without one); slice b's ingested
+// copies and assembly scratch sit at b times their strides from the slice-0
+// pointers.
+struct TvSlices {
+  int s0, nsl, T;
+  long long sA, sN, sB, sR;      // problem arrays: A and Q, A_nbr, B, R per slice
+  const double* QT;              // terminal weight (may be null)
+  long long iA, iN, iB, iR;      // ingested copies: A and Q, A_nbr, B, R per slice
+  long long cG13, cQi, c5, cRiBT, cBRB;  // scratch: G13; Qi; Cdn, Cup, AT5, A5; RiBT; BRB
+};
+
 // setup.hip
 void launch_setup(const Dims& D, const ProblemIn& P, const Coef& C,
                   Scalars* sc, hipStream_t s);
+// Ingest and assembly of a batch of time slices (P: slice-0 problem arrays,
+// in / C: slice-0 ingested copies and assembly scratch; the shared blocks of C
+// that time-varying data does not use, Q_T^-1 and the like, are written by
+// every slice of the batch).
+void launch_ingest_setup_tv(const Dims& D, const ProblemIn& P, const TvSlices& S,
+                            const int* nsz, const int* msz, const ProblemIn& in,
+                            int* nsz_out, const Coef& C, Scalars* sc, hipStream_t s);
 void launch_factor(const Dims& D, const Coef& C, Scalars* sc, hipStream_t s);
 void launch_rhs_init(const Dims& D, const double* x0, double* rd,
                      hipStream_t s, const int* nsz = nullptr);
