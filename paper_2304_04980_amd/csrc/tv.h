@@ -16,8 +16,8 @@ struct TvCoef {
 };
 
 // y = Delta d (and one FP64 partial of d'y per workgroup into partial);
-// returns the number of partials.  With C.A5, C.BRB and C.dw: the factored
-// two-pass form, else the 13-point form.
+// returns the number of partials.  The factored two-pass form: needs C.A5,
+// C.BRB and the intermediate vector C.dw.
 template <typename T>
 int tv_delta_apply(const Dims& D, const TvCoef<T>& C, const T* d, T* y, double* partial,
                    const Scalars* sc, int check, hipStream_t s);

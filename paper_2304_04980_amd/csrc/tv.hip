@@ -26,8 +26,8 @@
 // The operator kernels run one thread per (node, t); they are bound by the
 // coefficient reads.  Delta is applied in the factored form of Sec. II-B,
 // Delta = A~ Q~^-1 A~' + B~ R~^-1 B~', in two passes (12 n^2 coefficients
-// per node and step instead of the 24 n^2 of the 13-point form, which is
-// kept for the operator tests and as a fallback).  The block
+// per node and step instead of the 24 n^2 of the 13-point form); the
+// 13-point blocks serve the Omega~ right-hand side and the factorisation.  The block
 // solve runs eight threads per (v, t) system, one per row of a 2n-row block
 // row, exchanging the block row's values by cross-lane reads.
 #include "bodies_setup.h"
@@ -39,67 +39,55 @@ using namespace dev;
 
 __device__ __forceinline__ bool cross_pair(int j, int jq) { return (j >> 1) != (jq >> 1); }
 
-// y = Delta x (MODE 0), rho = r + Xi~ x (MODE 1), tau = r + Omega~ x (MODE 2);
-// r nullable.  MODE 0 also writes one FP64 partial of x'y per workgroup.
+// rho = r + Xi~ x (MODE 1) or tau = r + Omega~ x (MODE 2); r nullable.
+//   Xi~ = Psi~ - Delta: the time couplings of Delta with the sign flipped,
+//   Omega~ = Phi~ - Psi~: the 13-point blocks between different super-columns
+//   with the sign flipped.
 template <typename T, int NS, int MODE>
 __global__ __launch_bounds__(256) void k_tv_stencil(Dims D, TvCoef<T> C,
                                                     const T* __restrict__ x,
                                                     const T* __restrict__ r,
-                                                    T* __restrict__ y,
-                                                    double* __restrict__ partial,
-                                                    const Scalars* sc, int check) {
+                                                    T* __restrict__ y, const Scalars* sc,
+                                                    int check) {
+  static_assert(MODE == 1 || MODE == 2, "right-hand sides only");
   if (check && __builtin_nontemporal_load(&sc->done) != 0) return;
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int ldt = D.ldt, K = D.K;
   const int t = (int)(g % ldt), p = (int)(g / ldt);
   constexpr int nn = NS * NS;
-  double dot = 0.0;
-  if (p < D.real_nodes && t < D.Tt) {
-    const int j = p / K, i = p - j * K;
-    T acc[NS];
+  if (p >= D.real_nodes || t >= D.Tt) return;
+  const int j = p / K, i = p - j * K;
+  T acc[NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) acc[a] = r ? r[((size_t)p * NS + a) * ldt + t] : T(0);
+  auto term = [&](const T* blk, int q, int tq) {
+    T xv[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) xv[b] = x[((size_t)q * NS + b) * ldt + tq];
 #pragma unroll
     for (int a = 0; a < NS; ++a)
-      acc[a] = r ? r[((size_t)p * NS + a) * ldt + t] : T(0);
-    auto term = [&](const T* blk, int q, int tq, T sign) {
-      T xv[NS];
 #pragma unroll
-      for (int b = 0; b < NS; ++b) xv[b] = x[((size_t)q * NS + b) * ldt + tq];
-#pragma unroll
-      for (int a = 0; a < NS; ++a)
-#pragma unroll
-        for (int b = 0; b < NS; ++b)
-          acc[a] = fma(sign * blk[(size_t)(a * NS + b) * ldt], xv[b], acc[a]);
-    };
-    if (MODE == 0 || MODE == 2) {
-      for (int k = 0; k < 13; ++k) {
-        const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= D.N) continue;
-        if (MODE == 2 && !cross_pair(j, jq)) continue;
-        term(C.G13 + ((size_t)p * 13 + k) * nn * ldt + t, jq * K + iq, t,
-             MODE == 0 ? T(1) : T(-1));
-      }
-      if (MODE == 0) term(C.Qi + (size_t)p * nn * ldt + t, p, t, T(1));
+      for (int b = 0; b < NS; ++b)
+        acc[a] = fma(MODE == 2 ? -blk[(size_t)(a * NS + b) * ldt] : blk[(size_t)(a * NS + b) * ldt],
+                     xv[b], acc[a]);
+  };
+  if (MODE == 2) {
+    for (int k = 0; k < 13; ++k) {
+      const int iq = i + kOff13[k][0], jq = j + kOff13[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= D.N || !cross_pair(j, jq)) continue;
+      term(C.G13 + ((size_t)p * 13 + k) * nn * ldt + t, jq * K + iq, t);
     }
-    if (MODE == 0 || MODE == 1) {
-      const T sign = MODE == 0 ? T(-1) : T(1);
-      for (int k = 0; k < 5; ++k) {
-        const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
-        if (iq < 0 || iq >= K || jq < 0 || jq >= D.N) continue;
-        const int q = jq * K + iq;
-        if (t >= 1) term(C.Cdn + ((size_t)p * 5 + k) * nn * ldt + (t - 1), q, t - 1, sign);
-        if (t < D.T) term(C.Cup + ((size_t)p * 5 + k) * nn * ldt + t, q, t + 1, sign);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < NS; ++a) {
-      y[((size_t)p * NS + a) * ldt + t] = acc[a];
-      if (MODE == 0) dot += (double)acc[a] * (double)x[((size_t)p * NS + a) * ldt + t];
+  } else {
+    for (int k = 0; k < 5; ++k) {
+      const int iq = i + kOff5[k][0], jq = j + kOff5[k][1];
+      if (iq < 0 || iq >= K || jq < 0 || jq >= D.N) continue;
+      const int q = jq * K + iq;
+      if (t >= 1) term(C.Cdn + ((size_t)p * 5 + k) * nn * ldt + (t - 1), q, t - 1);
+      if (t < D.T) term(C.Cup + ((size_t)p * 5 + k) * nn * ldt + t, q, t + 1);
     }
   }
-  if (MODE == 0 && partial) {
-    const double s = block_sum<256>(dot);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  }
+#pragma unroll
+  for (int a = 0; a < NS; ++a) y[((size_t)p * NS + a) * ldt + t] = acc[a];
 }
 
 // First pass of the factored Delta apply, w = -Q~^-1 A~' d:
@@ -372,19 +360,11 @@ template <typename T>
 int tv_delta_apply(const Dims& D, const TvCoef<T>& C, const T* d, T* y, double* partial,
                    const Scalars* sc, int check, hipStream_t s) {
   const int nb = tv_blocks(D);
-  if (C.A5 && C.BRB && C.dw) {
 #define CALL(NS)                                                                            \
   hipLaunchKernelGGL((k_tv_delta_w<T, NS>), dim3(nb), dim3(256), 0, s, D, C, d, C.dw, sc,     \
                      check);                                                                \
   hipLaunchKernelGGL((k_tv_delta_y<T, NS>), dim3(nb), dim3(256), 0, s, D, C, d,             \
                      (const T*)C.dw, y, partial, sc, check)
-    LQG_TV_DISPATCH(D.n, CALL)
-#undef CALL
-    return nb;
-  }
-#define CALL(NS)                                                                      \
-  hipLaunchKernelGGL((k_tv_stencil<T, NS, 0>), dim3(nb), dim3(256), 0, s, D, C, d,    \
-                     (const T*)nullptr, y, partial, sc, check)
   LQG_TV_DISPATCH(D.n, CALL)
 #undef CALL
   return nb;
@@ -395,7 +375,7 @@ void tv_xi_rhs(const Dims& D, const TvCoef<T>& C, const T* r, const T* dl, T* rh
                const Scalars* sc, int check, hipStream_t s) {
 #define CALL(NS)                                                                        \
   hipLaunchKernelGGL((k_tv_stencil<T, NS, 1>), dim3(tv_blocks(D)), dim3(256), 0, s, D, C, \
-                     dl, r, rho, (double*)nullptr, sc, check)
+                     dl, r, rho, sc, check)
   LQG_TV_DISPATCH(D.n, CALL)
 #undef CALL
 }
@@ -405,7 +385,7 @@ void tv_omega_rhs(const Dims& D, const TvCoef<T>& C, const T* rho, const T* th, 
                   const Scalars* sc, int check, hipStream_t s) {
 #define CALL(NS)                                                                        \
   hipLaunchKernelGGL((k_tv_stencil<T, NS, 2>), dim3(tv_blocks(D)), dim3(256), 0, s, D, C, \
-                     th, rho, tau, (double*)nullptr, sc, check)
+                     th, rho, tau, sc, check)
   LQG_TV_DISPATCH(D.n, CALL)
 #undef CALL
 }
