@@ -12,8 +12,11 @@ value = steps / wall time of the chosen form's timed steps (solves/s); the
 plain figures are reported beside it.  After timing, the FP64 oracle evaluates
 the KKT residual of each form's last solution (delta~, x~, u~).  The default
 headline run also times the batched form (256 uneven problems) and the learned
-warm start (64 x 64 x 100) on their own workloads and adds their summaries to
-the same line.
+warm start (64 x 64 x 100) on their own workloads, and the other problem
+classes at the headline's dimensions (time-varying data, the node-temporal
+preconditioner, boundary states with per-node sizes) and the standalone NBJM,
+and adds their summaries to the same line (`batched`, `learned`, `rows`).
+`--workload` runs any of them alone as the line's value.
 
 Prints ONE JSON line.  Only one GPU is used; --gpus N > 1 exits with a message.
 """
@@ -432,48 +435,12 @@ def bench_nbjm(args, torch, lqgrid):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="headline",
-                    choices=["headline", "plain", "tiny", "learned", "batched", "nbjm"]
-                    + list(ROWS))
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", default="fp32r", choices=["fp64", "fp32r"],
-                    help="form reported as value (fp32r: FP32 sweeps inside FP64 "
-                         "iterative refinement); plain FP64 is always measured "
-                         "beside it unless --no-plain")
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--no-forms", action="store_true",
-                    help="headline only: skip the batched and learned summaries")
-    ap.add_argument("--form-steps", type=int, default=2,
-                    help="timed steps of the batched and learned summaries")
-    ap.add_argument("--copy-ref-mib", type=int, default=512,
-                    help="size of the plain copy used to scale PMC counters")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path; "
-              "run it with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
+def bench_single(args, torch, lqgrid):
+    """One problem of args.workload (headline, plain, tiny or a ROWS class):
+    plain FP64 and the chosen form measured on the same inputs; returns the
+    result dict of the JSON line (with the oracle check and the CPU baseline
+    for the non-row workloads unless switched off)."""
     from lqgrid_synth import config_problem
-    from paper_2304_04980_amd import lqgrid
-
-    if args.workload == "batched":
-        print(json.dumps(bench_batched(args, torch, lqgrid)), flush=True)
-        return
-    if args.workload == "learned":
-        print(json.dumps(bench_learned(args, torch, lqgrid)), flush=True)
-        return
-    if args.workload == "nbjm":
-        print(json.dumps(bench_nbjm(args, torch, lqgrid)), flush=True)
-        return
     row = ROWS.get(args.workload)
     if row is None:
         p, tol = config_problem(args.workload, args.seed)
@@ -586,11 +553,59 @@ def main():
         log("timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline(p, tol, int(round(
             plain["pcg_iterations"] if plain else chosen["pcg_iterations"])))
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "plain", "tiny", "learned", "batched", "nbjm"]
+                    + list(ROWS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precision", default="fp32r", choices=["fp64", "fp32r"],
+                    help="form reported as value (fp32r: FP32 sweeps inside FP64 "
+                         "iterative refinement); plain FP64 is always measured "
+                         "beside it unless --no-plain")
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="headline only: skip the batched and learned summaries")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="headline only: skip the summaries of the other problem "
+                         "classes (time-varying, node-temporal, boundary + sizes) "
+                         "and of the standalone NBJM")
+    ap.add_argument("--form-steps", type=int, default=2,
+                    help="timed steps of the batched, learned and row summaries")
+    ap.add_argument("--copy-ref-mib", type=int, default=512,
+                    help="size of the plain copy used to scale PMC counters")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_04980_amd import lqgrid
+
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args, torch, lqgrid)), flush=True)
+        return
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args, torch, lqgrid)), flush=True)
+        return
+    if args.workload == "nbjm":
+        print(json.dumps(bench_nbjm(args, torch, lqgrid)), flush=True)
+        return
+    result = bench_single(args, torch, lqgrid)
+    torch.cuda.empty_cache()
     if args.workload == "headline" and not args.no_forms:
         # the other two forms of the method on their own workloads, as
         # summaries in the same line
-        del chosen, plain, ws, arrays
-        torch.cuda.empty_cache()
         sub = argparse.Namespace(**vars(args))
         sub.steps, sub.warmup = args.form_steps, 1
         for key, fn in (("batched", bench_batched), ("learned", bench_learned)):
@@ -606,6 +621,28 @@ def main():
             except Exception as e:  # reported, never hides the headline line
                 result[key] = {"error": f"{type(e).__name__}: {e}"}
             torch.cuda.empty_cache()
+    if args.workload == "headline" and not args.no_rows:
+        # the other problem classes and the standalone NBJM at the headline's
+        # dimensions, as summaries in the same line
+        rows = {}
+        for name in list(ROWS) + ["nbjm"]:
+            sub = argparse.Namespace(**vars(args))
+            sub.workload, sub.steps, sub.warmup = name, args.form_steps, 1
+            sub.no_oracle_check = sub.no_cpu_baseline = True
+            try:
+                r = (bench_nbjm if name == "nbjm" else bench_single)(sub, torch, lqgrid)
+                rows[name] = {k: r.get(k) for k in (
+                    "metric", "value", "unit", "ms_per_step", "converged", "config",
+                    "pcg_iterations", "refinements", "sweeps", "rel_kkt_residual",
+                    "speedup_vs_plain", "pcg", "speedup_pcg_vs_nbjm", "condition",
+                    "roofline") if k in r}
+                if r.get("plain_fp64"):
+                    rows[name]["plain_fp64"] = {k: r["plain_fp64"].get(k) for k in (
+                        "value", "ms_per_step", "converged", "pcg_iterations")}
+            except Exception as e:  # reported, never hides the headline line
+                rows[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+        result["rows"] = rows
     print(json.dumps(result), flush=True)
 
 
