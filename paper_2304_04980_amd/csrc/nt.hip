@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_nt_solve(Dims D, const T* __restrict__ 
 
   // forward: z_t = Linv_t tau_t - M_t z_{t-1}
   auto ld_f = [&](int t, int slot) {
-    t = min(t, Tt - 1);
+    t = min(max(t, 0), Tt - 1);
     row_ld(t, 0, ca[slot]);  // Linv_t row rc
     row_ld(t, 1, cb[slot]);  // M_t row rc
   };
@@ -308,7 +308,9 @@ __global__ __launch_bounds__(256) void k_nt_solve(Dims D, const T* __restrict__ 
   // backward: theta_t = Linv_t' z_t - N_t theta_{t+1}; z_t is this lane's
   // own forward result, read back from zbuf
   auto ld_b = [&](int t, int slot) {
-    t = max(t, 0);
+    // clamped at both ends: on the steps past the last one of the last tile
+    // t - RING can still be >= Tt (up to TB - 1 such steps)
+    t = min(max(t, 0), Tt - 1);
     row_ld(t, 3, ca[slot]);  // Linv_t' row rc
     row_ld(t, 2, cb[slot]);  // N_t row rc
   };
