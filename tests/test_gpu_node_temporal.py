@@ -41,6 +41,16 @@ CASES = [
     (6, 1, 9, 2, 2, 1.0, "identity", False),  # N = 1
     (4, 3, 1, 1, 1, 1.0, "identity", False),  # T = 1, n = 1
     (5, 3, 30, 4, 2, 1.4, "spd", True),       # time-varying data
+    # horizons against the solve's 16-step (FP32) / 8-step (FP64) tiles and
+    # its 8- / 4-step coefficient ring: steps past the end of the last tile
+    # from none to more than the ring is deep (T + 1 = 101: 11 in FP32, where
+    # an index clamped at 0 only once read past the coefficient table)
+    (4, 4, 100, 4, 2, 1.0, "identity", False),
+    (3, 2, 3, 4, 2, 1.0, "identity", False),    # T + 1 = 4, shorter than the ring
+    (4, 4, 16, 4, 2, 1.0, "spd", False),        # T + 1 = 17
+    (4, 4, 63, 4, 2, 1.0, "identity", False),   # T + 1 = 64: no step past the end
+    (2, 4, 104, 2, 1, 1.0, "identity", False),  # T + 1 = 105: 7 past the end in FP64
+    (4, 2, 120, 4, 2, 2.0, "spd", False),       # T + 1 = 121
 ]
 
 
