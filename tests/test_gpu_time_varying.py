@@ -43,6 +43,11 @@ CASES = [
     (6, 1, 9, 2, 2, 1.0),       # N = 1
     (4, 3, 1, 1, 1, 1.0),       # T = 1, n = 1
     (16, 4, 33, 4, 3, 1.5),
+    # the setup assembles and scatters 16 time slices per batch: T + 1 = 16
+    # and 32 fill the batches exactly (T + 1 = 65 above leaves the terminal
+    # slice alone in the last batch)
+    (4, 4, 15, 2, 1, 1.0),
+    (3, 3, 31, 4, 2, 1.2),
 ]
 
 
