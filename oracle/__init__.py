@@ -19,7 +19,7 @@ Contents (each module cites the passage it follows):
   nbjm       -- Algorithm 2 (NBJM) with fixed S outer and L inner sweeps
   residual   -- primal recovery and the relative KKT residual
 
-Every reading of a garbled or ambiguous passage is listed in the design doc and
-repeated where it is used.  Parity status: every function here is pinned by a
+Every reading of a garbled or ambiguous passage is stated where it is used,
+in the docstring of the function that relies on it.  Parity status: every function here is pinned by a
 ``-m "not gpu"`` test in tests/test_oracle_*.py; none is "parity unpinned".
 """
